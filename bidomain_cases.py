@@ -1,0 +1,157 @@
+"""Seeded synthetic inputs for the Bidomain slab workloads.
+
+This module draws the *numbers* that define a case -- slab size, stimulus ellipsoids,
+serving arrival times -- and evaluates the initial transmembrane potential at the mesh
+nodes. It holds none of the solver's arithmetic (no assembly, no AMG, no Krylov step),
+so both the CPU oracle and the HIP library may take their inputs from here.
+
+The paper's own workloads (a truncated-ellipsoid ventricle and a patient mesh with the
+TP06 membrane model, Sec. 3) are not reproducible here; a 1 x 1 x 0.5 cm slab with the
+paper's kind of fiber rotation (Sec. 2, eq. (2)) and a plateau stimulus stands in.
+
+Node numbering: p = i + (nx+1) * (j + (ny+1) * k), x fastest.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import List, Tuple
+
+import numpy as np
+
+Ellipsoid = Tuple[float, float, float, float, float, float]  # cx, cy, cz, ax, ay, az (cm)
+
+
+@dataclass(frozen=True)
+class SlabCase:
+    """One Bidomain slab case. Units: cm, ms, mV, S/cm, mF/cm^3."""
+
+    nx: int
+    ny: int
+    nz: int
+    Lx: float = 1.0
+    Ly: float = 1.0
+    Lz: float = 0.5
+    # axisymmetric conductivities (sigma_n = sigma_t in eq. (2))
+    sig_il: float = 3.0e-3
+    sig_it: float = 3.1525e-4
+    sig_el: float = 2.0e-3
+    sig_et: float = 1.3514e-3
+    # in-plane fibers rotating linearly through the thickness: theta(z) = theta0 + rot * z / Lz
+    fiber_theta0: float = -math.pi / 3.0
+    fiber_rotation: float = 2.0 * math.pi / 3.0
+    cm: float = 1.0  # chi * C_m (1000 1/cm * 1 uF/cm^2)
+    dt: float = 0.05  # ms
+    v_rest: float = -85.0
+    v_plateau: float = 20.0
+    ellipsoids: Tuple[Ellipsoid, ...] = field(default_factory=tuple)
+    seed: int = 0
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+
+    @property
+    def h(self) -> Tuple[float, float, float]:
+        return self.Lx / self.nx, self.Ly / self.ny, self.Lz / self.nz
+
+    @property
+    def nnz27(self) -> int:
+        """Entries of the full 27-point Q1 pattern (structural zeros kept)."""
+        return (3 * self.nx + 1) * (3 * self.ny + 1) * (3 * self.nz + 1)
+
+    @property
+    def paper_dofs(self) -> int:
+        """The paper counts v and u_e at every node (weak-scaling tables)."""
+        return 2 * self.n
+
+
+def _draw_ellipsoids(rng: np.random.Generator, count: int, wide: bool) -> Tuple[Ellipsoid, ...]:
+    out = []
+    for _ in range(count):
+        if wide:
+            c = rng.uniform([0.1, 0.1, 0.1], [0.9, 0.9, 0.4])
+        else:
+            c = rng.uniform([0.3, 0.3, 0.15], [0.7, 0.7, 0.35])
+        a = rng.uniform([0.08, 0.08, 0.05], [0.2, 0.2, 0.12])
+        out.append(tuple(float(v) for v in (*c, *a)))
+    return tuple(out)
+
+
+def make_case(nx: int, ny: int, nz: int, seed: int, n_ellipsoids: int = 1, name: str = "", **kw) -> SlabCase:
+    rng = np.random.default_rng(seed)
+    ell = _draw_ellipsoids(rng, n_ellipsoids, wide=n_ellipsoids > 1)
+    return SlabCase(nx=nx, ny=ny, nz=nz, ellipsoids=ell, seed=seed, name=name or f"slab{nx}x{ny}x{nz}", **kw)
+
+
+# The five workloads (sizes in elements).
+CONFIGS = {
+    "C1": dict(nx=16, ny=16, nz=8, seed=1, n_ellipsoids=1),
+    "C2": dict(nx=128, ny=128, nz=64, seed=2, n_ellipsoids=1),
+    "C3": dict(nx=256, ny=256, nz=64, seed=3, n_ellipsoids=8),
+    "C5": dict(nx=384, ny=384, nz=96, seed=5, n_ellipsoids=8),
+}
+
+
+def config_case(name: str) -> SlabCase:
+    kw = dict(CONFIGS[name])
+    return make_case(name=name, **kw)
+
+
+def node_coordinates(case: SlabCase):
+    hx, hy, hz = case.h
+    x = np.arange(case.nx + 1) * hx
+    y = np.arange(case.ny + 1) * hy
+    z = np.arange(case.nz + 1) * hz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")  # k slowest, i fastest
+    return X.ravel(), Y.ravel(), Z.ravel()
+
+
+def nodal_v0(case: SlabCase) -> np.ndarray:
+    """Initial transmembrane potential: v_plateau inside the union of ellipsoids, v_rest outside."""
+    X, Y, Z = node_coordinates(case)
+    inside = np.zeros(X.shape, dtype=bool)
+    for cx, cy, cz, ax, ay, az in case.ellipsoids:
+        inside |= ((X - cx) / ax) ** 2 + ((Y - cy) / ay) ** 2 + ((Z - cz) / az) ** 2 <= 1.0
+    v = np.full(X.shape, case.v_rest, dtype=np.float64)
+    v[inside] = case.v_plateau
+    return v
+
+
+def nodal_w0(case: SlabCase) -> np.ndarray:
+    return np.zeros(case.n, dtype=np.float64)
+
+
+def random_vector(n: int, seed: int, dtype=np.float64) -> np.ndarray:
+    return np.random.default_rng(seed).uniform(-1.0, 1.0, size=n).astype(dtype)
+
+
+@dataclass
+class ServedRequest:
+    ticket: int
+    arrival_s: float
+    case: SlabCase
+    nsteps: int
+
+
+def serving_stream(n_cases: int = 64, nsteps: int = 20, rate_per_s: float = 20.0, seed: int = 4,
+                   min_dims=(32, 32, 16), max_dims=(160, 160, 64)) -> List[ServedRequest]:
+    """Poisson arrivals of slab cases with log-uniform element counts.
+
+    nx = ny = round(32 * 5**t), nz = round(16 * 4**t), t ~ U(0, 1); the first two cases
+    are pinned to t = 0 and t = 1 so that both size endpoints appear in every stream.
+    """
+    rng = np.random.default_rng(seed)
+    fx = max_dims[0] / min_dims[0]
+    fz = max_dims[2] / min_dims[2]
+    out = []
+    t_arr = 0.0
+    for c in range(n_cases):
+        t = 0.0 if c == 0 else (1.0 if c == 1 else float(rng.uniform()))
+        nxy = int(round(min_dims[0] * fx ** t))
+        nz = int(round(min_dims[2] * fz ** t))
+        case = make_case(nxy, nxy, nz, seed=int(rng.integers(1 << 31)), n_ellipsoids=1, name=f"serve{c}")
+        out.append(ServedRequest(ticket=c, arrival_s=t_arr, case=case, nsteps=nsteps))
+        t_arr += float(rng.exponential(1.0 / rate_per_s))
+    return out

@@ -1,0 +1,189 @@
+"""Pins for the oracle's smoothers, V-cycle and Krylov solvers (CPU only): the Chebyshev error
+polynomial in closed form, the pseudo-inverse coarse solve, a dense two-grid operator built
+from that closed form, V-cycle symmetry, PCG termination properties, exact dots against
+rational arithmetic, and AMG-PCG against dense direct solves."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+import bidomain_cases as bc
+from oracle import amg, fem, krylov
+
+
+def _cheb_error_factor(lam, lamhat, lo, hi):
+    """T_2((theta - lam) / delta) / T_2(theta / delta) with T_2(t) = 2 t^2 - 1."""
+    a, b = lo * lamhat, hi * lamhat
+    theta, delta = (a + b) / 2, (b - a) / 2
+    T2 = lambda t: 2 * t * t - 1
+    return T2((theta - lam) / delta) / T2(theta / delta)
+
+
+def test_chebyshev_error_polynomial_closed_form():
+    rng = np.random.default_rng(0)
+    Q = rng.standard_normal((10, 10))
+    A = Q @ Q.T + 3 * np.eye(10)
+    D = np.diag(np.diag(A))
+    lams, Y = sla.eigh(A, D)
+    lamhat = lams[-1] * 0.97
+    As = sp.csr_matrix(A)
+    Dinv = 1.0 / np.diag(A)
+    for lam, y in zip(lams, Y.T):
+        x = krylov.chebyshev(As, Dinv, A @ y, None, lamhat, 2, 0.05, 1.05)
+        err = y - x
+        np.testing.assert_allclose(err, _cheb_error_factor(lam, lamhat, 0.05, 1.05) * y, rtol=0,
+                                   atol=1e-11 * np.abs(y).max())
+
+
+def _small_hierarchy(nx, ny, nz, nullspace=True, **kw):
+    c = bc.make_case(nx, ny, nz, seed=3)
+    ops = fem.assemble_operators(c)
+    A = ops["Aell"] if nullspace else ops["Apar"]
+    opts = amg.AMGOptions(nullspace=nullspace, coarse_eq_limit=kw.pop("coarse_eq_limit", 4), **kw)
+    return c, ops, A, amg.setup(A, opts)
+
+
+def test_coarse_solve_is_pseudo_inverse_on_range():
+    c, ops, A, h = _small_hierarchy(3, 3, 2, max_levels=1, coarse_eq_limit=1000)
+    Ad = A.toarray()
+    f = np.random.default_rng(1).standard_normal(Ad.shape[0])
+    f -= f.mean()
+    np.testing.assert_allclose(krylov.coarse_solve(h, f), np.linalg.pinv(Ad) @ f, rtol=0,
+                               atol=1e-9 * np.abs(np.linalg.pinv(Ad) @ f).max())
+
+
+def _vcycle_matrix(h, n):
+    return np.column_stack([krylov.vcycle(h, e) for e in np.eye(n)])
+
+
+def test_two_grid_matches_dense_closed_form():
+    """Two levels, exact coarse solve: B = G + M - M A G with G = M + P A_c^+ R (I - A M) and
+    the smoother M = q(D^{-1} A) D^{-1}, 1 - t q(t) = T_2((theta - t)/delta) / T_2(sigma)."""
+    c, ops, A, h = _small_hierarchy(4, 4, 2, max_levels=2, coarse_eq_limit=4)
+    assert h.nlevels == 2
+    lv = h.levels[0]
+    Ad = A.toarray()
+    n = Ad.shape[0]
+    lo, hi = h.opts.cheb_lo, h.opts.cheb_hi
+    a, b = lo * lv.lam, hi * lv.lam
+    theta, delta = (a + b) / 2, (b - a) / 2
+    sigma = theta / delta
+    T2s = 2 * sigma ** 2 - 1
+    # p(t) = (2 ((theta - t)/delta)^2 - 1) / T2s = c0 + c1 t + c2 t^2 with c0 = 1; q(t) = -(c1 + c2 t)
+    c1 = -4 * theta / delta ** 2 / T2s
+    c2 = 2 / delta ** 2 / T2s
+    S = np.diag(lv.Dinv) @ Ad
+    M = -(c1 * np.eye(n) + c2 * S) @ np.diag(lv.Dinv)
+    Ac = h.levels[1].A.toarray()
+    P, R = lv.P.toarray(), lv.R.toarray()
+    G = M + P @ np.linalg.pinv(Ac) @ R @ (np.eye(n) - Ad @ M)
+    Bdense = G + M - M @ Ad @ G
+    B = _vcycle_matrix(h, n)
+    # compare on the range of A (the singular direction is projected by PCG anyway)
+    Pi = np.eye(n) - np.ones((n, n)) / n
+    np.testing.assert_allclose(B @ Pi, Bdense @ Pi, rtol=0, atol=1e-9 * np.abs(Bdense).max())
+
+
+def test_vcycle_symmetric_positive():
+    c, ops, A, h = _small_hierarchy(5, 5, 3, coarse_eq_limit=10)
+    assert h.nlevels >= 3
+    n = A.shape[0]
+    B = _vcycle_matrix(h, n)
+    assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
+    Pi = np.eye(n) - np.ones((n, n)) / n
+    ev = np.linalg.eigvalsh(Pi @ (0.5 * (B + B.T)) @ Pi)
+    assert np.sort(ev)[1] > 0  # one zero eigenvalue along the constant, the rest positive
+
+
+def test_pcg_exact_preconditioner_one_iteration():
+    c, ops, A, h = _small_hierarchy(3, 3, 2, max_levels=1, coarse_eq_limit=1000)
+    f = np.random.default_rng(2).standard_normal(A.shape[0])
+    Apinv = np.linalg.pinv(A.toarray())
+    res = krylov.pcg(A, f, lambda r: Apinv @ r, rtol=1e-10, nullspace=True)
+    assert res.iterations == 1 and res.converged
+
+
+def test_pcg_identity_terminates_within_n():
+    rng = np.random.default_rng(4)
+    n = 40
+    Q = rng.standard_normal((n, n))
+    A = sp.csr_matrix(Q @ Q.T / n + np.eye(n))
+    res = krylov.pcg(A, rng.standard_normal(n), lambda r: r, rtol=1e-10)
+    assert res.converged and res.iterations <= n
+
+
+def test_fcg_equals_cg_in_double():
+    c, ops, A, h = _small_hierarchy(6, 6, 3, coarse_eq_limit=20)
+    f = -(ops["Ai"] @ bc.random_vector(A.shape[0], 9))
+    r1 = krylov.pcg(A, f, lambda r: krylov.vcycle(h, r), rtol=1e-10, nullspace=True)
+    r2 = krylov.fcg(A, f, lambda r: krylov.vcycle(h, r), rtol=1e-10, nullspace=True, lowp=np.float64)
+    assert r1.iterations == r2.iterations
+    np.testing.assert_allclose(r1.x, r2.x, rtol=0, atol=1e-9 * np.abs(r1.x).max())
+
+
+def test_exact_dot_is_correctly_rounded():
+    rng = np.random.default_rng(5)
+    for n in (1, 7, 1000):
+        x = rng.standard_normal(n).astype(np.float32) * np.float32(1e3)
+        y = rng.standard_normal(n).astype(np.float32)
+        exact = sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(x, y))
+        assert krylov.exact_dot(x, y) == float(exact)
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 1), (3, 3, 2), (4, 4, 2)])
+def test_amg_pcg_matches_dense_pseudo_inverse_tiny(dims):
+    c, ops, A, h = _small_hierarchy(*dims, coarse_eq_limit=4)
+    f = -(ops["Ai"] @ bc.nodal_v0(bc.make_case(*dims, seed=3)))
+    f = f + 1e-3 * bc.random_vector(A.shape[0], 1)  # make the load non-trivial on tiny meshes
+    res = krylov.amg_pcg(A, f, h, rtol=1e-12, m=ops["m"])
+    fh = f - f.mean()
+    x = np.linalg.pinv(A.toarray()) @ fh
+    x -= (ops["m"] @ x) / ops["m"].sum()
+    assert np.linalg.norm(res.x - x) <= 1e-10 * np.linalg.norm(x)
+
+
+@pytest.mark.slow
+def test_amg_pcg_matches_dense_pseudo_inverse_c1():
+    c = bc.config_case("C1")
+    ops = fem.assemble_operators(c)
+    A = ops["Aell"]
+    h = amg.setup(A, amg.AMGOptions(nullspace=True))
+    f = -(ops["Ai"] @ bc.nodal_v0(c))
+    res = krylov.amg_pcg(A, f, h, rtol=1e-12, m=ops["m"])
+    Ad = A.toarray()
+    w, V = np.linalg.eigh(Ad)
+    fh = f - f.mean()
+    coef = V.T @ fh
+    keep = w > 1e-12 * w[-1]
+    x = V[:, keep] @ (coef[keep] / w[keep])
+    x -= (ops["m"] @ x) / ops["m"].sum()
+    assert np.linalg.norm(res.x - x) <= 1e-10 * np.linalg.norm(x)
+    # and at the working tolerance, relative error and residual as the solver reports
+    res8 = krylov.amg_pcg(A, f, h, rtol=1e-8, m=ops["m"])
+    assert res8.rel_residual_true <= 1e-8
+    assert np.linalg.norm(res8.x - x) <= 1e-6 * np.linalg.norm(x)
+
+
+def test_parabolic_matches_dense_cholesky():
+    c = bc.make_case(6, 6, 3, seed=2)
+    ops = fem.assemble_operators(c)
+    A = ops["Apar"]
+    h = amg.setup(A, amg.AMGOptions(coarse_eq_limit=10, threshold=0.0))
+    f = A @ bc.nodal_v0(c)
+    res = krylov.amg_pcg(A, f, h, rtol=1e-12)
+    x = sla.cho_solve(sla.cho_factor(A.toarray()), f)
+    assert np.linalg.norm(res.x - x) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_mixed_fcg_reaches_tolerance_c1():
+    c = bc.config_case("C1")
+    ops = fem.assemble_operators(c)
+    A = ops["Aell"]
+    h = amg.setup(A, amg.AMGOptions(nullspace=True))
+    f = -(ops["Ai"] @ bc.nodal_v0(c))
+    r64 = krylov.amg_pcg(A, f, h, rtol=1e-8, m=ops["m"])
+    r32 = krylov.amg_fcg_mixed(A, f, h, rtol=1e-8, m=ops["m"])
+    assert r32.converged and r32.rel_residual_true <= 1e-8
+    assert abs(r32.iterations - r64.iterations) <= 2
