@@ -1,0 +1,238 @@
+/*
+ * bidomain.h -- C ABI of the MI355X (gfx950) AMG-preconditioned CG solver for the
+ * decoupled Bidomain step.
+ *
+ * The method: Centofanti & Scacchi, "A comparison of Algebraic Multigrid Bidomain solvers
+ * on hybrid CPU-GPU architectures".  Each time step of the IMEX scheme (eqs. (4)-(7)) solves
+ * one elliptic system (A_i + A_e) u_e = -A_i v and one parabolic system
+ * (c_m/dt M + A_i) v^{n+1} = ... with CG preconditioned by algebraic multigrid (Sec. 2.2,
+ * Sec. 4): a setup phase (Alg. 1) builds the level hierarchy once, and every CG iteration
+ * applies one V-cycle (Alg. 2).
+ *
+ * Conventions for every entry point:
+ *   - "_dev" pointers are device (HBM) pointers on the current HIP device; every other
+ *     pointer is a host pointer.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All device work
+ *     of a call is enqueued on that stream; calls return after the results are in place
+ *     (they synchronise the stream once per convergence check).
+ *   - The caller owns every buffer it passes; setup and create calls copy what they keep
+ *     into library-owned device memory, so caller buffers may be freed once the call returns.
+ *   - Handles are owned by the library and released by the matching *_destroy call.  A
+ *     handle may be used by one stream (one host thread) at a time.
+ *   - Return value: one of the BD_* status codes.  On a nonzero status,
+ *     bidomain_last_error() returns a thread-local message.
+ *   - Sparse matrices are CSR with 32-bit row offsets and column indices, columns sorted
+ *     and unique within each row, square, every diagonal entry stored and positive.
+ */
+#ifndef BIDOMAIN_H
+#define BIDOMAIN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------ */
+#define BD_OK 0
+#define BD_E_NOT_CONVERGED 1   /* maxit reached: x holds the last iterate, info is filled */
+#define BD_E_INVALID (-1)      /* malformed CSR, bad options or arguments                  */
+#define BD_E_NOMEM (-2)        /* device or host allocation failed                         */
+#define BD_E_DEVICE (-3)       /* a HIP call failed                                        */
+#define BD_E_BREAKDOWN (-4)    /* CG breakdown: p^T A p <= 0 or r^T z <= 0                 */
+#define BD_E_NONFINITE (-5)    /* NaN/Inf in the right-hand side or an iterate             */
+#define BD_E_BUDGET (-6)       /* serving: the case does not fit the device budget         */
+
+/* ---- options ----------------------------------------------------------------------- */
+enum { BD_SA = 0, BD_RS = 1 };                 /* coarsening                                */
+enum { BD_CHEBYSHEV = 0, BD_JACOBI = 1 };      /* level smoother                            */
+enum { BD_F64 = 0, BD_F32 = 1 };               /* V-cycle precision                          */
+enum { BD_NULL_NONE = 0, BD_NULL_CONSTANT = 1 };/* kernel of the operator                    */
+
+/*
+ * AMG options.  Defaults (bidomain_default_opts) follow App. A of the paper: smoothed
+ * aggregation with threshold 0.06, one prolongator smoothing, graph squaring on the first
+ * level, coarse-equation limit 100, Chebyshev smoother of degree 2 on D^{-1}A over
+ * [0.05, 1.05] x lambda with lambda from 10 Jacobi-CG steps.  For BD_RS, `threshold` is the
+ * strong threshold alpha of eq. (10) (0.5 is the paper's CPU optimum).
+ */
+typedef struct {
+  int32_t coarsening;          /* BD_SA | BD_RS                                          */
+  double threshold;            /* SA theta (default 0.06) or RS alpha                     */
+  int32_t square_graph_levels; /* levels whose MIS runs on the squared graph (1)         */
+  int32_t prolong_smooths;     /* Jacobi smoothings of the tentative prolongator (1)     */
+  int32_t coarse_eq_limit;     /* stop coarsening at or below this many rows (100)       */
+  int32_t max_levels;          /* (25)                                                   */
+  int32_t smoother;            /* BD_CHEBYSHEV | BD_JACOBI                               */
+  int32_t smoother_degree;     /* Chebyshev degree or Jacobi sweeps per application (2)  */
+  double cheb_lo, cheb_hi;     /* Chebyshev interval factors (0.05, 1.05)                */
+  int32_t esteig_iters;        /* CG steps of the eigenvalue estimate (10)               */
+  uint64_t seed;               /* SplitMix64 seed of the estimate's start vector (0)     */
+  int32_t vcycle_precision;    /* BD_F64 | BD_F32 (then the outer CG is flexible CG)     */
+  int32_t nullspace;           /* BD_NULL_NONE | BD_NULL_CONSTANT                        */
+  double stagnation_ratio;     /* stop coarsening when n_c > ratio * n_k (0.9)           */
+  int32_t coarse_dense_max;    /* largest coarsest level solved directly (2048)          */
+} bd_amg_opts;
+
+void bidomain_default_opts(bd_amg_opts* opts);
+
+/* A CSR matrix in host memory (see the conventions above). */
+typedef struct {
+  int32_t n;
+  int64_t nnz;
+  const int32_t* row_ptr; /* n + 1 */
+  const int32_t* col_idx; /* nnz   */
+  const double* val;      /* nnz   */
+} bd_csr;
+
+typedef struct bd_amg bd_amg; /* opaque hierarchy handle */
+
+typedef struct {
+  int32_t iterations;        /* number of products A p                          */
+  double rel_residual_true;  /* ||b^ - A x|| / ||b^|| from a fresh product at exit */
+  double rel_residual_rec;   /* the recursive residual the stopping test used   */
+  double seconds;            /* wall time of the solve on the stream            */
+  int32_t status;
+} bd_solve_info;
+
+#define BD_MAX_LEVELS 32
+typedef struct {
+  int32_t nlevels;
+  int64_t n[BD_MAX_LEVELS];
+  int64_t nnz[BD_MAX_LEVELS];
+  int64_t p_nnz[BD_MAX_LEVELS];   /* prolongator P_k (level k -> k+1); 0 on the coarsest */
+  double lambda[BD_MAX_LEVELS];   /* estimate of lambda_max(D_k^{-1} A_k)                 */
+  int32_t coarse_mode;            /* 0 dense direct, 1 smoother relaxation                */
+  double operator_complexity;
+  double grid_complexity;
+  int64_t device_bytes;           /* device memory owned by the handle                    */
+} bd_amg_stats;
+
+/*
+ * Setup phase (Alg. 1): build the hierarchy of A on the host and copy it to the device.
+ * A: host CSR (copied).  opts: NULL for defaults.  null_weights: NULL, or n host doubles w;
+ * with BD_NULL_CONSTANT the solution is normalised to w^T x = 0 (w = lumped mass gives the
+ * integral-zero normalisation of the extracellular potential, Sec. 2.1), else to 1^T x = 0.
+ * Errors: BD_E_INVALID (malformed CSR, bad options), BD_E_NOMEM, BD_E_DEVICE.
+ */
+int bidomain_amg_setup(const bd_csr* A, const bd_amg_opts* opts, const double* null_weights,
+                       void* stream, bd_amg** out);
+
+/*
+ * The setup phase alone, on the host: the returned handle holds the hierarchy but no device
+ * memory; only bidomain_amg_info, bidomain_amg_export and bidomain_amg_destroy accept it
+ * (other calls return BD_E_INVALID).  Needs no GPU.  Arguments as for bidomain_amg_setup.
+ */
+int bidomain_amg_build_host(const bd_csr* A, const bd_amg_opts* opts, bd_amg** out);
+
+/*
+ * Solve A x = b with AMG-preconditioned CG (Sec. 2.2): PCG in float64 (BD_F64), or flexible
+ * CG in float64 around a float32 V-cycle (BD_F32).  With BD_NULL_CONSTANT, b, the initial
+ * guess and every preconditioned residual are projected onto 1-perp.  Stops when
+ * ||b^ - A x|| <= rtol ||b^|| on the recursive residual (b^ = projected b).
+ * b_dev: n doubles (read).  x_dev: n doubles; read as the initial guess if x_is_guess,
+ * overwritten with the solution.  maxit: iteration cap.  info: may be NULL.
+ * Returns BD_OK, BD_E_NOT_CONVERGED, BD_E_BREAKDOWN, BD_E_NONFINITE, BD_E_INVALID,
+ * BD_E_DEVICE.
+ */
+int bidomain_pcg_solve(bd_amg* h, const double* b_dev, double* x_dev, int x_is_guess, double rtol,
+                       int maxit, void* stream, bd_solve_info* info);
+
+int bidomain_amg_info(const bd_amg* h, bd_amg_stats* s);
+void bidomain_amg_destroy(bd_amg* h);
+
+/*
+ * Copy level k's operator (which = 0: A_k, 1: P_k, 2: R_k) to host arrays.  Pass NULL
+ * arrays to query sizes: *rows, *cols, *nnz are always written.  row_ptr needs rows + 1
+ * entries, col_idx and val nnz entries.
+ */
+int bidomain_amg_export(const bd_amg* h, int level, int which, int32_t* rows, int32_t* cols,
+                        int64_t* nnz, int32_t* row_ptr, int32_t* col_idx, double* val);
+
+/*
+ * Apply one operation of the V-cycle on level k, on device vectors of the hierarchy's
+ * working precision (double for BD_F64, float for BD_F32; `in_dev`/`out_dev` are typed as
+ * void* for that reason):
+ *   BD_OP_A        out = A_k in
+ *   BD_OP_P        out = P_k in           (in: level k+1, out: level k)
+ *   BD_OP_R        out = R_k in           (in: level k,   out: level k+1)
+ *   BD_OP_PRESMOOTH  out = S_k(in) from a zero guess (in = right-hand side)
+ *   BD_OP_VCYCLE   out = V-cycle from level k with right-hand side in (Alg. 2)
+ *   BD_OP_COARSE   out = coarsest-level solve of in (k is ignored)
+ * These run the same kernels the solve uses; they exist so each can be checked alone.
+ */
+enum { BD_OP_A = 0, BD_OP_P = 1, BD_OP_R = 2, BD_OP_PRESMOOTH = 3, BD_OP_VCYCLE = 4, BD_OP_COARSE = 5 };
+int bidomain_amg_apply(bd_amg* h, int op, int level, const void* in_dev, void* out_dev, void* stream);
+
+/* ---- the Bidomain slab and its time step --------------------------------------------- */
+/*
+ * A slab [0,Lx] x [0,Ly] x [0,Lz] (cm) of nx*ny*nz trilinear (Q1) elements, node
+ * p = i + (nx+1)(j + (ny+1)k).  Conductivities (S/cm) are axisymmetric (eq. (2) with
+ * sigma_n = sigma_t) around in-plane fibers at angle theta(z) = fiber_theta0 +
+ * fiber_rotation * z / Lz.  cm = chi C_m (mF/cm^3), dt in ms.
+ */
+typedef struct {
+  int32_t nx, ny, nz;
+  double Lx, Ly, Lz;
+  double sig_il, sig_it, sig_el, sig_et;
+  double fiber_theta0, fiber_rotation;
+  double cm, dt;
+} bd_slab;
+
+enum { BD_MAT_AI = 0, BD_MAT_AE = 1, BD_MAT_AELL = 2, BD_MAT_APAR = 3 };
+/*
+ * Assemble one slab operator on the host (Sec. 2.2: Q1 stiffness with 2x2x2 Gauss points,
+ * lumped mass): A_i, A_e, A_ell = A_i + A_e, or A_par = (cm/dt) M + A_i, all on the full
+ * 27-point pattern.  Arrays are caller-owned host buffers of n + 1 (row_ptr), nnz27 (col_idx,
+ * val) and n (mass, may be NULL) entries, n = (nx+1)(ny+1)(nz+1),
+ * nnz27 = (3nx+1)(3ny+1)(3nz+1).
+ */
+int bidomain_slab_assemble(const bd_slab* s, int which, int32_t* row_ptr, int32_t* col_idx,
+                           double* val, double* mass);
+
+typedef struct bd_sim bd_sim;
+
+typedef struct {
+  int32_t steps;
+  int32_t it_par, it_ell;           /* iterations summed over the steps      */
+  double ms_memb, ms_par, ms_ell;   /* device time summed over the steps     */
+  double rel_res_par, rel_res_ell;  /* true relative residuals of the last step */
+  int32_t status;
+} bd_step_info;
+
+/*
+ * Create a simulation: assemble A_i, A_e and M, build the elliptic (ell, nullspace forced to
+ * BD_NULL_CONSTANT, normalised with the lumped mass) and parabolic (par) hierarchies once
+ * (hierarchy reuse, App. A), copy v0 (and w0, NULL = 0), and solve for u_e^0.
+ * v0_dev, w0_dev: n device doubles (read).
+ */
+int bidomain_sim_create(const bd_slab* s, const bd_amg_opts* ell, const bd_amg_opts* par,
+                        const double* v0_dev, const double* w0_dev, double rtol, void* stream,
+                        bd_sim** out);
+
+/*
+ * Advance nsteps IMEX steps (eqs. (4)-(7)): Aliev-Panfilov membrane update, parabolic solve
+ * (warm-started from v^n), elliptic solve (warm-started from u_e^n).  rtol for both solves.
+ */
+int bidomain_step(bd_sim* sim, int nsteps, double rtol, void* stream, bd_step_info* info);
+
+enum { BD_V = 0, BD_UE = 1, BD_W = 2 };
+int bidomain_sim_get(bd_sim* sim, int field, double* out_dev, void* stream);
+/* Handles of the two hierarchies (owned by the simulation). */
+bd_amg* bidomain_sim_hierarchy(bd_sim* sim, int which /* 0 elliptic, 1 parabolic */);
+void bidomain_sim_destroy(bd_sim* sim);
+
+/*
+ * Instrumentation: when enabled, every launch of the fine-level outer product q = A p
+ * (the solve's dominant kernel) is bracketed by HIP events on the solve's stream; the sum
+ * of their durations and the launch count accumulate until read (and reset) here.
+ */
+void bidomain_profile_enable(int on);
+void bidomain_profile_read(double* total_ms, int64_t* launches, int reset);
+
+const char* bidomain_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIDOMAIN_H */

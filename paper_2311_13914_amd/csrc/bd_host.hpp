@@ -1,0 +1,56 @@
+// Host-side data structures of the library: CSR matrices, the AMG level hierarchy as built
+// on the host, and the setup/assembly routines (setup phase, Alg. 1; Q1 assembly, Sec. 2.2).
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "bidomain.h"
+
+namespace bd {
+
+struct Csr {
+  int32_t nrows = 0, ncols = 0;
+  std::vector<int32_t> rp;  // nrows + 1
+  std::vector<int32_t> ci;  // nnz, sorted within each row
+  std::vector<double> v;    // nnz
+  int64_t nnz() const { return (int64_t)ci.size(); }
+};
+
+// C = A^T (columns sorted).
+Csr transpose(const Csr& A);
+// C = A B on the structural pattern of the product (no value is dropped).
+Csr spgemm(const Csr& A, const Csr& B);
+std::vector<double> diagonal(const Csr& A);
+// Checks the boundary's CSR contract; returns an empty string when valid.
+std::string validate(const Csr& A);
+
+struct HostLevel {
+  Csr A;                        // level operator
+  Csr P, R;                     // prolongator to this level from the next, and its transpose
+  std::vector<double> B;        // near-null vector on this level
+  std::vector<double> Dinv;     // 1 / diag(A)
+  double lam = std::numeric_limits<double>::quiet_NaN();  // lambda_max(D^{-1} A) estimate
+};
+
+struct HostHierarchy {
+  std::vector<HostLevel> lv;
+  int coarse_mode = 0;          // 0: dense G on the coarsest level, 1: smoother relaxation
+  std::vector<double> G;        // n_M x n_M row-major: A_M^{-1}, or the pseudo-inverse on b-perp
+};
+
+// Setup phase: returns BD_OK or a BD_E_* code with a message in err.
+int build_hierarchy(const Csr& A, const bd_amg_opts& o, HostHierarchy& H, std::string& err);
+
+// Largest Ritz value of D^{-1} A after `iters` Jacobi-CG steps from a SplitMix64 vector.
+double lambda_estimate(const Csr& A, const std::vector<double>& Dinv, int iters, uint64_t seed);
+
+// Q1 slab operators (27-point pattern, structural zeros kept).
+void assemble_slab_stiffness(const bd_slab& s, double sig_l, double sig_t, Csr& A);
+void slab_lumped_mass(const bd_slab& s, std::vector<double>& m);
+int64_t slab_nodes(const bd_slab& s);
+
+}  // namespace bd

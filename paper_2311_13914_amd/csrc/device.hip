@@ -1,0 +1,1104 @@
+// Device side of the library: the AMG hierarchy in HBM, the V-cycle (Alg. 2) as a sequence
+// of fused kernels, PCG / flexible CG with all scalars kept on the device, the Bidomain
+// time step (eqs. (4)-(7)) and the C ABI declared in bidomain.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "bd_host.hpp"
+#include "bidomain.h"
+#include "kernels.hpp"
+
+namespace bd {
+
+// ------------------------------------------------------------------------------------------
+// Errors: internal code throws Failure; every C entry point converts it to a status code.
+struct Failure {
+  int code;
+  std::string msg;
+};
+thread_local std::string g_last_error;
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw Failure{e_ == hipErrorOutOfMemory ? BD_E_NOMEM : BD_E_DEVICE,                 \
+                    std::string(#expr) + ": " + hipGetErrorString(e_)};                   \
+  } while (0)
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Failure& e) {
+    g_last_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return BD_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return BD_E_INVALID;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Device memory owned by a handle.
+struct Arena {
+  std::vector<void*> ptrs;
+  int64_t bytes = 0;
+  template <typename T>
+  T* alloc(size_t count) {
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    HIPCHK(hipMalloc(&p, count * sizeof(T)));
+    ptrs.push_back(p);
+    bytes += (int64_t)(count * sizeof(T));
+    return static_cast<T*>(p);
+  }
+  ~Arena() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+template <typename T>
+struct DCsr {
+  int n = 0, ncols = 0;
+  int64_t nnz = 0;
+  const int* rp = nullptr;
+  const int* ci = nullptr;
+  T* v = nullptr;
+  int G = 8;    // lanes per row
+  int tpb = 1;  // row tiles per block
+  int nb = 0;   // blocks of a product launch
+};
+
+int lanes_for(double mean_row) {
+  int g = 2;
+  while (g < 64 && g * 4 < mean_row) g *= 2;
+  return g;
+}
+
+template <typename T>
+void configure(DCsr<T>& M, int max_blocks) {
+  M.G = lanes_for(M.n ? (double)M.nnz / M.n : 1.0);
+  const int rpt = kBlock / M.G;
+  const int64_t tiles = (M.n + rpt - 1) / rpt;
+  M.tpb = (int)std::max<int64_t>(1, (tiles + max_blocks - 1) / max_blocks);
+  M.nb = (int)std::max<int64_t>(1, (tiles + M.tpb - 1) / M.tpb);
+}
+
+template <typename T>
+DCsr<T> upload(Arena& ar, const Csr& H, const int* rp_shared, const int* ci_shared, hipStream_t st,
+               int max_blocks) {
+  DCsr<T> M;
+  M.n = H.nrows;
+  M.ncols = H.ncols;
+  M.nnz = H.nnz();
+  if (rp_shared) {
+    M.rp = rp_shared;
+    M.ci = ci_shared;
+  } else {
+    int* rp = ar.alloc<int>(H.rp.size());
+    int* ci = ar.alloc<int>(H.ci.size());
+    HIPCHK(hipMemcpyAsync(rp, H.rp.data(), H.rp.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ci, H.ci.data(), H.ci.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    M.rp = rp;
+    M.ci = ci;
+  }
+  M.v = ar.alloc<T>(H.v.size());
+  std::vector<T> tmp(H.v.begin(), H.v.end());
+  HIPCHK(hipMemcpyAsync(M.v, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  configure(M, max_blocks);
+  return M;
+}
+
+template <typename T>
+T* upload_vec(Arena& ar, const std::vector<double>& h, hipStream_t st) {
+  T* d = ar.alloc<T>(h.size());
+  std::vector<T> tmp(h.begin(), h.end());
+  HIPCHK(hipMemcpyAsync(d, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return d;
+}
+
+template <typename T>
+struct DLevel {
+  int n = 0;
+  DCsr<T> A, P, R;
+  T* dinv = nullptr;
+  T* f = nullptr;  // right-hand side (level 0: set per call)
+  T *x = nullptr, *r = nullptr, *da = nullptr, *db = nullptr;
+  double lam = 0.0;
+  T c0 = 0;                 // first smoothing step coefficient (Chebyshev 1/theta, Jacobi omega)
+  std::vector<T> c1, c2;    // Chebyshev step j = 1 .. degree-1
+};
+
+constexpr int kMaxBlocksSpmv = 8192;
+constexpr int kMaxBlocksVec = 2048;
+
+int vec_blocks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, kMaxBlocksVec));
+}
+
+// Profiling of the fine-level outer product (see bidomain_profile_enable).
+struct Prof {
+  std::mutex mu;
+  bool on = false;
+  double total_ms = 0.0;
+  int64_t launches = 0;
+} g_prof;
+
+}  // namespace bd
+
+using namespace bd;
+
+struct bd_amg {
+  bd_amg_opts o{};
+  HostHierarchy H;
+  Arena ar;
+  int n = 0;
+  int M = 0;  // index of the coarsest level
+  bool mixed = false;
+  bool host_only = false;   // hierarchy on the host only (bidomain_amg_build_host)
+  // outer (float64) fine operator
+  DCsr<double> A0;
+  std::vector<DLevel<double>> L64;
+  std::vector<DLevel<float>> L32;
+  double* G = nullptr;  // coarsest dense operator (float64)
+  int nM = 0;
+  // CG state
+  double *r = nullptr, *p = nullptr, *q = nullptr, *w = nullptr;
+  float* r32[2] = {nullptr, nullptr};
+  Solve sv{};
+  Solve sv_apply{};     // flags that never say "done", for bidomain_amg_apply
+  int64_t part_len = 0;
+  int* host_flags = nullptr;  // pinned
+  int last_iters = 8;
+  std::vector<hipEvent_t> prof_ev;
+  ~bd_amg() {
+    if (host_flags) (void)hipHostFree(host_flags);
+    for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+  }
+};
+
+namespace bd {
+
+// ------------------------------------------------------------------------------------------
+// Kernel launch helpers.
+template <typename T, int OP>
+void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
+  a.rp = M.rp;
+  a.ci = M.ci;
+  a.av = M.v;
+  a.nrows = M.n;
+  a.tpb = M.tpb;
+  if (M.n == 0) return;
+  switch (M.G) {
+    case 2: k_spmv<T, 2, OP><<<M.nb, kBlock, 0, st>>>(a); break;
+    case 4: k_spmv<T, 4, OP><<<M.nb, kBlock, 0, st>>>(a); break;
+    case 8: k_spmv<T, 8, OP><<<M.nb, kBlock, 0, st>>>(a); break;
+    case 16: k_spmv<T, 16, OP><<<M.nb, kBlock, 0, st>>>(a); break;
+    case 32: k_spmv<T, 32, OP><<<M.nb, kBlock, 0, st>>>(a); break;
+    default: k_spmv<T, 64, OP><<<M.nb, kBlock, 0, st>>>(a); break;
+  }
+  HIPCHK(hipGetLastError());
+}
+
+template <typename T>
+SpArgs<T> args(const Solve& sv) {
+  SpArgs<T> a{};
+  a.sv = sv;
+  return a;
+}
+
+template <typename T>
+std::vector<DLevel<T>>& levels(bd_amg* h);
+template <>
+std::vector<DLevel<double>>& levels<double>(bd_amg* h) { return h->L64; }
+template <>
+std::vector<DLevel<float>>& levels<float>(bd_amg* h) { return h->L32; }
+
+// First smoothing step from a zero guess can be folded into the producer of f_k when level k
+// is smoothed (every level but a directly solved coarsest one).
+bool smoothed_level(const bd_amg* h, int k) { return k < h->M || h->H.coarse_mode == 1; }
+
+// Pre-smoothing from a zero guess: x_k = S_k(f_k).  `d_ready`: d = c0 dinv f (and x = d for
+// degree 1 / Jacobi) were already written by the producer of f_k.
+template <typename T>
+void smooth_pre(bd_amg* h, DLevel<T>& L, const Solve& sv, bool d_ready, hipStream_t st) {
+  const int deg = h->o.smoother_degree;
+  const bool jac = h->o.smoother == BD_JACOBI;
+  if (!d_ready) {
+    k_cheb_pre0<T><<<vec_blocks(L.n), kBlock, 0, st>>>(sv, L.f, L.dinv, L.da, (deg == 1 || jac) ? L.x : nullptr,
+                                                      L.c0, L.n);
+    HIPCHK(hipGetLastError());
+  }
+  if (jac) {
+    T* cur = L.x;
+    T* oth = L.da;
+    for (int j = 1; j < deg; ++j) {
+      SpArgs<T> a = args<T>(sv);
+      a.x = cur; a.y = oth; a.f = L.f; a.dinv = L.dinv; a.c0 = L.c0;
+      launch_spmv<T, OP_JACOBI>(L.A, a, st);
+      std::swap(cur, oth);
+    }
+    if (cur != L.x) {
+      k_add<T><<<vec_blocks(L.n), kBlock, 0, st>>>(sv, L.x, cur, 1, L.n);
+      HIPCHK(hipGetLastError());
+    }
+    return;
+  }
+  if (deg < 2) return;
+  SpArgs<T> a = args<T>(sv);
+  a.x = L.da; a.xs = L.x; a.f = L.f; a.dinv = L.dinv; a.c1 = L.c1[0]; a.c2 = L.c2[0];
+  a.store_rd = deg > 2; a.r = L.r; a.y2 = L.db;
+  launch_spmv<T, OP_CHEB_FIRST>(L.A, a, st);
+  T* dcur = L.db;
+  T* doth = L.da;
+  for (int j = 2; j < deg; ++j) {
+    SpArgs<T> b = args<T>(sv);
+    b.x = dcur; b.xs = L.x; b.r = L.r; b.dinv = L.dinv; b.c1 = L.c1[j - 1]; b.c2 = L.c2[j - 1];
+    b.add_d = 0; b.store_rd = j < deg - 1; b.y2 = doth;
+    launch_spmv<T, OP_CHEB_STEP>(L.A, b, st);
+    std::swap(dcur, doth);
+  }
+}
+
+struct RedSpec {
+  int red = RED_NONE;
+  const double* r64 = nullptr;
+  const float* r32 = nullptr;
+  const float* r32_old = nullptr;
+};
+
+// Post-smoothing from the current x_k.  Returns true if the level-0 reductions were fused
+// into its last kernel.
+template <typename T>
+bool smooth_post(bd_amg* h, DLevel<T>& L, const Solve& sv, const RedSpec& red, hipStream_t st) {
+  const int deg = h->o.smoother_degree;
+  if (h->o.smoother == BD_JACOBI) {
+    T* cur = L.x;
+    T* oth = L.da;
+    for (int j = 0; j < deg; ++j) {
+      SpArgs<T> a = args<T>(sv);
+      a.x = cur; a.y = oth; a.f = L.f; a.dinv = L.dinv; a.c0 = L.c0;
+      launch_spmv<T, OP_JACOBI>(L.A, a, st);
+      std::swap(cur, oth);
+    }
+    if (cur != L.x) {
+      k_add<T><<<vec_blocks(L.n), kBlock, 0, st>>>(sv, L.x, cur, 1, L.n);
+      HIPCHK(hipGetLastError());
+    }
+    return false;
+  }
+  SpArgs<T> a = args<T>(sv);
+  a.x = L.x; a.f = L.f; a.r = L.r; a.y2 = L.da; a.dinv = L.dinv; a.c0 = L.c0;
+  launch_spmv<T, OP_CHEB_POST0>(L.A, a, st);
+  if (deg == 1) {
+    k_add<T><<<vec_blocks(L.n), kBlock, 0, st>>>(sv, L.x, L.da, 0, L.n);
+    HIPCHK(hipGetLastError());
+    return false;
+  }
+  T* dcur = L.da;
+  T* doth = L.db;
+  bool fused = false;
+  for (int j = 1; j < deg; ++j) {
+    SpArgs<T> b = args<T>(sv);
+    b.x = dcur; b.xs = L.x; b.r = L.r; b.dinv = L.dinv; b.c1 = L.c1[j - 1]; b.c2 = L.c2[j - 1];
+    b.add_d = j == 1; b.store_rd = j < deg - 1; b.y2 = doth;
+    if (j == deg - 1 && red.red != RED_NONE) {
+      b.red = red.red; b.r64 = red.r64; b.r32 = red.r32; b.r32_old = red.r32_old;
+      fused = true;
+    }
+    launch_spmv<T, OP_CHEB_STEP>(L.A, b, st);
+    std::swap(dcur, doth);
+  }
+  return fused;
+}
+
+template <typename T>
+void coarse_solve(bd_amg* h, DLevel<T>& L, const Solve& sv, bool d_ready, hipStream_t st) {
+  if (h->H.coarse_mode == 1) {
+    smooth_pre<T>(h, L, sv, d_ready, st);
+    return;
+  }
+  k_coarse_gemv<T><<<(h->nM + 3) / 4, kBlock, 0, st>>>(sv, h->G, L.f, L.x, h->nM);
+  HIPCHK(hipGetLastError());
+}
+
+// V-cycle from level k (Alg. 2, mu1 = mu2 = 1): x_k = V(f_k).  Returns true if the level-0
+// reductions were fused.
+template <typename T>
+bool vcycle(bd_amg* h, int k, const Solve& sv, bool d_ready, const RedSpec& red, hipStream_t st) {
+  auto& L = levels<T>(h);
+  DLevel<T>& Lk = L[k];
+  if (k == h->M) {
+    coarse_solve<T>(h, Lk, sv, d_ready, st);
+    return false;
+  }
+  smooth_pre<T>(h, Lk, sv, d_ready, st);
+  {  // residual
+    SpArgs<T> a = args<T>(sv);
+    a.x = Lk.x; a.f = Lk.f; a.y = Lk.r;
+    launch_spmv<T, OP_RESID>(Lk.A, a, st);
+  }
+  DLevel<T>& Ln = L[k + 1];
+  const bool fuse = smoothed_level(h, k + 1);
+  {  // restriction (+ first smoothing step of the next level)
+    SpArgs<T> a = args<T>(sv);
+    a.x = Lk.r; a.y = Ln.f;
+    if (fuse) {
+      a.y2 = Ln.da; a.dinv2 = Ln.dinv; a.c0 = Ln.c0;
+      a.xs = (h->o.smoother == BD_JACOBI || h->o.smoother_degree == 1) ? Ln.x : nullptr;
+      launch_spmv<T, OP_RESTRICT>(Lk.R, a, st);
+    } else {
+      launch_spmv<T, OP_Y>(Lk.R, a, st);
+    }
+  }
+  vcycle<T>(h, k + 1, sv, fuse, RedSpec{}, st);
+  {  // prolongation and correction
+    SpArgs<T> a = args<T>(sv);
+    a.x = Ln.x; a.y = Lk.x;
+    launch_spmv<T, OP_ADDY>(Lk.P, a, st);
+  }
+  return smooth_post<T>(h, Lk, sv, k == 0 ? red : RedSpec{}, st);
+}
+
+// Runs the V-cycle on level 0 and makes sure the level-0 reductions happen.
+template <typename T>
+void precondition(bd_amg* h, const Solve& sv, bool d_ready, const RedSpec& red, hipStream_t st) {
+  auto& L = levels<T>(h);
+  const bool fused = vcycle<T>(h, 0, sv, d_ready, red, st);
+  if (!fused && red.red != RED_NONE) {
+    SpArgs<T> a = args<T>(sv);
+    a.nrows = L[0].n;
+    a.red = red.red; a.r64 = red.r64; a.r32 = red.r32; a.r32_old = red.r32_old;
+    k_vc_reduce<T><<<vec_blocks(L[0].n), kBlock, 0, st>>>(a, L[0].x);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+template <typename T>
+void build_levels(bd_amg* h, hipStream_t st) {
+  auto& L = levels<T>(h);
+  const auto& HL = h->H.lv;
+  const int nl = (int)HL.size();
+  L.resize(nl);
+  const int deg = std::max(1, h->o.smoother_degree);
+  for (int k = 0; k < nl; ++k) {
+    DLevel<T>& D = L[k];
+    D.n = HL[k].A.nrows;
+    if constexpr (std::is_same<T, double>::value) {
+      if (k == 0) D.A = h->A0;  // level 0 of the float64 V-cycle is the outer operator itself
+    }
+    if (D.A.n == 0)
+      D.A = upload<T>(h->ar, HL[k].A, k == 0 ? h->A0.rp : nullptr, k == 0 ? h->A0.ci : nullptr, st, kMaxBlocksSpmv);
+    if (k < nl - 1) {
+      D.P = upload<T>(h->ar, HL[k].P, nullptr, nullptr, st, kMaxBlocksSpmv);
+      D.R = upload<T>(h->ar, HL[k].R, nullptr, nullptr, st, kMaxBlocksSpmv);
+    }
+    D.dinv = upload_vec<T>(h->ar, HL[k].Dinv, st);
+    if (k > 0) D.f = h->ar.alloc<T>(D.n);
+    D.x = h->ar.alloc<T>(D.n);
+    D.r = h->ar.alloc<T>(D.n);
+    D.da = h->ar.alloc<T>(D.n);
+    D.db = h->ar.alloc<T>(D.n);
+    D.lam = HL[k].lam;
+    if (smoothed_level(h, k)) {
+      if (h->o.smoother == BD_JACOBI) {
+        D.c0 = (T)(4.0 / (3.0 * D.lam));
+      } else {
+        // Chebyshev three-term recurrence on [lo, hi] * lambda (Saad, Iterative Methods, Alg. 12.1)
+        const double a = h->o.cheb_lo * D.lam, b = h->o.cheb_hi * D.lam;
+        const double theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
+        double rho = 1.0 / sigma;
+        D.c0 = (T)(1.0 / theta);
+        for (int j = 1; j < deg; ++j) {
+          const double rn = 1.0 / (2.0 * sigma - rho);
+          D.c1.push_back((T)(rn * rho));
+          D.c2.push_back((T)(2.0 * rn / delta));
+          rho = rn;
+        }
+      }
+    }
+  }
+}
+
+void alloc_solve_state(bd_amg* h, hipStream_t st) {
+  Arena& ar = h->ar;
+  const int n = h->n;
+  h->r = ar.alloc<double>(n);
+  h->p = ar.alloc<double>(n);
+  h->q = ar.alloc<double>(n);
+  if (h->mixed) {
+    h->r32[0] = ar.alloc<float>(n);
+    h->r32[1] = ar.alloc<float>(n);
+  }
+  int64_t maxnb = vec_blocks(n);
+  auto upd = [&](int nb) { maxnb = std::max<int64_t>(maxnb, nb); };
+  upd(h->A0.nb);
+  if (h->mixed) upd(h->L32[0].A.nb); else upd(h->L64[0].A.nb);
+  h->part_len = 4 * maxnb + 16;
+  for (Solve* s : {&h->sv, &h->sv_apply}) {
+    s->sc = ar.alloc<double>(S_COUNT);
+    s->fl = ar.alloc<int>(F_COUNT);
+    s->cnt = ar.alloc<unsigned>(C_COUNT);
+    s->part = ar.alloc<double>(h->part_len);
+    s->n = n;
+    HIPCHK(hipMemsetAsync(s->sc, 0, S_COUNT * sizeof(double), st));
+    HIPCHK(hipMemsetAsync(s->fl, 0, F_COUNT * sizeof(int), st));
+    HIPCHK(hipMemsetAsync(s->cnt, 0, C_COUNT * sizeof(unsigned), st));
+  }
+  // fine-grained (coherent) pinned memory: the update kernel's system-scope stores are seen
+  // by the host as soon as the event after that kernel completes
+  HIPCHK(hipHostMalloc(&h->host_flags, 4 * sizeof(int), hipHostMallocCoherent | hipHostMallocMapped));
+  std::memset(h->host_flags, 0, 4 * sizeof(int));
+  int* dflags = nullptr;
+  HIPCHK(hipHostGetDevicePointer((void**)&dflags, h->host_flags, 0));
+  h->sv.host_flags = dflags;
+  h->sv_apply.host_flags = nullptr;
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// ------------------------------------------------------------------------------------------
+// The solve.
+template <typename T>
+int pcg(bd_amg* h, const double* b, double* x, int guess, double rtol, int maxit, hipStream_t st,
+        bd_solve_info* info) {
+  const int n = h->n;
+  const Solve& sv = h->sv;
+  auto& L = levels<T>(h);
+  hipEvent_t t0, t1;
+  HIPCHK(hipEventCreate(&t0));
+  HIPCHK(hipEventCreate(&t1));
+  struct EvGuard {
+    hipEvent_t a, b;
+    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  } eg{t0, t1};
+  HIPCHK(hipEventRecord(t0, st));
+
+  // solve state
+  int fl0[F_COUNT] = {0};
+  fl0[F_FIRST] = 1;
+  fl0[F_MAXIT] = std::max(1, maxit);
+  fl0[F_NULLSPACE] = h->o.nullspace == BD_NULL_CONSTANT;
+  double rtol2 = rtol * rtol;
+  HIPCHK(hipMemcpyAsync(sv.fl, fl0, sizeof(fl0), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(sv.sc + S_RTOL2, &rtol2, sizeof(double), hipMemcpyHostToDevice, st));
+  h->host_flags[0] = h->host_flags[1] = 0;
+
+  const int vb = vec_blocks(n);
+  k_init_means<<<vb, kBlock, 0, st>>>(sv, b, guess ? x : nullptr, n);
+  k_init_guess<<<vb, kBlock, 0, st>>>(sv, x, guess, n);
+  HIPCHK(hipGetLastError());
+  {
+    SpArgs<double> a = args<double>(sv);
+    a.x = x; a.y = h->r; a.b = b;
+    launch_spmv<double, OP_INIT_RESID>(h->A0, a, st);
+  }
+  int flags[F_COUNT];
+  HIPCHK(hipMemcpyAsync(flags, sv.fl, sizeof(flags), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+
+  if (!flags[F_DONE]) {
+    const bool mixed = h->mixed;
+    // level-0 right-hand side of the V-cycle
+    int cur = 0;
+    RedSpec red;
+    if (mixed) {
+      k_convert<double, float><<<vb, kBlock, 0, st>>>(h->r, h->r32[0], n);
+      HIPCHK(hipGetLastError());
+      L[0].f = (T*)h->r32[0];
+      red.red = RED_F32; red.r32 = h->r32[0]; red.r32_old = h->r32[0];
+    } else {
+      L[0].f = (T*)h->r;
+      red.red = RED_F64; red.r64 = h->r;
+    }
+    precondition<T>(h, sv, false, red, st);
+    k_cg_direction<T><<<vb, kBlock, 0, st>>>(sv, h->p, L[0].x, n);
+    k_clear_first<<<1, 64, 0, st>>>(sv);
+    HIPCHK(hipGetLastError());
+
+    const bool fuse0 = smoothed_level(h, 0);
+    const bool x0_too = h->o.smoother == BD_JACOBI || h->o.smoother_degree == 1;
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    struct EvGuard2 {
+      hipEvent_t* e;
+      ~EvGuard2() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
+    } eg2{ev};
+    std::lock_guard<std::mutex> plock(g_prof.mu);
+    const bool prof = g_prof.on;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pev;
+    int enq = 0;
+    for (;;) {
+      // q = A p, alpha
+      SpArgs<double> a = args<double>(sv);
+      a.x = h->p; a.y = h->q;
+      if (prof) {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, st));
+        launch_spmv<double, OP_CG_Q>(h->A0, a, st);
+        HIPCHK(hipEventRecord(e1, st));
+        pev.push_back({e0, e1});
+      } else {
+        launch_spmv<double, OP_CG_Q>(h->A0, a, st);
+      }
+      // x, r update, convergence test, next V-cycle right-hand side
+      float* r32n = mixed ? h->r32[cur ^ 1] : nullptr;
+      T* f0 = mixed ? (T*)r32n : (T*)h->r;
+      k_cg_update<T><<<vb, kBlock, 0, st>>>(sv, x, h->r, h->p, h->q, r32n, L[0].dinv, fuse0 ? L[0].da : nullptr,
+                                           (fuse0 && x0_too) ? L[0].x : nullptr, L[0].c0, n);
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipEventRecord(ev[enq & 1], st));
+      if (mixed) {
+        red.r32_old = h->r32[cur];
+        red.r32 = r32n;
+        cur ^= 1;
+      }
+      L[0].f = f0;
+      precondition<T>(h, sv, fuse0, red, st);
+      k_cg_direction<T><<<vb, kBlock, 0, st>>>(sv, h->p, L[0].x, n);
+      HIPCHK(hipGetLastError());
+      ++enq;
+      // look one iteration behind: the update of iteration enq-1 has finished (or will soon)
+      if (enq >= 2 || enq > maxit) {
+        HIPCHK(hipEventSynchronize(ev[(enq - 2) & 1]));  // update kernel of iteration enq - 1
+        const int done = __atomic_load_n(&h->host_flags[0], __ATOMIC_ACQUIRE);
+        if (done || enq > maxit) break;
+      }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (prof) {
+      for (auto& e : pev) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+        g_prof.total_ms += ms;
+      }
+      g_prof.launches += (int64_t)pev.size();
+    }
+  } else if (flags[F_STATUS] == 0) {
+    // b^ = 0 gives x = 0; a converged initial guess is kept
+  }
+
+  double sc[S_COUNT];
+  HIPCHK(hipMemcpyAsync(sc, sv.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(flags, sv.fl, sizeof(flags), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const bool zero_rhs = sc[S_FNORM2] == 0.0;
+  if (zero_rhs) HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+  // true residual, then the null-space normalisation
+  Solve svx = sv;
+  int fl_true[F_COUNT] = {0};
+  fl_true[F_NULLSPACE] = flags[F_NULLSPACE];
+  HIPCHK(hipMemcpyAsync(sv.fl + F_DONE, fl_true, sizeof(int), hipMemcpyHostToDevice, st));
+  if (!zero_rhs) {
+    SpArgs<double> a = args<double>(svx);
+    a.x = x; a.b = b;
+    launch_spmv<double, OP_TRUE_RESID>(h->A0, a, st);
+  }
+  if (h->o.nullspace == BD_NULL_CONSTANT && !zero_rhs) {
+    k_norm_sums<<<vb, kBlock, 0, st>>>(svx, h->w, x, n);
+    k_norm_apply<<<vb, kBlock, 0, st>>>(svx, x, n);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipEventRecord(t1, st));
+  HIPCHK(hipMemcpyAsync(sc, sv.sc, sizeof(sc), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, t0, t1));
+
+  int status = flags[F_STATUS];
+  const double fn = sc[S_FNORM2];
+  bd_solve_info inf{};
+  inf.iterations = flags[F_ITERS];
+  inf.rel_residual_rec = fn > 0 ? std::sqrt(sc[S_RNORM2] / fn) : 0.0;
+  inf.rel_residual_true = fn > 0 ? std::sqrt(sc[S_TRUE2] / fn) : 0.0;
+  inf.seconds = ms * 1e-3;
+  if (status == 0 && !std::isfinite(inf.rel_residual_true)) status = BD_E_NONFINITE;
+  inf.status = status;
+  if (info) *info = inf;
+  h->last_iters = std::max(1, inf.iterations);
+  if (status == BD_E_BREAKDOWN) g_last_error = "CG breakdown (p^T A p <= 0 or r^T z <= 0)";
+  if (status == BD_E_NONFINITE) g_last_error = "non-finite value in the right-hand side or an iterate";
+  if (status == BD_E_NOT_CONVERGED) g_last_error = "iteration cap reached before convergence";
+  return status;
+}
+
+}  // namespace bd
+
+// ==========================================================================================
+// Simulation handle.
+struct bd_sim {
+  bd_slab s{};
+  int n = 0;
+  bd_amg* hell = nullptr;
+  bd_amg* hpar = nullptr;
+  Arena ar;
+  DCsr<double> Ai;
+  double *v = nullptr, *ue = nullptr, *w = nullptr, *m = nullptr, *rhs = nullptr, *fell = nullptr;
+  ~bd_sim() {
+    delete hell;
+    delete hpar;
+  }
+};
+
+namespace bd {
+
+// Aliev-Panfilov (Chaos Solitons Fractals 7 (1996) 293): k = 8, a = 0.15, eps0 = 0.002,
+// mu1 = 0.2, mu2 = 0.3, one model time unit = 12.9 ms; u = (v + 85) / 105.
+constexpr double kApK = 8.0, kApA = 0.15, kApEps0 = 0.002, kApMu1 = 0.2, kApMu2 = 0.3;
+constexpr double kApTunit = 12.9, kApVscale = 105.0, kApVrest = -85.0;
+
+// One membrane step and the parabolic right-hand side (eqs. (4), (7)):
+//   w <- (w + dt' eps (-k u (u - a - 1))) / (1 + dt' eps),   eps = eps0 + mu1 w / (u + mu2),
+//   I_ion = -cm (105 / 12.9) [k u (u - a)(1 - u) - u w_new],
+//   rhs = (cm / dt) m v - (A_i u_e) - m I_ion.
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_membrane_rhs(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                         const double* __restrict__ av, const double* __restrict__ ue,
+                                                         const double* __restrict__ v, double* __restrict__ w,
+                                                         const double* __restrict__ m, double* __restrict__ rhs,
+                                                         double dt, double cm, int n) {
+  constexpr int RPT = kBlock / G;
+  const int row = xcd_tile(blockIdx.x, gridDim.x) * RPT + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= n) return;
+  const double s = row_product<double, G>(rp, ci, av, ue, row, lane);
+  if (lane != 0) return;
+  const double u = (v[row] - kApVrest) / kApVscale;
+  const double dtp = dt / kApTunit;
+  const double wo = w[row];
+  const double eps = kApEps0 + kApMu1 * wo / (u + kApMu2);
+  const double wn = (wo + dtp * eps * (-kApK * u * (u - kApA - 1.0))) / (1.0 + dtp * eps);
+  w[row] = wn;
+  const double iion = -cm * (kApVscale / kApTunit) * (kApK * u * (u - kApA) * (1.0 - u) - u * wn);
+  rhs[row] = (cm / dt) * m[row] * v[row] - s - m[row] * iion;
+}
+
+// y = -A x (right-hand side of the elliptic system, eq. (6)).
+template <int G>
+__global__ __launch_bounds__(kBlock) void k_neg_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const double* __restrict__ av, const double* __restrict__ x,
+                                                     double* __restrict__ y, int n) {
+  constexpr int RPT = kBlock / G;
+  const int row = xcd_tile(blockIdx.x, gridDim.x) * RPT + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= n) return;
+  const double s = row_product<double, G>(rp, ci, av, x, row, lane);
+  if (lane == 0) y[row] = -s;
+}
+
+int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, hipStream_t st, bd_amg** out,
+               bool host_only = false) {
+  if (!A || !out) throw Failure{BD_E_INVALID, "null argument"};
+  bd_amg_opts o;
+  bidomain_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.smoother_degree < 1 || o.coarse_eq_limit < 1 || o.max_levels < 1 || !(o.cheb_hi > o.cheb_lo) ||
+      !(o.cheb_lo >= 0.0) || o.esteig_iters < 1 || !(o.threshold >= 0.0) || !(o.stagnation_ratio > 0.0) ||
+      o.coarse_dense_max < 1 || (o.coarsening != BD_SA && o.coarsening != BD_RS) ||
+      (o.smoother != BD_CHEBYSHEV && o.smoother != BD_JACOBI) ||
+      (o.vcycle_precision != BD_F64 && o.vcycle_precision != BD_F32))
+    throw Failure{BD_E_INVALID, "invalid AMG options"};
+  Csr H;
+  H.nrows = H.ncols = A->n;
+  if (A->n <= 0 || A->nnz < 0 || A->nnz > INT32_MAX || !A->row_ptr || !A->col_idx || !A->val)
+    throw Failure{BD_E_INVALID, "invalid CSR arguments"};
+  H.rp.assign(A->row_ptr, A->row_ptr + A->n + 1);
+  if (H.rp[A->n] != A->nnz) throw Failure{BD_E_INVALID, "row_ptr[n] must equal nnz"};
+  H.ci.assign(A->col_idx, A->col_idx + A->nnz);
+  H.v.assign(A->val, A->val + A->nnz);
+  const std::string bad = validate(H);
+  if (!bad.empty()) throw Failure{BD_E_INVALID, bad};
+
+  std::unique_ptr<bd_amg> h(new bd_amg());
+  h->o = o;
+  h->n = A->n;
+  h->mixed = o.vcycle_precision == BD_F32;
+  std::string err;
+  const int rc = build_hierarchy(H, o, h->H, err);
+  if (rc != BD_OK) throw Failure{rc, err};
+  h->M = (int)h->H.lv.size() - 1;
+  h->host_only = host_only;
+  if (host_only) {
+    *out = h.release();
+    return BD_OK;
+  }
+
+  h->A0 = upload<double>(h->ar, h->H.lv[0].A, nullptr, nullptr, st, kMaxBlocksSpmv);
+  if (h->mixed) build_levels<float>(h.get(), st);
+  else build_levels<double>(h.get(), st);
+  if (h->H.coarse_mode == 0) {
+    h->nM = h->H.lv.back().A.nrows;
+    h->G = upload_vec<double>(h->ar, h->H.G, st);
+  }
+  if (o.nullspace == BD_NULL_CONSTANT && weights) {
+    std::vector<double> wv(weights, weights + A->n);
+    h->w = upload_vec<double>(h->ar, wv, st);
+  }
+  alloc_solve_state(h.get(), st);
+  *out = h.release();
+  return BD_OK;
+}
+
+}  // namespace bd
+
+// ==========================================================================================
+// C ABI
+extern "C" {
+
+void bidomain_default_opts(bd_amg_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->coarsening = BD_SA;
+  o->threshold = 0.06;
+  o->square_graph_levels = 1;
+  o->prolong_smooths = 1;
+  o->coarse_eq_limit = 100;
+  o->max_levels = 25;
+  o->smoother = BD_CHEBYSHEV;
+  o->smoother_degree = 2;
+  o->cheb_lo = 0.05;
+  o->cheb_hi = 1.05;
+  o->esteig_iters = 10;
+  o->seed = 0;
+  o->vcycle_precision = BD_F64;
+  o->nullspace = BD_NULL_NONE;
+  o->stagnation_ratio = 0.9;
+  o->coarse_dense_max = 2048;
+}
+
+const char* bidomain_last_error(void) { return g_last_error.c_str(); }
+
+int bidomain_amg_setup(const bd_csr* A, const bd_amg_opts* opts, const double* null_weights, void* stream,
+                       bd_amg** out) {
+  return guarded([&] { return setup_impl(A, opts, null_weights, (hipStream_t)stream, out); });
+}
+
+int bidomain_amg_build_host(const bd_csr* A, const bd_amg_opts* opts, bd_amg** out) {
+  return guarded([&] { return setup_impl(A, opts, nullptr, nullptr, out, true); });
+}
+
+int bidomain_pcg_solve(bd_amg* h, const double* b_dev, double* x_dev, int x_is_guess, double rtol, int maxit,
+                       void* stream, bd_solve_info* info) {
+  return guarded([&] {
+    if (h && h->host_only) throw Failure{BD_E_INVALID, "host-only hierarchy"};
+    if (!h || !b_dev || !x_dev || !(rtol > 0.0) || maxit < 1) throw Failure{BD_E_INVALID, "invalid solve arguments"};
+    hipStream_t st = (hipStream_t)stream;
+    return h->mixed ? pcg<float>(h, b_dev, x_dev, x_is_guess, rtol, maxit, st, info)
+                    : pcg<double>(h, b_dev, x_dev, x_is_guess, rtol, maxit, st, info);
+  });
+}
+
+int bidomain_amg_info(const bd_amg* h, bd_amg_stats* s) {
+  return guarded([&] {
+    if (!h || !s) throw Failure{BD_E_INVALID, "null argument"};
+    std::memset(s, 0, sizeof(*s));
+    const auto& L = h->H.lv;
+    s->nlevels = (int)L.size();
+    double nnz = 0, nn = 0;
+    for (size_t k = 0; k < L.size() && k < BD_MAX_LEVELS; ++k) {
+      s->n[k] = L[k].A.nrows;
+      s->nnz[k] = L[k].A.nnz();
+      s->p_nnz[k] = L[k].P.nnz();
+      s->lambda[k] = L[k].lam;
+      nnz += (double)L[k].A.nnz();
+      nn += L[k].A.nrows;
+    }
+    s->coarse_mode = h->H.coarse_mode;
+    s->operator_complexity = nnz / (double)L[0].A.nnz();
+    s->grid_complexity = nn / (double)L[0].A.nrows;
+    s->device_bytes = h->ar.bytes;
+    return BD_OK;
+  });
+}
+
+void bidomain_amg_destroy(bd_amg* h) { delete h; }
+
+int bidomain_amg_export(const bd_amg* h, int level, int which, int32_t* rows, int32_t* cols, int64_t* nnz,
+                        int32_t* row_ptr, int32_t* col_idx, double* val) {
+  return guarded([&] {
+    if (!h || level < 0 || level >= (int)h->H.lv.size() || which < 0 || which > 2 || !rows || !cols || !nnz)
+      throw Failure{BD_E_INVALID, "invalid export arguments"};
+    const HostLevel& L = h->H.lv[level];
+    const Csr& M = which == 0 ? L.A : (which == 1 ? L.P : L.R);
+    *rows = M.nrows;
+    *cols = M.ncols;
+    *nnz = M.nnz();
+    if (row_ptr) std::copy(M.rp.begin(), M.rp.end(), row_ptr);
+    if (col_idx) std::copy(M.ci.begin(), M.ci.end(), col_idx);
+    if (val) std::copy(M.v.begin(), M.v.end(), val);
+    return BD_OK;
+  });
+}
+
+int bidomain_amg_apply(bd_amg* h, int op, int level, const void* in_dev, void* out_dev, void* stream) {
+  return guarded([&] {
+    if (!h || h->host_only || !in_dev || !out_dev || level < 0 || level > h->M)
+      throw Failure{BD_E_INVALID, "invalid apply arguments"};
+    hipStream_t st = (hipStream_t)stream;
+    auto run = [&](auto tag) {
+      using T = decltype(tag);
+      auto& L = levels<T>(h);
+      const Solve& sv = h->sv_apply;
+      const T* in = (const T*)in_dev;
+      T* out = (T*)out_dev;
+      DLevel<T>& Lk = L[level];
+      switch (op) {
+        case BD_OP_A: {
+          SpArgs<T> a = args<T>(sv); a.x = in; a.y = out;
+          launch_spmv<T, OP_Y>(Lk.A, a, st);
+          break;
+        }
+        case BD_OP_P:
+        case BD_OP_R: {
+          if (level >= h->M) throw Failure{BD_E_INVALID, "the coarsest level has no transfer operators"};
+          SpArgs<T> a = args<T>(sv); a.x = in; a.y = out;
+          launch_spmv<T, OP_Y>(op == BD_OP_P ? Lk.P : Lk.R, a, st);
+          break;
+        }
+        case BD_OP_PRESMOOTH:
+        case BD_OP_VCYCLE:
+        case BD_OP_COARSE: {
+          const int k = op == BD_OP_COARSE ? h->M : level;
+          DLevel<T>& Lx = L[k];
+          T* saved = Lx.f;
+          if (k == 0) {
+            Lx.f = (T*)in;
+          } else {
+            HIPCHK(hipMemcpyAsync(Lx.f, in, sizeof(T) * Lx.n, hipMemcpyDeviceToDevice, st));
+          }
+          if (op == BD_OP_PRESMOOTH) {
+            if (!smoothed_level(h, k)) throw Failure{BD_E_INVALID, "the coarsest level is solved directly"};
+            smooth_pre<T>(h, Lx, sv, false, st);
+          } else if (op == BD_OP_COARSE) {
+            coarse_solve<T>(h, Lx, sv, false, st);
+          } else {
+            vcycle<T>(h, k, sv, false, RedSpec{}, st);
+          }
+          HIPCHK(hipMemcpyAsync(out, Lx.x, sizeof(T) * Lx.n, hipMemcpyDeviceToDevice, st));
+          if (k == 0) Lx.f = saved;
+          break;
+        }
+        default:
+          throw Failure{BD_E_INVALID, "unknown operation"};
+      }
+      HIPCHK(hipStreamSynchronize(st));
+    };
+    if (h->mixed) run(float{}); else run(double{});
+    return BD_OK;
+  });
+}
+
+static int64_t bd_slab_nnz27(const bd_slab* s) {
+  return (int64_t)(3 * s->nx + 1) * (3 * s->ny + 1) * (3 * s->nz + 1);
+}
+
+static void check_slab(const bd_slab* s) {
+  if (!s || s->nx < 1 || s->ny < 1 || s->nz < 1 || !(s->Lx > 0) || !(s->Ly > 0) || !(s->Lz > 0) || !(s->dt > 0) ||
+      !(s->cm > 0) || !(s->sig_it > 0) || !(s->sig_il > 0) || !(s->sig_et > 0) || !(s->sig_el > 0))
+    throw Failure{BD_E_INVALID, "invalid slab description"};
+  if (bd::slab_nodes(*s) > INT32_MAX || bd_slab_nnz27(s) > INT32_MAX)
+    throw Failure{BD_E_INVALID, "slab too large for 32-bit CSR indices"};
+}
+
+int bidomain_slab_assemble(const bd_slab* s, int which, int32_t* row_ptr, int32_t* col_idx, double* val,
+                           double* mass) {
+  return guarded([&] {
+    check_slab(s);
+    if (which < BD_MAT_AI || which > BD_MAT_APAR || !row_ptr || !col_idx || !val)
+      throw Failure{BD_E_INVALID, "invalid assemble arguments"};
+    Csr A;
+    std::vector<double> m;
+    slab_lumped_mass(*s, m);
+    if (which == BD_MAT_AE) {
+      assemble_slab_stiffness(*s, s->sig_el, s->sig_et, A);
+    } else {
+      assemble_slab_stiffness(*s, s->sig_il, s->sig_it, A);
+      if (which == BD_MAT_AELL) {
+        Csr E;
+        assemble_slab_stiffness(*s, s->sig_el, s->sig_et, E);
+        for (size_t k = 0; k < A.v.size(); ++k) A.v[k] += E.v[k];
+      } else if (which == BD_MAT_APAR) {
+        for (int32_t i = 0; i < A.nrows; ++i)
+          for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+            if (A.ci[k] == i) A.v[k] += s->cm / s->dt * m[i];
+      }
+    }
+    std::copy(A.rp.begin(), A.rp.end(), row_ptr);
+    std::copy(A.ci.begin(), A.ci.end(), col_idx);
+    std::copy(A.v.begin(), A.v.end(), val);
+    if (mass) std::copy(m.begin(), m.end(), mass);
+    return BD_OK;
+  });
+}
+
+static void launch_membrane(bd_sim* S, hipStream_t st) {
+  const int G = S->Ai.G;
+  const int rpt = kBlock / G;
+  const int nb = (S->n + rpt - 1) / rpt;
+  switch (G) {
+    case 4: k_membrane_rhs<4><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, S->n); break;
+    case 8: k_membrane_rhs<8><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, S->n); break;
+    default: k_membrane_rhs<16><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, S->n); break;
+  }
+  HIPCHK(hipGetLastError());
+}
+
+static void launch_neg_spmv(bd_sim* S, const double* x, double* y, hipStream_t st) {
+  const int G = S->Ai.G;
+  const int rpt = kBlock / G;
+  const int nb = (S->n + rpt - 1) / rpt;
+  switch (G) {
+    case 4: k_neg_spmv<4><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, x, y, S->n); break;
+    case 8: k_neg_spmv<8><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, x, y, S->n); break;
+    default: k_neg_spmv<16><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, x, y, S->n); break;
+  }
+  HIPCHK(hipGetLastError());
+}
+
+int bidomain_sim_create(const bd_slab* s, const bd_amg_opts* ell, const bd_amg_opts* par, const double* v0_dev,
+                        const double* w0_dev, double rtol, void* stream, bd_sim** out) {
+  return guarded([&] {
+    check_slab(s);
+    if (!v0_dev || !out || !(rtol > 0)) throw Failure{BD_E_INVALID, "invalid simulation arguments"};
+    hipStream_t st = (hipStream_t)stream;
+    std::unique_ptr<bd_sim> S(new bd_sim());
+    S->s = *s;
+    S->n = (int)slab_nodes(*s);
+    const int n = S->n;
+    Csr Ai, Ae;
+    std::vector<double> m;
+    assemble_slab_stiffness(*s, s->sig_il, s->sig_it, Ai);
+    assemble_slab_stiffness(*s, s->sig_el, s->sig_et, Ae);
+    slab_lumped_mass(*s, m);
+    Csr Aell = Ai, Apar = Ai;
+    for (size_t k = 0; k < Ai.v.size(); ++k) Aell.v[k] += Ae.v[k];
+    for (int32_t i = 0; i < Ai.nrows; ++i)
+      for (int32_t k = Ai.rp[i]; k < Ai.rp[i + 1]; ++k)
+        if (Ai.ci[k] == i) Apar.v[k] += s->cm / s->dt * m[i];
+    bd_amg_opts oe, op;
+    bidomain_default_opts(&oe);
+    bidomain_default_opts(&op);
+    if (ell) oe = *ell;
+    if (par) op = *par;
+    oe.nullspace = BD_NULL_CONSTANT;
+    op.nullspace = BD_NULL_NONE;
+    bd_csr ce{n, Aell.nnz(), Aell.rp.data(), Aell.ci.data(), Aell.v.data()};
+    bd_csr cp{n, Apar.nnz(), Apar.rp.data(), Apar.ci.data(), Apar.v.data()};
+    setup_impl(&ce, &oe, m.data(), st, &S->hell);
+    setup_impl(&cp, &op, nullptr, st, &S->hpar);
+    S->Ai = upload<double>(S->ar, Ai, S->hell->A0.rp, S->hell->A0.ci, st, kMaxBlocksSpmv);
+    S->v = S->ar.alloc<double>(n);
+    S->ue = S->ar.alloc<double>(n);
+    S->w = S->ar.alloc<double>(n);
+    S->rhs = S->ar.alloc<double>(n);
+    S->fell = S->ar.alloc<double>(n);
+    S->m = upload_vec<double>(S->ar, m, st);
+    HIPCHK(hipMemcpyAsync(S->v, v0_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    if (w0_dev) HIPCHK(hipMemcpyAsync(S->w, w0_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    else HIPCHK(hipMemsetAsync(S->w, 0, sizeof(double) * n, st));
+    HIPCHK(hipMemsetAsync(S->ue, 0, sizeof(double) * n, st));
+    // u_e^0 from v^0 (eq. (6))
+    launch_neg_spmv(S.get(), S->v, S->fell, st);
+    bd_solve_info inf;
+    const int rc = S->hell->mixed ? pcg<float>(S->hell, S->fell, S->ue, 0, rtol, 1000, st, &inf)
+                                  : pcg<double>(S->hell, S->fell, S->ue, 0, rtol, 1000, st, &inf);
+    if (rc < 0) return rc;
+    *out = S.release();
+    return BD_OK;
+  });
+}
+
+int bidomain_step(bd_sim* S, int nsteps, double rtol, void* stream, bd_step_info* info) {
+  return guarded([&] {
+    if (!S || nsteps < 0 || !(rtol > 0)) throw Failure{BD_E_INVALID, "invalid step arguments"};
+    hipStream_t st = (hipStream_t)stream;
+    bd_step_info inf{};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int status = BD_OK;
+    for (int s = 0; s < nsteps; ++s) {
+      HIPCHK(hipEventRecord(e0, st));
+      launch_membrane(S, st);
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      inf.ms_memb += ms;
+      bd_solve_info ip, ie;
+      int rc = S->hpar->mixed ? pcg<float>(S->hpar, S->rhs, S->v, 1, rtol, 1000, st, &ip)
+                              : pcg<double>(S->hpar, S->rhs, S->v, 1, rtol, 1000, st, &ip);
+      if (rc != BD_OK) status = rc;
+      launch_neg_spmv(S, S->v, S->fell, st);
+      rc = S->hell->mixed ? pcg<float>(S->hell, S->fell, S->ue, 1, rtol, 1000, st, &ie)
+                          : pcg<double>(S->hell, S->fell, S->ue, 1, rtol, 1000, st, &ie);
+      if (rc != BD_OK && status == BD_OK) status = rc;
+      inf.steps++;
+      inf.it_par += ip.iterations;
+      inf.it_ell += ie.iterations;
+      inf.ms_par += ip.seconds * 1e3;
+      inf.ms_ell += ie.seconds * 1e3;
+      inf.rel_res_par = ip.rel_residual_true;
+      inf.rel_res_ell = ie.rel_residual_true;
+      if (status < 0) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    inf.status = status;
+    if (info) *info = inf;
+    return status;
+  });
+}
+
+int bidomain_sim_get(bd_sim* S, int field, double* out_dev, void* stream) {
+  return guarded([&] {
+    if (!S || !out_dev || field < BD_V || field > BD_W) throw Failure{BD_E_INVALID, "invalid get arguments"};
+    hipStream_t st = (hipStream_t)stream;
+    const double* src = field == BD_V ? S->v : (field == BD_UE ? S->ue : S->w);
+    HIPCHK(hipMemcpyAsync(out_dev, src, sizeof(double) * S->n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return BD_OK;
+  });
+}
+
+bd_amg* bidomain_sim_hierarchy(bd_sim* S, int which) { return S ? (which == 0 ? S->hell : S->hpar) : nullptr; }
+
+void bidomain_sim_destroy(bd_sim* S) { delete S; }
+
+void bidomain_profile_enable(int on) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  g_prof.on = on != 0;
+}
+
+void bidomain_profile_read(double* total_ms, int64_t* launches, int reset) {
+  std::lock_guard<std::mutex> g(g_prof.mu);
+  if (total_ms) *total_ms = g_prof.total_ms;
+  if (launches) *launches = g_prof.launches;
+  if (reset) {
+    g_prof.total_ms = 0.0;
+    g_prof.launches = 0;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,671 @@
+// AMG setup phase on the host (Alg. 1 of the paper; Sec. 4 and App. A for the components).
+//
+// Smoothed aggregation: strength graph from w_ij = |a_ij| / sqrt(a_ii a_jj) >= theta, greedy
+// maximal independent set (on the squared graph for the first `square_graph_levels` levels),
+// clusters formed around the MIS roots by largest weight, tentative prolongator normalised
+// per cluster (|C_j|^{-1/2} for the constant near-null vector), one Jacobi smoothing of the
+// prolongator, Galerkin coarse operator R A P with R = P^T.  Classical coarsening: strong
+// set of eq. (10), first-pass C/F splitting, direct interpolation.  The coarsest level gets
+// a dense inverse (pseudo-inverse on the complement of the constant when the operator is
+// singular).  Tie and threshold rules are spelled out where they are applied; they make the
+// hierarchy independent of the rounding of the matrix entries.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include <omp.h>
+
+#include "bd_host.hpp"
+
+namespace bd {
+
+namespace {
+constexpr double kTie = 1e-12;  // relative width of a tie / threshold band
+}
+
+// ------------------------------------------------------------------------------------------
+Csr transpose(const Csr& A) {
+  Csr T;
+  T.nrows = A.ncols;
+  T.ncols = A.nrows;
+  T.rp.assign((size_t)T.nrows + 1, 0);
+  for (int32_t c : A.ci) T.rp[c + 1]++;
+  for (int32_t i = 0; i < T.nrows; ++i) T.rp[i + 1] += T.rp[i];
+  T.ci.resize(A.ci.size());
+  T.v.resize(A.v.size());
+  std::vector<int32_t> next(T.rp.begin(), T.rp.end() - 1);
+  for (int32_t i = 0; i < A.nrows; ++i)  // rows in order, so each output row is sorted
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t pos = next[A.ci[k]]++;
+      T.ci[pos] = i;
+      T.v[pos] = A.v[k];
+    }
+  return T;
+}
+
+Csr spgemm(const Csr& A, const Csr& B) {
+  Csr C;
+  C.nrows = A.nrows;
+  C.ncols = B.ncols;
+  C.rp.assign((size_t)C.nrows + 1, 0);
+  const int nt = omp_get_max_threads();
+  std::vector<std::vector<int32_t>> mark(nt, std::vector<int32_t>());
+  // symbolic pass: row sizes
+#pragma omp parallel
+  {
+    std::vector<int32_t>& mk = mark[omp_get_thread_num()];
+    mk.assign(B.ncols, -1);
+#pragma omp for schedule(dynamic, 256)
+    for (int32_t i = 0; i < A.nrows; ++i) {
+      int32_t cnt = 0;
+      for (int32_t ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
+        const int32_t k = A.ci[ka];
+        for (int32_t kb = B.rp[k]; kb < B.rp[k + 1]; ++kb)
+          if (mk[B.ci[kb]] != i) {
+            mk[B.ci[kb]] = i;
+            ++cnt;
+          }
+      }
+      C.rp[i + 1] = cnt;
+    }
+  }
+  for (int32_t i = 0; i < C.nrows; ++i) C.rp[i + 1] += C.rp[i];
+  C.ci.resize(C.rp[C.nrows]);
+  C.v.resize(C.rp[C.nrows]);
+  // numeric pass: accumulate in the order of A's row then B's rows, then sort the columns
+#pragma omp parallel
+  {
+    std::vector<int32_t>& mk = mark[omp_get_thread_num()];
+    std::fill(mk.begin(), mk.end(), -1);
+    std::vector<double> acc(B.ncols, 0.0);
+    std::vector<int32_t> cols;
+#pragma omp for schedule(dynamic, 256)
+    for (int32_t i = 0; i < A.nrows; ++i) {
+      cols.clear();
+      for (int32_t ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
+        const int32_t k = A.ci[ka];
+        const double a = A.v[ka];
+        for (int32_t kb = B.rp[k]; kb < B.rp[k + 1]; ++kb) {
+          const int32_t j = B.ci[kb];
+          if (mk[j] != i) {
+            mk[j] = i;
+            acc[j] = a * B.v[kb];
+            cols.push_back(j);
+          } else {
+            acc[j] += a * B.v[kb];
+          }
+        }
+      }
+      std::sort(cols.begin(), cols.end());
+      int32_t pos = C.rp[i];
+      for (int32_t j : cols) {
+        C.ci[pos] = j;
+        C.v[pos] = acc[j];
+        ++pos;
+      }
+    }
+  }
+  return C;
+}
+
+std::vector<double> diagonal(const Csr& A) {
+  std::vector<double> d(A.nrows, 0.0);
+  for (int32_t i = 0; i < A.nrows; ++i)
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] == i) d[i] = A.v[k];
+  return d;
+}
+
+std::string validate(const Csr& A) {
+  if (A.nrows <= 0 || A.nrows != A.ncols) return "matrix must be square with n > 0";
+  if ((int64_t)A.rp.size() != (int64_t)A.nrows + 1 || A.rp[0] != 0) return "row_ptr must start at 0";
+  for (int32_t i = 0; i < A.nrows; ++i)
+    if (A.rp[i + 1] < A.rp[i]) return "row_ptr must be non-decreasing";
+  if ((int64_t)A.rp[A.nrows] != A.nnz()) return "row_ptr[n] must equal nnz";
+  for (int32_t i = 0; i < A.nrows; ++i) {
+    bool diag = false;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      if (A.ci[k] < 0 || A.ci[k] >= A.ncols) return "column index out of range in row " + std::to_string(i);
+      if (k > A.rp[i] && A.ci[k] <= A.ci[k - 1]) return "columns must be sorted and unique in row " + std::to_string(i);
+      if (!std::isfinite(A.v[k])) return "non-finite value in row " + std::to_string(i);
+      if (A.ci[k] == i) {
+        diag = true;
+        if (!(A.v[k] > 0.0)) return "diagonal must be positive in row " + std::to_string(i);
+      }
+    }
+    if (!diag) return "missing diagonal in row " + std::to_string(i);
+  }
+  return "";
+}
+
+// ------------------------------------------------------------------------------------------
+// Eigenvalue estimate for the Chebyshev interval and the prolongator damping.
+namespace {
+
+uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+  // output i (0-based) of SplitMix64 seeded with `seed`: the state advances by the golden
+  // gamma before each output, then the published finaliser is applied
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (diag a, off-diagonal b) by bisection on
+// the Sturm sequence count.
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int m = (int)a.size();
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {  // number of eigenvalues < x
+    int cnt = 0;
+    double q = a[0] - x;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < m; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = (a[i] - x) - b[i - 1] * b[i - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) == m) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+}  // namespace
+
+double lambda_estimate(const Csr& A, const std::vector<double>& Dinv, int iters, uint64_t seed) {
+  const int32_t n = A.nrows;
+  std::vector<double> r(n), z(n), p(n), q(n);
+  for (int32_t i = 0; i < n; ++i)
+    r[i] = 2.0 * ((double)(splitmix64_at(seed, (uint64_t)i) >> 11) * 0x1.0p-53) - 1.0;
+  double rho = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    z[i] = Dinv[i] * r[i];
+    p[i] = z[i];
+    rho += r[i] * z[i];
+  }
+  const double rho0 = rho;
+  std::vector<double> alpha, beta;
+  for (int j = 0; j < iters; ++j) {
+    double pq = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * p[A.ci[k]];
+      q[i] = s;
+      pq += p[i] * s;
+    }
+    if (!(pq > 0.0)) break;
+    const double al = rho / pq;
+    alpha.push_back(al);
+    if (j == iters - 1) break;
+    double rn = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+      r[i] -= al * q[i];
+      z[i] = Dinv[i] * r[i];
+      rn += r[i] * z[i];
+    }
+    if (!(rn > 1e-28 * rho0)) break;
+    const double be = rn / rho;
+    beta.push_back(be);
+    for (int32_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
+    rho = rn;
+  }
+  const int m = (int)alpha.size();
+  if (m == 0) {
+    double mx = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+        if (A.ci[k] == i) mx = std::max(mx, Dinv[i] * A.v[k]);
+    return mx;
+  }
+  // CG/Lanczos relation: T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1}, T_{j,j+1} = sqrt(beta_j)/alpha_j
+  std::vector<double> td(m), to(std::max(m - 1, 0));
+  for (int j = 0; j < m; ++j) {
+    td[j] = 1.0 / alpha[j] + (j > 0 ? beta[j - 1] / alpha[j - 1] : 0.0);
+    if (j + 1 < m) to[j] = std::sqrt(beta[j]) / alpha[j];
+  }
+  return tridiag_max_eig(td, to);
+}
+
+// ------------------------------------------------------------------------------------------
+// Smoothed aggregation.
+namespace {
+
+struct Graph {
+  std::vector<int32_t> rp, ci;
+  std::vector<double> w;
+};
+
+Graph sa_strength(const Csr& A, const std::vector<double>& d, double theta) {
+  Graph G;
+  const int32_t n = A.nrows;
+  G.rp.assign(n + 1, 0);
+  const double cut = theta * (1.0 - kTie);
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t c = 0;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t j = A.ci[k];
+      if (j == i || A.v[k] == 0.0) continue;
+      if (std::fabs(A.v[k]) / std::sqrt(d[i] * d[j]) >= cut) ++c;
+    }
+    G.rp[i + 1] = G.rp[i] + c;
+  }
+  G.ci.resize(G.rp[n]);
+  G.w.resize(G.rp[n]);
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t pos = G.rp[i];
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t j = A.ci[k];
+      if (j == i || A.v[k] == 0.0) continue;
+      const double w = std::fabs(A.v[k]) / std::sqrt(d[i] * d[j]);
+      if (w >= cut) {
+        G.ci[pos] = j;
+        G.w[pos] = w;
+        ++pos;
+      }
+    }
+  }
+  return G;
+}
+
+// Greedy MIS in index order; with `square`, a new root also takes its distance-2 nodes.
+std::vector<uint8_t> greedy_mis(const Graph& G, int32_t n, bool square) {
+  std::vector<uint8_t> st(n, 0);  // 0 free, 1 root, 2 taken
+  for (int32_t i = 0; i < n; ++i) {
+    if (st[i]) continue;
+    st[i] = 1;
+    for (int32_t k = G.rp[i]; k < G.rp[i + 1]; ++k) {
+      const int32_t j = G.ci[k];
+      if (st[j] == 0) st[j] = 2;
+      if (square)
+        for (int32_t l = G.rp[j]; l < G.rp[j + 1]; ++l)
+          if (st[G.ci[l]] == 0) st[G.ci[l]] = 2;
+    }
+  }
+  return st;
+}
+
+// Among the neighbours j of i accepted by `ok`, the one of largest weight; weights within the
+// tie band of the largest are equal and the lowest index wins.  -1 if none.
+template <class Ok>
+int32_t best_neighbour(const Graph& G, int32_t i, Ok ok) {
+  double best = -1.0;
+  for (int32_t k = G.rp[i]; k < G.rp[i + 1]; ++k)
+    if (ok(G.ci[k]) && G.w[k] > best) best = G.w[k];
+  if (best < 0.0) return -1;
+  int32_t pick = -1;
+  for (int32_t k = G.rp[i]; k < G.rp[i + 1]; ++k) {
+    const int32_t j = G.ci[k];
+    if (ok(j) && G.w[k] >= best * (1.0 - kTie) && (pick < 0 || j < pick)) pick = j;
+  }
+  return pick;
+}
+
+// Returns the number of aggregates; agg[i] = aggregate of node i (rank of its root).
+int32_t sa_aggregate(const Graph& G, const std::vector<uint8_t>& st, std::vector<int32_t>& agg) {
+  const int32_t n = (int32_t)st.size();
+  agg.assign(n, -1);
+  int32_t nc = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (st[i] == 1) agg[i] = nc++;
+  for (int32_t i = 0; i < n; ++i) {  // pass 1: strongly connected root of largest weight
+    if (st[i] == 1) continue;
+    const int32_t j = best_neighbour(G, i, [&](int32_t c) { return st[c] == 1; });
+    if (j >= 0) agg[i] = agg[j];
+  }
+  const std::vector<int32_t> snap(agg);
+  for (int32_t i = 0; i < n; ++i) {  // pass 2: assigned neighbour of largest weight (snapshot)
+    if (snap[i] >= 0) continue;
+    const int32_t j = best_neighbour(G, i, [&](int32_t c) { return snap[c] >= 0; });
+    if (j >= 0) agg[i] = snap[j];
+  }
+  for (int32_t i = 0; i < n; ++i)
+    if (agg[i] < 0) return -1;
+  return nc;
+}
+
+Csr sa_prolongator(const Csr& A, const std::vector<double>& Dinv, const std::vector<double>& B,
+                   const std::vector<int32_t>& agg, int32_t nc, double lam, int nsmooth,
+                   std::vector<double>& Bc) {
+  const int32_t n = A.nrows;
+  std::vector<double> norm2(nc, 0.0);
+  for (int32_t i = 0; i < n; ++i) norm2[agg[i]] += B[i] * B[i];
+  Bc.resize(nc);
+  for (int32_t c = 0; c < nc; ++c) Bc[c] = std::sqrt(norm2[c]);
+  Csr P;
+  P.nrows = n;
+  P.ncols = nc;
+  P.rp.resize(n + 1);
+  P.ci.resize(n);
+  P.v.resize(n);
+  for (int32_t i = 0; i <= n; ++i) P.rp[i] = i;
+  for (int32_t i = 0; i < n; ++i) {
+    P.ci[i] = agg[i];
+    P.v[i] = B[i] / Bc[agg[i]];
+  }
+  const double omega = 4.0 / (3.0 * lam);
+  for (int s = 0; s < nsmooth; ++s) {
+    Csr AP = spgemm(A, P);  // pattern(AP) contains pattern(P): every diagonal a_ii is stored
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) {
+      const double sc = omega * Dinv[i];
+      int32_t kp = P.rp[i];
+      for (int32_t k = AP.rp[i]; k < AP.rp[i + 1]; ++k) {
+        double pij = 0.0;
+        while (kp < P.rp[i + 1] && P.ci[kp] < AP.ci[k]) ++kp;
+        if (kp < P.rp[i + 1] && P.ci[kp] == AP.ci[k]) pij = P.v[kp];
+        AP.v[k] = pij - sc * AP.v[k];
+      }
+    }
+    P = std::move(AP);
+  }
+  return P;
+}
+
+// ------------------------------------------------------------------------------------------
+// Classical coarsening.
+Csr rs_strength(const Csr& A, double alpha) {
+  Csr S;
+  const int32_t n = A.nrows;
+  S.nrows = S.ncols = n;
+  S.rp.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    double mx = 0.0;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] != i) mx = std::max(mx, std::fabs(A.v[k]));
+    const double cut = alpha * mx * (1.0 - kTie);
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] != i && A.v[k] != 0.0 && std::fabs(A.v[k]) >= cut) {
+        S.ci.push_back(A.ci[k]);
+        S.v.push_back(1.0);
+      }
+    S.rp[i + 1] = (int32_t)S.ci.size();
+  }
+  return S;
+}
+
+// First pass: repeatedly make the undecided point of largest measure (lowest index on ties)
+// a C point; the undecided points depending on it become F points, and measures are updated.
+std::vector<uint8_t> rs_split(const Csr& S) {
+  const int32_t n = S.nrows;
+  const Csr ST = transpose(S);
+  enum : uint8_t { UND = 0, CP = 1, FP = 2 };
+  std::vector<uint8_t> st(n, UND);
+  std::vector<int32_t> lam(n);
+  for (int32_t i = 0; i < n; ++i) {
+    lam[i] = ST.rp[i + 1] - ST.rp[i];
+    if (lam[i] == 0 && S.rp[i + 1] == S.rp[i]) st[i] = FP;  // no strong connection at all
+  }
+  std::priority_queue<std::pair<int32_t, int32_t>> pq;  // (measure, -index)
+  for (int32_t i = 0; i < n; ++i)
+    if (st[i] == UND) pq.push({lam[i], -i});
+  while (!pq.empty()) {
+    const auto top = pq.top();
+    pq.pop();
+    const int32_t i = -top.second;
+    if (st[i] != UND || top.first != lam[i]) continue;
+    st[i] = CP;
+    for (int32_t k = ST.rp[i]; k < ST.rp[i + 1]; ++k) {
+      const int32_t j = ST.ci[k];
+      if (st[j] != UND) continue;
+      st[j] = FP;
+      for (int32_t l = S.rp[j]; l < S.rp[j + 1]; ++l) {
+        const int32_t m = S.ci[l];
+        if (st[m] == UND) pq.push({++lam[m], -m});
+      }
+    }
+    for (int32_t l = S.rp[i]; l < S.rp[i + 1]; ++l) {
+      const int32_t m = S.ci[l];
+      if (st[m] == UND) pq.push({--lam[m], -m});
+    }
+  }
+  return st;
+}
+
+// Direct interpolation: an F point interpolates from its strong C neighbours, scaling the
+// negative and positive couplings separately so that row sums are preserved; a sign class
+// with no interpolatory member is added to the diagonal.
+Csr rs_interpolation(const Csr& A, const Csr& S, const std::vector<uint8_t>& st) {
+  const int32_t n = A.nrows;
+  std::vector<int32_t> cidx(n, -1);
+  int32_t nc = 0;
+  for (int32_t i = 0; i < n; ++i)
+    if (st[i] == 1) cidx[i] = nc++;
+  Csr P;
+  P.nrows = n;
+  P.ncols = nc;
+  P.rp.assign(n + 1, 0);
+  std::vector<uint8_t> strong(n, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    if (st[i] == 1) {
+      P.ci.push_back(cidx[i]);
+      P.v.push_back(1.0);
+      P.rp[i + 1] = (int32_t)P.ci.size();
+      continue;
+    }
+    for (int32_t l = S.rp[i]; l < S.rp[i + 1]; ++l) strong[S.ci[l]] = 1;
+    double aii = 0.0, negN = 0.0, posN = 0.0, negP = 0.0, posP = 0.0;
+    bool any = false;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t j = A.ci[k];
+      const double a = A.v[k];
+      if (j == i) { aii = a; continue; }
+      if (a < 0) negN += a; else posN += a;
+      if (strong[j] && st[j] == 1) {
+        any = true;
+        if (a < 0) negP += a; else posP += a;
+      }
+    }
+    if (any) {
+      double abar = aii;
+      if (negP == 0.0) abar += negN;
+      if (posP == 0.0) abar += posN;
+      const double al = negP != 0.0 ? negN / negP : 0.0;
+      const double be = posP != 0.0 ? posN / posP : 0.0;
+      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int32_t j = A.ci[k];
+        if (j == i || !strong[j] || st[j] != 1) continue;
+        const double a = A.v[k];
+        P.ci.push_back(cidx[j]);
+        P.v.push_back(-(a < 0 ? al : be) * a / abar);
+      }
+    }
+    for (int32_t l = S.rp[i]; l < S.rp[i + 1]; ++l) strong[S.ci[l]] = 0;
+    P.rp[i + 1] = (int32_t)P.ci.size();
+  }
+  return P;  // columns ascend with the fine index, so rows are sorted
+}
+
+// ------------------------------------------------------------------------------------------
+// (A + A^T) / 2 on the union of the two patterns.
+Csr symmetrize(const Csr& A) {
+  const Csr T = transpose(A);
+  Csr C;
+  C.nrows = A.nrows;
+  C.ncols = A.ncols;
+  C.rp.assign(A.nrows + 1, 0);
+  for (int32_t i = 0; i < A.nrows; ++i) {
+    int32_t a = A.rp[i], b = T.rp[i];
+    while (a < A.rp[i + 1] || b < T.rp[i + 1]) {
+      const int32_t ca = a < A.rp[i + 1] ? A.ci[a] : INT32_MAX;
+      const int32_t cb = b < T.rp[i + 1] ? T.ci[b] : INT32_MAX;
+      double va = 0.0, vb = 0.0;
+      int32_t c;
+      if (ca == cb) { c = ca; va = A.v[a++]; vb = T.v[b++]; }
+      else if (ca < cb) { c = ca; va = A.v[a++]; }
+      else { c = cb; vb = T.v[b++]; }
+      C.ci.push_back(c);
+      C.v.push_back(0.5 * (va + vb));
+    }
+    C.rp[i + 1] = (int32_t)C.ci.size();
+  }
+  return C;
+}
+
+bool cholesky(std::vector<double>& K, int n) {  // in place, lower triangle, row-major
+  for (int j = 0; j < n; ++j) {
+    double s = K[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= K[(size_t)j * n + k] * K[(size_t)j * n + k];
+    if (!(s > 0.0)) return false;
+    const double d = std::sqrt(s);
+    K[(size_t)j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = K[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= K[(size_t)i * n + k] * K[(size_t)j * n + k];
+      K[(size_t)i * n + j] = t / d;
+    }
+  }
+  return true;
+}
+
+// Inverse of an SPD matrix from its Cholesky factor L: solve L L^T X = I column by column.
+std::vector<double> spd_inverse(const std::vector<double>& L, int n) {
+  std::vector<double> X((size_t)n * n, 0.0);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int c = 0; c < n; ++c) {
+    std::vector<double> y(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) t -= L[(size_t)i * n + k] * y[k];
+      y[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int k = i + 1; k < n; ++k) t -= L[(size_t)k * n + i] * y[k];
+      y[i] = t / L[(size_t)i * n + i];
+    }
+    for (int i = 0; i < n; ++i) X[(size_t)i * n + c] = y[i];
+  }
+  return X;
+}
+
+// Coarsest-level operator G: A_M^{-1}; for the singular operator, the pseudo-inverse on the
+// complement of bbar = B_M / ||B_M||, obtained as Pi K^{-1} Pi with K = A_M + abar bbar bbar^T
+// and abar = mean(diag A_M), Pi = I - bbar bbar^T.
+int coarse_operator(const HostLevel& L, bool nullspace, std::vector<double>& G, std::string& err) {
+  const int n = L.A.nrows;
+  G.assign((size_t)n * n, 0.0);
+  if (nullspace && n == 1) return BD_OK;  // b-perp = {0}: zero correction
+  std::vector<double> K((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int32_t k = L.A.rp[i]; k < L.A.rp[i + 1]; ++k) K[(size_t)i * n + L.A.ci[k]] = L.A.v[k];
+  std::vector<double> bb;
+  if (nullspace) {
+    double nb = 0.0, md = 0.0;
+    for (int i = 0; i < n; ++i) { nb += L.B[i] * L.B[i]; md += K[(size_t)i * n + i]; }
+    nb = std::sqrt(nb);
+    md /= n;
+    bb.resize(n);
+    for (int i = 0; i < n; ++i) bb[i] = L.B[i] / nb;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) K[(size_t)i * n + j] += md * bb[i] * bb[j];
+  }
+  if (!cholesky(K, n)) {
+    err = "coarsest-level operator is not positive definite";
+    return BD_E_INVALID;
+  }
+  G = spd_inverse(K, n);
+  if (nullspace) {
+    std::vector<double> u(n, 0.0);  // u = K^{-1} bbar
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) u[i] += G[(size_t)i * n + j] * bb[j];
+    double c = 0.0;
+    for (int i = 0; i < n; ++i) c += bb[i] * u[i];
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        G[(size_t)i * n + j] += -u[i] * bb[j] - bb[i] * u[j] + c * bb[i] * bb[j];
+  }
+  return BD_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::string& err) {
+  H.lv.clear();
+  HostLevel cur;
+  cur.A = A0;
+  cur.B.assign(A0.nrows, 1.0);
+  for (int k = 0;; ++k) {
+    const std::vector<double> d = diagonal(cur.A);
+    cur.Dinv.resize(d.size());
+    bool positive = true;
+    for (size_t i = 0; i < d.size(); ++i) {
+      positive = positive && d[i] > 0.0;
+      cur.Dinv[i] = 1.0 / d[i];
+    }
+    const int32_t n = cur.A.nrows;
+    const std::string bad_diag = "level " + std::to_string(k) + " has a non-positive diagonal entry";
+    if (n <= o.coarse_eq_limit || k == o.max_levels - 1 || k == BD_MAX_LEVELS - 1) {
+      // a directly solved coarsest level is never Jacobi-scaled (a one-row level of the
+      // singular operator is zero up to rounding)
+      if (!positive && n > o.coarse_dense_max) {
+        err = bad_diag;
+        return BD_E_INVALID;
+      }
+      H.lv.push_back(std::move(cur));
+      break;
+    }
+    if (!positive) {
+      err = bad_diag;
+      return BD_E_INVALID;
+    }
+    cur.lam = lambda_estimate(cur.A, cur.Dinv, o.esteig_iters, o.seed + (uint64_t)k);
+    Csr P;
+    std::vector<double> Bc;
+    int32_t nc = 0;
+    if (o.coarsening == BD_SA) {
+      const Graph G = sa_strength(cur.A, d, o.threshold);
+      const std::vector<uint8_t> st = greedy_mis(G, n, k < o.square_graph_levels);
+      std::vector<int32_t> agg;
+      nc = sa_aggregate(G, st, agg);
+      if (nc < 0) {
+        err = "aggregation left nodes unassigned";
+        return BD_E_INVALID;
+      }
+      P = sa_prolongator(cur.A, cur.Dinv, cur.B, agg, nc, cur.lam, o.prolong_smooths, Bc);
+    } else {
+      const Csr S = rs_strength(cur.A, o.threshold);
+      const std::vector<uint8_t> st = rs_split(S);
+      P = rs_interpolation(cur.A, S, st);
+      nc = P.ncols;
+      Bc.assign(nc, 1.0);
+    }
+    if (nc == 0 || (double)nc > o.stagnation_ratio * n) {
+      H.lv.push_back(std::move(cur));  // keep lam: this level may be relaxed as coarsest
+      break;
+    }
+    Csr R = transpose(P);
+    Csr Ac = symmetrize(spgemm(R, spgemm(cur.A, P)));
+    cur.P = std::move(P);
+    cur.R = std::move(R);
+    HostLevel next;
+    next.A = std::move(Ac);
+    next.B = std::move(Bc);
+    H.lv.push_back(std::move(cur));
+    cur = std::move(next);
+  }
+  HostLevel& L = H.lv.back();
+  if (L.A.nrows > o.coarse_dense_max) {
+    H.coarse_mode = 1;
+    if (!std::isfinite(L.lam))
+      L.lam = lambda_estimate(L.A, L.Dinv, o.esteig_iters, o.seed + (uint64_t)(H.lv.size() - 1));
+    H.G.clear();
+    return BD_OK;
+  }
+  H.coarse_mode = 0;
+  return coarse_operator(L, o.nullspace == BD_NULL_CONSTANT, H.G, err);
+}
+
+}  // namespace bd

@@ -1,0 +1,631 @@
+// Device kernels of the AMG-PCG solve phase for gfx950 (CDNA4, wave64).
+//
+// Everything here is bandwidth-bound streaming: CSR products with a fused epilogue (the
+// V-cycle steps of Alg. 2 and the CG product q = A p), pointwise CG vector updates, and
+// deterministic reductions.  No matrix-core (MFMA) work: nothing on this path is a dense
+// contraction (the coarsest-level matrix-vector product has at most a few thousand rows).
+//
+// Conventions:
+//  * a block has 256 threads (4 waves); a CSR row is handled by a group of G lanes (G a power
+//    of two, chosen per matrix from its mean row length), rows_per_block = 256 / G * TPB;
+//  * the block -> row-tile map is XCD-aware: the hardware deals blocks round-robin over the
+//    8 XCDs, so consecutive block ids are remapped to one contiguous row range per XCD, which
+//    keeps each XCD's L2 working on neighbouring rows (and their shared x entries);
+//  * reductions are deterministic: each block writes a partial from a fixed-order tree, and
+//    the last block to finish (integer atomic counter, no float atomics) sums the partials in
+//    a fixed order and derives the solver scalars on the device;
+//  * every solve kernel first reads the solve's `done` flag and returns at once when it is set,
+//    so iterations enqueued past convergence cost only their launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bd {
+
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;
+
+// Device scalar slots (double) and flag slots (int) of one solve.
+enum Scalar : int {
+  S_RHO = 0,      // current r^T z (or its compensated float analogue)
+  S_PQ,           // p^T A p
+  S_ALPHA,
+  S_BETA,
+  S_RNORM2,       // ||r||^2 (recursive residual)
+  S_FNORM2,       // ||b^||^2
+  S_TOL2,         // rtol^2 ||b^||^2
+  S_MU_B,         // mean of b (projection)
+  S_MU_X,         // mean of the initial guess
+  S_MU_Z,         // mean of the preconditioned residual
+  S_RTOL2,        // rtol^2 (input)
+  S_TRUE2,        // ||b^ - A x||^2 at exit
+  S_WX,           // w^T x (normalisation)
+  S_WSUM,         // sum of w
+  S_COUNT
+};
+enum Flag : int {
+  F_DONE = 0,     // 1 once converged / failed / capped
+  F_ITERS,        // completed iterations
+  F_STATUS,       // BD_* status
+  F_FIRST,        // 1 before the first direction is formed
+  F_MAXIT,
+  F_NULLSPACE,
+  F_COUNT
+};
+// Reduction counters (one per kernel family so families never share a counter).
+enum Counter : int { C_SPMV = 0, C_UPD, C_VC, C_INIT, C_TRUE, C_NORM, C_COUNT };
+
+struct Solve {
+  double* sc;          // S_COUNT scalars
+  int* fl;             // F_COUNT flags
+  unsigned* cnt;       // C_COUNT counters (zero between kernels)
+  double* part;        // block partials
+  int* host_flags;     // pinned host mirror of (done, iters, status), may be null
+  long n;              // fine-level rows
+};
+
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  // bijection of [0, nb): block b runs on XCD b % 8; XCD x gets one contiguous tile range
+  const int x = b % kXcds, idx = b / kXcds;
+  const int per = nb / kXcds, rem = nb % kXcds;
+  return x * per + (x < rem ? x : rem) + idx;
+}
+
+__device__ __forceinline__ bool solve_done(const Solve& s) {
+  return __hip_atomic_load(&s.fl[F_DONE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Coherent (L1-bypassing) load of another block's partial.
+template <typename T>
+__device__ __forceinline__ T load_coherent(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------------------
+// Reductions.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NV * 4 */) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    double t = v[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    v[k] = t;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) lds[k * 4 + wave] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) v[k] = (lds[k * 4 + 0] + lds[k * 4 + 1]) + (lds[k * 4 + 2] + lds[k * 4 + 3]);
+  __syncthreads();
+}
+
+// True in exactly one block: the last one to publish its partials.
+__device__ __forceinline__ bool arrive_last(unsigned* counter) {
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+  __syncthreads();
+  return last != 0;
+}
+
+// Fixed-order sum of NV partial arrays (stride nb) by the whole block.
+template <int NV>
+__device__ __forceinline__ void sum_partials(const double* part, int nb, double (&out)[NV], double* lds) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] += load_coherent(part + (long)k * nb + i);
+  block_sum<NV>(out, lds);
+}
+
+// Compensated float arithmetic (Ogita, Rump & Oishi, SIAM J. Sci. Comput. 26 (2005)):
+// TwoSum (Knuth) and TwoProduct with a fused multiply-add.
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+// (p, s) accumulator of Dot2: p the running sum, s the accumulated error terms.
+struct Dot2 {
+  float p = 0.f, s = 0.f;
+  __device__ __forceinline__ void add(float x, float y) {
+    float h, r, q;
+    two_prod(x, y, h, r);
+    two_sum(p, h, p, q);
+    s += q + r;
+  }
+  __device__ __forceinline__ void merge(float op, float os) {
+    float q;
+    two_sum(p, op, p, q);
+    s += os + q;
+  }
+};
+
+template <int NV>
+__device__ __forceinline__ void block_dot2(Dot2 (&v)[NV], float* lds /* NV * 8 */) {
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float op = __shfl_xor(v[k].p, off, 64), os = __shfl_xor(v[k].s, off, 64);
+      // both lanes of a pair combine in the same order so that they hold identical values
+      Dot2 a, b;
+      const bool lo = (threadIdx.x & off) == 0;
+      a.p = lo ? v[k].p : op; a.s = lo ? v[k].s : os;
+      b.p = lo ? op : v[k].p; b.s = lo ? os : v[k].s;
+      a.merge(b.p, b.s);
+      v[k] = a;
+    }
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { lds[k * 8 + wave * 2] = v[k].p; lds[k * 8 + wave * 2 + 1] = v[k].s; }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    Dot2 a;
+    a.p = lds[k * 8 + 0]; a.s = lds[k * 8 + 1];
+    for (int w = 1; w < 4; ++w) a.merge(lds[k * 8 + 2 * w], lds[k * 8 + 2 * w + 1]);
+    v[k] = a;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// CSR row product by a group of G lanes; every lane of the group returns the row sum.
+template <typename T, int G>
+__device__ __forceinline__ T row_product(const int* __restrict__ rp, const int* __restrict__ ci,
+                                         const T* __restrict__ av, const T* __restrict__ x, int row,
+                                         int lane) {
+  T s = T(0);
+  const int beg = rp[row], end = rp[row + 1];
+  for (int k = beg + lane; k < end; k += G) s += av[k] * x[ci[k]];
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+  return s;
+}
+
+// Operations fused into the CSR product (epilogue at row i, s = (A x)_i, x the product input):
+enum SpOp : int {
+  OP_Y = 0,        // y = s
+  OP_ADDY,         // y += s                                   (prolongation + correction)
+  OP_RESID,        // y = f - s                                (residual)
+  OP_RESTRICT,     // y = s; y2 = c0 dinv2 s; xs = y2 if set   (restriction + first smoothing
+                   //                                           step of the next level)
+  OP_CHEB_FIRST,   // r1 = f - s; dn = c1 x + c2 dinv r1; xs = x + dn; [r = r1; y2 = dn]
+                   //                                          (pre-smoothing from zero, step 1)
+  OP_CHEB_POST0,   // r = f - s; y2 = c0 dinv r                (post-smoothing, step 0)
+  OP_CHEB_STEP,    // r1 = r - s; dn = c1 x + c2 dinv r1; xs += [x] + dn; [r = r1; y2 = dn]
+  OP_JACOBI,       // y = x + c0 dinv (f - s)                  (Richardson-Jacobi sweep)
+  OP_CG_Q,         // y = s; partial x^T s; last block: alpha  (outer CG product q = A p)
+  OP_INIT_RESID,   // y = (b - mu_b) - s; partials |b^|^2, |y|^2 (initial residual)
+  OP_TRUE_RESID,   // partial |(b - mu_b) - s|^2               (true residual at exit)
+};
+
+// Level-0 reductions fused into the last V-cycle kernel (OP_CHEB_STEP) or run alone.
+enum VcRed : int { RED_NONE = 0, RED_F64 = 1, RED_F32 = 2 };
+
+template <typename T>
+struct SpArgs {
+  const int* rp;
+  const int* ci;
+  const T* av;
+  int nrows;
+  int tpb;           // row tiles per block
+  const T* x;        // product input (also the pointwise direction d of the Chebyshev steps)
+  T* y;              // output
+  T* y2;             // second output
+  const T* f;        // right-hand side
+  T* r;              // residual in/out
+  T* xs;             // iterate in/out
+  const T* dinv;     // 1 / diag of this matrix's level
+  const T* dinv2;    // OP_RESTRICT: 1 / diag of the next level
+  T c0, c1, c2;
+  int add_d;         // OP_CHEB_STEP: also add x_i (the deferred step 0 of post-smoothing)
+  int store_rd;      // OP_CHEB_FIRST / OP_CHEB_STEP: store r1 into r and dn into y2
+  Solve sv;
+  int red;           // VcRed (OP_CHEB_STEP only)
+  const double* b;   // OP_INIT_RESID / OP_TRUE_RESID: the caller's right-hand side
+  const double* r64;     // RED_F64: the CG residual (level-0 right-hand side)
+  const float* r32;      // RED_F32: current level-0 right-hand side
+  const float* r32_old;  // RED_F32: previous level-0 right-hand side
+};
+
+template <typename T>
+struct VcAcc {
+  double acc[3] = {0.0, 0.0, 0.0};
+  Dot2 dd[2];
+  __device__ __forceinline__ void add(int red, double z64, float z32, int row, const SpArgs<T>& a) {
+    if (red == RED_F64) {
+      const double rr = a.r64[row];
+      acc[0] += z64;
+      acc[1] += rr * z64;
+      acc[2] += rr;
+    } else if (red == RED_F32) {
+      dd[0].add(z32, a.r32[row]);
+      dd[1].add(z32, a.r32_old[row]);
+      acc[0] += (double)z32;
+    }
+  }
+};
+
+template <typename T>
+__device__ void vc_finish(VcAcc<T>& v, int red, const Solve& sv, int nb, double* lds, float* lds32);
+
+template <typename T, int G, int OP>
+__global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
+  if (solve_done(a.sv)) return;
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  constexpr int RPT = kBlock / G;  // rows per tile
+  const int nb = gridDim.x;
+  const int tile0 = xcd_tile(blockIdx.x, nb) * a.tpb;
+  const int grp = threadIdx.x / G, lane = threadIdx.x % G;
+
+  double acc[3] = {0.0, 0.0, 0.0};
+  VcAcc<T> vc;
+  for (int t = 0; t < a.tpb; ++t) {
+    const int row = (tile0 + t) * RPT + grp;
+    if (row >= a.nrows) break;
+    const T s = row_product<T, G>(a.rp, a.ci, a.av, a.x, row, lane);
+    if (lane != 0) continue;
+    if constexpr (OP == OP_Y) {
+      a.y[row] = s;
+    } else if constexpr (OP == OP_ADDY) {
+      a.y[row] += s;
+    } else if constexpr (OP == OP_RESID) {
+      a.y[row] = a.f[row] - s;
+    } else if constexpr (OP == OP_RESTRICT) {
+      a.y[row] = s;
+      const T d = a.c0 * a.dinv2[row] * s;
+      a.y2[row] = d;
+      if (a.xs) a.xs[row] = d;
+    } else if constexpr (OP == OP_CHEB_FIRST) {
+      const T r1 = a.f[row] - s;
+      const T d = a.x[row];
+      const T dn = a.c1 * d + a.c2 * a.dinv[row] * r1;
+      a.xs[row] = d + dn;
+      if (a.store_rd) { a.r[row] = r1; a.y2[row] = dn; }
+    } else if constexpr (OP == OP_CHEB_POST0) {
+      const T r0 = a.f[row] - s;
+      a.r[row] = r0;
+      a.y2[row] = a.c0 * a.dinv[row] * r0;
+    } else if constexpr (OP == OP_CHEB_STEP) {
+      const T r1 = a.r[row] - s;
+      const T d = a.x[row];
+      const T dn = a.c1 * d + a.c2 * a.dinv[row] * r1;
+      const T xn = a.xs[row] + (a.add_d ? d + dn : dn);
+      a.xs[row] = xn;
+      if (a.store_rd) { a.r[row] = r1; a.y2[row] = dn; }
+      vc.add(a.red, (double)xn, (float)xn, row, a);
+    } else if constexpr (OP == OP_JACOBI) {
+      a.y[row] = a.x[row] + a.c0 * a.dinv[row] * (a.f[row] - s);
+    } else if constexpr (OP == OP_CG_Q) {
+      a.y[row] = s;
+      acc[0] += (double)a.x[row] * (double)s;
+    } else if constexpr (OP == OP_INIT_RESID) {
+      const double bh = a.b[row] - a.sv.sc[S_MU_B];
+      const double rr = bh - (double)s;
+      a.y[row] = (T)rr;
+      acc[0] += bh * bh;
+      acc[1] += rr * rr;
+    } else if constexpr (OP == OP_TRUE_RESID) {
+      const double rr = (a.b[row] - a.sv.sc[S_MU_B]) - (double)s;
+      acc[0] += rr * rr;
+    }
+  }
+
+  // ---- reductions and device-side scalar updates
+  if constexpr (OP == OP_CG_Q) {
+    block_sum<1>(*reinterpret_cast<double(*)[1]>(acc), lds);
+    if (threadIdx.x == 0) a.sv.part[blockIdx.x] = acc[0];
+    if (arrive_last(&a.sv.cnt[C_SPMV])) {
+      double tot[1];
+      sum_partials<1>(a.sv.part, nb, tot, lds);
+      if (threadIdx.x == 0) {
+        const double pq = tot[0];
+        a.sv.sc[S_PQ] = pq;
+        if (!(pq > 0.0) || !isfinite(pq)) {
+          a.sv.fl[F_STATUS] = isfinite(pq) ? -4 : -5;
+          a.sv.fl[F_DONE] = 1;
+        } else {
+          a.sv.sc[S_ALPHA] = a.sv.sc[S_RHO] / pq;
+        }
+        a.sv.cnt[C_SPMV] = 0;
+      }
+    }
+  } else if constexpr (OP == OP_INIT_RESID) {
+    block_sum<2>(*reinterpret_cast<double(*)[2]>(acc), lds);
+    if (threadIdx.x == 0) { a.sv.part[blockIdx.x] = acc[0]; a.sv.part[nb + blockIdx.x] = acc[1]; }
+    if (arrive_last(&a.sv.cnt[C_INIT])) {
+      double tot[2];
+      sum_partials<2>(a.sv.part, nb, tot, lds);
+      if (threadIdx.x == 0) {
+        a.sv.sc[S_FNORM2] = tot[0];
+        a.sv.sc[S_RNORM2] = tot[1];
+        const double tol2 = a.sv.sc[S_RTOL2] * tot[0];
+        a.sv.sc[S_TOL2] = tol2;
+        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+          a.sv.fl[F_STATUS] = -5;
+          a.sv.fl[F_DONE] = 1;
+        } else if (tot[0] == 0.0 || tot[1] <= tol2) {
+          a.sv.fl[F_DONE] = 1;
+        }
+        a.sv.cnt[C_INIT] = 0;
+      }
+    }
+  } else if constexpr (OP == OP_TRUE_RESID) {
+    block_sum<1>(*reinterpret_cast<double(*)[1]>(acc), lds);
+    if (threadIdx.x == 0) a.sv.part[blockIdx.x] = acc[0];
+    if (arrive_last(&a.sv.cnt[C_TRUE])) {
+      double tot[1];
+      sum_partials<1>(a.sv.part, nb, tot, lds);
+      if (threadIdx.x == 0) {
+        a.sv.sc[S_TRUE2] = tot[0];
+        a.sv.cnt[C_TRUE] = 0;
+      }
+    }
+  } else if constexpr (OP == OP_CHEB_STEP) {
+    if (a.red != RED_NONE) vc_finish<T>(vc, a.red, a.sv, nb, lds, lds32);
+  }
+}
+
+// Block partials of the level-0 reductions, then (last block) the CG scalars:
+// mu_z = 1^T z / n (projection), rho = r^T (z - mu_z 1) and beta = rho / rho_old (RED_F64);
+// rho = Dot2(z32, r32), beta = (rho - Dot2(z32, r32_old)) / rho_old (RED_F32, flexible CG).
+template <typename T>
+__device__ void vc_finish(VcAcc<T>& v, int red, const Solve& sv, int nb, double* lds, float* lds32) {
+  if (red == RED_F64) {
+    block_sum<3>(v.acc, lds);
+    if (threadIdx.x == 0) {
+      sv.part[blockIdx.x] = v.acc[0];
+      sv.part[nb + blockIdx.x] = v.acc[1];
+      sv.part[2 * nb + blockIdx.x] = v.acc[2];
+    }
+  } else {
+    block_dot2<2>(v.dd, lds32);
+    block_sum<1>(*reinterpret_cast<double(*)[1]>(v.acc), lds);
+    if (threadIdx.x == 0) {
+      float* pf = reinterpret_cast<float*>(sv.part + nb);
+      pf[4 * blockIdx.x + 0] = v.dd[0].p;
+      pf[4 * blockIdx.x + 1] = v.dd[0].s;
+      pf[4 * blockIdx.x + 2] = v.dd[1].p;
+      pf[4 * blockIdx.x + 3] = v.dd[1].s;
+      sv.part[blockIdx.x] = v.acc[0];
+    }
+  }
+  if (!arrive_last(&sv.cnt[C_VC])) return;
+  double sz, rz, num;
+  if (red == RED_F64) {
+    double tot[3];
+    sum_partials<3>(sv.part, nb, tot, lds);
+    const double mu = sv.fl[F_NULLSPACE] ? tot[0] / (double)sv.n : 0.0;
+    sz = tot[0];
+    rz = tot[1] - mu * tot[2];
+    num = rz;
+  } else {
+    double tot[1];
+    sum_partials<1>(sv.part, nb, tot, lds);
+    sz = tot[0];
+    Dot2 c[2];
+    const float* pf = reinterpret_cast<const float*>(sv.part + nb);
+    for (int i = threadIdx.x; i < nb; i += kBlock) {  // fixed order per thread, then a fixed tree
+      c[0].merge(load_coherent(pf + 4 * i + 0), load_coherent(pf + 4 * i + 1));
+      c[1].merge(load_coherent(pf + 4 * i + 2), load_coherent(pf + 4 * i + 3));
+    }
+    block_dot2<2>(c, lds32);
+    rz = (double)c[0].p + (double)c[0].s;
+    num = rz - ((double)c[1].p + (double)c[1].s);
+  }
+  if (threadIdx.x == 0) {
+    sv.sc[S_MU_Z] = sv.fl[F_NULLSPACE] ? sz / (double)sv.n : 0.0;
+    const double rho_old = sv.sc[S_RHO];
+    sv.sc[S_BETA] = sv.fl[F_FIRST] ? 0.0 : num / rho_old;
+    sv.sc[S_RHO] = rz;
+    if (!(rz > 0.0) || !isfinite(rz)) {
+      sv.fl[F_STATUS] = isfinite(rz) ? -4 : -5;
+      sv.fl[F_DONE] = 1;
+    }
+    sv.cnt[C_VC] = 0;
+  }
+}
+
+// The level-0 reductions on their own, for V-cycles whose last kernel is not a fused
+// Chebyshev step (single-level hierarchies, Jacobi smoothing).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_vc_reduce(SpArgs<T> a, const T* __restrict__ z) {
+  if (solve_done(a.sv)) return;
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  VcAcc<T> vc;
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < a.nrows; i += (long)gridDim.x * kBlock)
+    vc.add(a.red, (double)z[i], (float)z[i], (int)i, a);
+  vc_finish<T>(vc, a.red, a.sv, gridDim.x, lds, lds32);
+}
+
+// ---------------------------------------------------------------------------------------
+// Pointwise kernels.
+__device__ __forceinline__ long gtid() { return (long)blockIdx.x * kBlock + threadIdx.x; }
+
+// x += alpha p; r -= alpha q; ||r||^2 -> convergence test.  Optionally writes the level-0
+// right-hand side of the float V-cycle (r32 = fl32(r)) and the first pre-smoothing step of
+// level 0 (d0 = c0 dinv0 f0; also x0 = d0 when x0 is given).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(Solve sv, double* __restrict__ x, double* __restrict__ r,
+                                                      const double* __restrict__ p, const double* __restrict__ q,
+                                                      float* __restrict__ r32, const T* __restrict__ dinv0,
+                                                      T* __restrict__ d0, T* __restrict__ x0, T c0, long n) {
+  if (solve_done(sv)) return;
+  __shared__ double lds[4];
+  const double alpha = sv.sc[S_ALPHA];
+  double acc[1] = {0.0};
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) {
+    x[i] += alpha * p[i];
+    const double rn = r[i] - alpha * q[i];
+    r[i] = rn;
+    acc[0] += rn * rn;
+    T f0;
+    if (r32) { const float rf = (float)rn; r32[i] = rf; f0 = (T)rf; } else { f0 = (T)rn; }
+    if (d0) {
+      const T d = c0 * dinv0[i] * f0;
+      d0[i] = d;
+      if (x0) x0[i] = d;
+    }
+  }
+  block_sum<1>(acc, lds);
+  if (threadIdx.x == 0) sv.part[blockIdx.x] = acc[0];
+  if (arrive_last(&sv.cnt[C_UPD])) {
+    double tot[1];
+    sum_partials<1>(sv.part, gridDim.x, tot, lds);
+    if (threadIdx.x == 0) {
+      const double r2 = tot[0];
+      sv.sc[S_RNORM2] = r2;
+      const int it = sv.fl[F_ITERS] + 1;
+      sv.fl[F_ITERS] = it;
+      int done = 0;
+      if (!isfinite(r2)) { sv.fl[F_STATUS] = -5; done = 1; }
+      else if (r2 <= sv.sc[S_TOL2]) { done = 1; }
+      else if (it >= sv.fl[F_MAXIT]) { sv.fl[F_STATUS] = 1; done = 1; }
+      if (done) sv.fl[F_DONE] = 1;
+      if (sv.host_flags) {
+        __hip_atomic_store(&sv.host_flags[1], it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&sv.host_flags[0], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+      sv.cnt[C_UPD] = 0;
+    }
+  }
+}
+
+// p = (z - mu_z) + beta p   (p = z - mu_z for the first direction).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_direction(Solve sv, double* __restrict__ p, const T* __restrict__ z, long n) {
+  if (solve_done(sv)) return;
+  const double mu = sv.sc[S_MU_Z], beta = sv.sc[S_BETA];
+  const int first = sv.fl[F_FIRST];
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) {
+    const double zi = (double)z[i] - mu;
+    p[i] = first ? zi : zi + beta * p[i];
+  }
+}
+
+// Marks the first direction as formed (a separate launch, so that every block of
+// k_cg_direction has read the flag before it changes).
+__global__ void k_clear_first(Solve sv) {
+  if (threadIdx.x == 0) sv.fl[F_FIRST] = 0;
+}
+
+// d = c0 dinv f, and x = d when x is given (first smoothing step from a zero guess, when it
+// is not fused into the kernel that produced f).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cheb_pre0(Solve sv, const T* __restrict__ f, const T* __restrict__ dinv,
+                                                      T* __restrict__ d, T* __restrict__ x, T c0, long n) {
+  if (solve_done(sv)) return;
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) {
+    const T v = c0 * dinv[i] * f[i];
+    d[i] = v;
+    if (x) x[i] = v;
+  }
+}
+
+// x += d   (degree-1 post-smoothing completion); x = d when `assign`.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_add(Solve sv, T* __restrict__ x, const T* __restrict__ d, int assign, long n) {
+  if (solve_done(sv)) return;
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) x[i] = assign ? d[i] : x[i] + d[i];
+}
+
+// Coarsest level: x = G f with the dense float64 operator G (one wave per row).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv(Solve sv, const double* __restrict__ G, const T* __restrict__ f,
+                                                        T* __restrict__ x, int n) {
+  if (solve_done(sv)) return;
+  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += G[(long)row * n + j] * (double)f[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) x[row] = (T)s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Setup / exit kernels of a solve.
+// Sums of b (and of the initial guess) -> means for the projection.
+__global__ __launch_bounds__(kBlock) void k_init_means(Solve sv, const double* __restrict__ b, const double* __restrict__ x,
+                                                       long n) {
+  __shared__ double lds[8];
+  double acc[2] = {0.0, 0.0};
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) {
+    acc[0] += b[i];
+    if (x) acc[1] += x[i];
+  }
+  block_sum<2>(acc, lds);
+  const int nb = gridDim.x;
+  if (threadIdx.x == 0) { sv.part[blockIdx.x] = acc[0]; sv.part[nb + blockIdx.x] = acc[1]; }
+  if (arrive_last(&sv.cnt[C_INIT])) {
+    double tot[2];
+    sum_partials<2>(sv.part, nb, tot, lds);
+    if (threadIdx.x == 0) {
+      const bool ns = sv.fl[F_NULLSPACE] != 0;
+      sv.sc[S_MU_B] = ns ? tot[0] / (double)n : 0.0;
+      sv.sc[S_MU_X] = ns ? tot[1] / (double)n : 0.0;
+      sv.cnt[C_INIT] = 0;
+    }
+  }
+}
+
+// x = x - mu_x (guess) or 0; with no guess also r = b - mu_b and the norms of b^.
+__global__ __launch_bounds__(kBlock) void k_init_guess(Solve sv, double* __restrict__ x, int guess, long n) {
+  const double mu = sv.sc[S_MU_X];
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) x[i] = guess ? x[i] - mu : 0.0;
+}
+
+// Weighted normalisation x -= (w^T x / sum w) 1 : reduction, then update.
+__global__ __launch_bounds__(kBlock) void k_norm_sums(Solve sv, const double* __restrict__ w, const double* __restrict__ x,
+                                                      long n) {
+  __shared__ double lds[8];
+  double acc[2] = {0.0, 0.0};
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) {
+    const double wi = w ? w[i] : 1.0;
+    acc[0] += wi * x[i];
+    acc[1] += wi;
+  }
+  block_sum<2>(acc, lds);
+  const int nb = gridDim.x;
+  if (threadIdx.x == 0) { sv.part[blockIdx.x] = acc[0]; sv.part[nb + blockIdx.x] = acc[1]; }
+  if (arrive_last(&sv.cnt[C_NORM])) {
+    double tot[2];
+    sum_partials<2>(sv.part, nb, tot, lds);
+    if (threadIdx.x == 0) {
+      sv.sc[S_WX] = tot[0];
+      sv.sc[S_WSUM] = tot[1];
+      sv.cnt[C_NORM] = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm_apply(Solve sv, double* __restrict__ x, long n) {
+  const double s = sv.sc[S_WX] / sv.sc[S_WSUM];
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) x[i] -= s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Vector utilities.
+template <typename S, typename D>
+__global__ __launch_bounds__(kBlock) void k_convert(const S* __restrict__ s, D* __restrict__ d, long n) {
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) d[i] = (D)s[i];
+}
+
+}  // namespace bd

@@ -1,0 +1,244 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Bars (float64 path): every V-cycle operation on every level within 1e-12 (relative, max norm)
+of the oracle's operation on the oracle's own hierarchy; solves at rtol 1e-8 with true relative
+residual <= 1e-8 (recomputed here with the oracle's matrix) and relative error <= 1e-6 against
+the oracle's rtol-1e-12 solution; iteration counts equal to the oracle's within one.
+Mixed form: the same residual bar and error <= 1e-6; iterations within two of the oracle's
+float32 V-cycle.
+"""
+import numpy as np
+import pytest
+
+import bidomain_cases as bc
+from oracle import amg, bidomain, fem, krylov
+
+pytestmark = pytest.mark.gpu
+
+lib = pytest.importorskip("paper_2311_13914_amd")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def dev(torch, a, dtype=None):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = {
+    "C1": lambda: bc.config_case("C1"),
+    "ragged": lambda: bc.make_case(37, 29, 13, seed=7),   # several tiles and a ragged tail
+}
+
+
+def _problem(name):
+    c = CASES[name]()
+    ops = fem.assemble_operators(c)
+    f = -(ops["Ai"] @ bc.nodal_v0(c))
+    return c, ops, f
+
+
+def _relerr(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_vcycle_operations_match_oracle(torch, name):
+    c, ops, f = _problem(name)
+    A = ops["Aell"]
+    h_or = amg.setup(A, amg.AMGOptions(nullspace=True))
+    print(f"[gpu] case={name} n={c.n} levels={h_or.nlevels}", flush=True)
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1), ops["m"])
+    try:
+        info = lib.bidomain_amg_info(h)
+        assert info["n"] == [lv.A.shape[0] for lv in h_or.levels]
+        rng = np.random.default_rng(11)
+        for k, lv in enumerate(h_or.levels):
+            n = lv.A.shape[0]
+            x = rng.uniform(-1, 1, n)
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+            lib.bidomain_amg_apply(h, lib.BD_OP_A, k, dev(torch, x), out)
+            assert _relerr(host(out), lv.A @ x) <= 1e-12, f"A_{k}"
+            if lv.P is not None:
+                nc = lv.P.shape[1]
+                e = rng.uniform(-1, 1, nc)
+                out = torch.empty(n, dtype=torch.float64, device="cuda")
+                lib.bidomain_amg_apply(h, lib.BD_OP_P, k, dev(torch, e), out)
+                assert _relerr(host(out), lv.P @ e) <= 1e-12, f"P_{k}"
+                outc = torch.empty(nc, dtype=torch.float64, device="cuda")
+                lib.bidomain_amg_apply(h, lib.BD_OP_R, k, dev(torch, x), outc)
+                assert _relerr(host(outc), lv.R @ x) <= 1e-12, f"R_{k}"
+                out = torch.empty(n, dtype=torch.float64, device="cuda")
+                lib.bidomain_amg_apply(h, lib.BD_OP_PRESMOOTH, k, dev(torch, x), out)
+                assert _relerr(host(out), krylov.smooth(h_or, k, x, None)) <= 1e-12, f"S_{k}"
+                fk = x - x.mean()
+                out = torch.empty(n, dtype=torch.float64, device="cuda")
+                lib.bidomain_amg_apply(h, lib.BD_OP_VCYCLE, k, dev(torch, fk), out)
+                assert _relerr(host(out), krylov.vcycle(h_or, fk, k)) <= 1e-10, f"V_{k}"
+        M = h_or.levels[-1]
+        fM = rng.uniform(-1, 1, M.A.shape[0])
+        fM -= fM.mean()
+        out = torch.empty(M.A.shape[0], dtype=torch.float64, device="cuda")
+        lib.bidomain_amg_apply(h, lib.BD_OP_COARSE, 0, dev(torch, fM), out)
+        assert _relerr(host(out), krylov.coarse_solve(h_or, fM)) <= 1e-10
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+def _check_solution(A, f, x, m, x_ref, rtol=1e-8, err=1e-6, nullspace=True):
+    fh = f - f.mean() if nullspace else f
+    assert np.linalg.norm(fh - A @ x) <= rtol * np.linalg.norm(fh) * (1 + 1e-6)
+    if nullspace:
+        assert abs(m @ x) <= 1e-12 * np.abs(x).max() * m.sum()
+    assert np.linalg.norm(x - x_ref) <= err * np.linalg.norm(x_ref)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_elliptic_solve_matches_oracle(torch, name, precision):
+    c, ops, f = _problem(name)
+    A, m = ops["Aell"], ops["m"]
+    h_or = amg.setup(A, amg.AMGOptions(nullspace=True))
+    ref = krylov.amg_pcg(A, f, h_or, rtol=1e-12, m=m)
+    or8 = (krylov.amg_pcg if precision == "f64" else krylov.amg_fcg_mixed)(A, f, h_or, rtol=1e-8, m=m)
+    print(f"[gpu] case={name} precision={precision} oracle_its={or8.iterations}", flush=True)
+    opts = lib.bidomain_default_opts(nullspace=1, vcycle_precision=lib.BD_F64 if precision == "f64" else lib.BD_F32)
+    h = lib.bidomain_amg_setup(A, opts, m)
+    try:
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-8, 200)
+        assert rc == lib.BD_OK, info
+        assert info["rel_residual_true"] <= 1e-8
+        xs = host(x)
+        _check_solution(A, f, xs, m, ref.x)
+        assert abs(info["iterations"] - or8.iterations) <= (1 if precision == "f64" else 2)
+        # a second solve is bitwise identical (deterministic reductions)
+        x2 = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+        rc2, info2 = lib.bidomain_pcg_solve(h, dev(torch, f), x2, False, 1e-8, 200)
+        assert info2["iterations"] == info["iterations"]
+        assert np.array_equal(host(x2), xs)
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+@pytest.mark.parametrize("dims", [(24, 24, 12), (48, 48, 24)])
+def test_parabolic_solve_matches_oracle(torch, dims):
+    c = bc.make_case(*dims, seed=5)
+    ops = fem.assemble_operators(c)
+    A = ops["Apar"]
+    f = A @ bc.nodal_v0(c) + 0.1 * ops["m"] * bc.random_vector(c.n, 2)
+    h_or = amg.setup(A, amg.AMGOptions())
+    ref = krylov.amg_pcg(A, f, h_or, rtol=1e-12)
+    or8 = krylov.amg_pcg(A, f, h_or, rtol=1e-8)
+    print(f"[gpu] parabolic dims={dims} levels={h_or.nlevels} oracle_its={or8.iterations}", flush=True)
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts())
+    try:
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-8, 200)
+        assert rc == lib.BD_OK and info["rel_residual_true"] <= 1e-8
+        _check_solution(A, f, host(x), None, ref.x, nullspace=False)
+        assert abs(info["iterations"] - or8.iterations) <= 1
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+def test_classical_hierarchy_solve(torch):
+    c, ops, f = _problem("ragged")
+    A, m = ops["Aell"], ops["m"]
+    h_or = amg.setup(A, amg.AMGOptions(coarsening="rs", threshold=0.5, nullspace=True))
+    ref = krylov.amg_pcg(A, f, h_or, rtol=1e-12, m=m)
+    or8 = krylov.amg_pcg(A, f, h_or, rtol=1e-8, m=m)
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, coarsening=lib.BD_RS, threshold=0.5), m)
+    try:
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-8, 200)
+        assert rc == lib.BD_OK
+        _check_solution(A, f, host(x), m, ref.x)
+        assert abs(info["iterations"] - or8.iterations) <= 1
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+def test_edge_cases(torch):
+    c, ops, f = _problem("C1")
+    A, m = ops["Aell"], ops["m"]
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1), m)
+    try:
+        x = torch.full((c.n,), 3.0, dtype=torch.float64, device="cuda")
+        # zero right-hand side: x = 0, no iteration
+        rc, info = lib.bidomain_pcg_solve(h, torch.zeros(c.n, dtype=torch.float64, device="cuda"), x, True)
+        assert rc == lib.BD_OK and info["iterations"] == 0 and float(x.abs().max()) == 0.0
+        # a constant right-hand side lies in the kernel: projected away, x = 0
+        rc, info = lib.bidomain_pcg_solve(h, torch.ones(c.n, dtype=torch.float64, device="cuda"), x, False)
+        assert rc == lib.BD_OK and info["iterations"] == 0
+        # warm start at the solution: converged before the first iteration
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-10)
+        rc, info2 = lib.bidomain_pcg_solve(h, dev(torch, f), x, True, 1e-8)
+        assert rc == lib.BD_OK and info2["iterations"] == 0
+        # iteration cap
+        x.zero_()
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-12, 1)
+        assert rc == lib.BD_E_NOT_CONVERGED and info["iterations"] == 1
+        # non-finite input
+        bad = f.copy()
+        bad[5] = np.nan
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, bad), x, False)
+        assert rc == lib.BD_E_NONFINITE
+        # wrong sizes are refused before any launch
+        with pytest.raises(ValueError):
+            lib.bidomain_pcg_solve(h, torch.zeros(c.n - 1, dtype=torch.float64, device="cuda"), x, False)
+        # and the handle still solves correctly afterwards
+        x.zero_()
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False)
+        assert rc == lib.BD_OK and info["rel_residual_true"] <= 1e-8
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 1), (3, 3, 2), (4, 4, 2)])
+def test_tiny_meshes(torch, dims):
+    c = bc.make_case(*dims, seed=3)
+    ops = fem.assemble_operators(c)
+    A, m = ops["Aell"], ops["m"]
+    f = -(ops["Ai"] @ bc.nodal_v0(c)) + 1e-3 * bc.random_vector(c.n, 1)
+    x_ref = np.linalg.pinv(A.toarray()) @ (f - f.mean())
+    x_ref -= (m @ x_ref) / m.sum()
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, coarse_eq_limit=4), m)
+    try:
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-12, 100)
+        assert rc == lib.BD_OK
+        assert np.linalg.norm(host(x) - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_time_steps_match_oracle(torch, mixed):
+    c = bc.make_case(24, 24, 12, seed=2)
+    v0 = bc.nodal_v0(c)
+    sim_or = bidomain.create(c, v0, rtol=1e-12)
+    prec = lib.BD_F32 if mixed else lib.BD_F64
+    sim = lib.bidomain_sim_create(c, dev(torch, v0), rtol=1e-10,
+                                  ell_opts=lib.bidomain_default_opts(vcycle_precision=prec),
+                                  par_opts=lib.bidomain_default_opts(vcycle_precision=prec))
+    try:
+        out = torch.empty(c.n, dtype=torch.float64, device="cuda")
+        for s in range(4):
+            bidomain.step(sim_or)
+            rc, info = lib.bidomain_step(sim, 1, 1e-10)
+            assert rc == lib.BD_OK, info
+            for field, ref in ((lib.BD_V, sim_or.v), (lib.BD_UE, sim_or.ue), (lib.BD_W, sim_or.w)):
+                lib.bidomain_sim_get(sim, field, out)
+                err = np.linalg.norm(host(out) - ref) / np.linalg.norm(ref)
+                assert err <= 1e-6, (s, field, err)
+    finally:
+        lib.bidomain_sim_destroy(sim)
