@@ -1,0 +1,183 @@
+#!/usr/bin/env python3
+"""Benchmark: decoupled Bidomain time stepping on one MI355X, float64 AMG-PCG.
+
+Workload (default): the 1 x 1 x 0.5 cm slab at 128 x 128 x 64 Q1 elements (1,081,665 nodes,
+28.6 M nonzeros), rotating axisymmetric fibers, seeded ellipsoidal plateau; each step is one
+Aliev-Panfilov membrane update, one parabolic solve and one elliptic solve (eqs. (4)-(7) of
+the paper), both AMG-preconditioned CG to rtol 1e-8 with the hierarchies built once.
+
+Metric: elliptic PCG-AMG DOF*iters/s = n * (elliptic iterations) / (elliptic solve time), summed
+over the timed steps; solve times come from HIP events on the solve stream.  The JSON line also
+carries the roofline of the dominant fine-level kernel (the outer CG product q = A p, timed with
+HIP events around each launch) and the CPU oracle timed on a bounded sample of the same solve.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_outer_spmv_c2.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_13914_amd", "csrc", f) for f in ("kernels.hpp", "device.hip")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def spmv_bytes(n: int, nnz: int, s: int = 8) -> int:
+    """Algorithmic bytes of y = A x in CSR: values + column indices + row offsets, x read once,
+    y written once (the p^T q partials are negligible)."""
+    return nnz * (s + 4) + n * (4 + 2 * s)
+
+
+def traffic_from_profile(n, nnz):
+    """Measured HBM bytes per launch of the outer product, from the committed rocprofv3 counter
+    summary -- only while the kernel sources are the ones that were profiled."""
+    if not os.path.exists(PMC_FILE):
+        return None
+    rec = json.load(open(PMC_FILE))
+    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("n") != n or rec.get("nnz") != nnz:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(case, iters: int):
+    """The CPU oracle on a bounded sample of the same elliptic solve: assembly and setup are run
+    (untimed), then `iters` AMG-PCG iterations are timed from the zero guess."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import amg, fem, krylov
+    import bidomain_cases as bc
+
+    with threadpool_limits(limits=1):
+        ops = fem.assemble_operators(case)
+        A = ops["Aell"]
+        f = -(ops["Ai"] @ bc.nodal_v0(case))
+        t = time.perf_counter()
+        h = amg.setup(A, amg.AMGOptions(nullspace=True))
+        t_setup = time.perf_counter() - t
+        t = time.perf_counter()
+        res = krylov.amg_pcg(A, f, h, rtol=1e-8, maxit=iters, m=ops["m"])
+        dt = time.perf_counter() - t
+    return dict(value=case.n * res.iterations / dt, unit="DOF*iters/s", cores=1, kind="oracle",
+                sample=f"{res.iterations} AMG-PCG iterations of the elliptic solve on the same "
+                       f"{case.nx}x{case.ny}x{case.nz} slab from a zero guess (float64 numpy/scipy, "
+                       f"{dt:.1f} s timed; oracle setup {t_setup:.1f} s untimed)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--mixed", action="store_true", help="float32 V-cycle inside float64 flexible CG")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import bidomain_cases as bc
+    import paper_2311_13914_amd as lib
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    case = bc.config_case(args.workload)
+    n, nnz = case.n, case.nnz27
+    prec = lib.BD_F32 if args.mixed else lib.BD_F64
+    opts_e = lib.bidomain_default_opts(vcycle_precision=prec)
+    opts_p = lib.bidomain_default_opts(vcycle_precision=prec)
+    v0 = torch.tensor(bc.nodal_v0(case), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    t = time.perf_counter()
+    sim = lib.bidomain_sim_create(case, v0, rtol=args.rtol, ell_opts=opts_e, par_opts=opts_p, stream=stream)
+    setup_s = time.perf_counter() - t
+    info_e = lib.bidomain_amg_info(lib.bidomain_sim_hierarchy(sim, 0))
+    info_p = lib.bidomain_amg_info(lib.bidomain_sim_hierarchy(sim, 1))
+    print(f"[bench] {args.workload} n={n} setup {setup_s:.1f} s; elliptic levels {info_e['n']}; "
+          f"parabolic levels {info_p['n']}", file=sys.stderr, flush=True)
+
+    if args.warmup:
+        rc, _ = lib.bidomain_step(sim, args.warmup, args.rtol, stream=stream)
+        assert rc == lib.BD_OK, rc
+    lib.bidomain_profile_read(reset=True)
+    lib.bidomain_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, info = lib.bidomain_step(sim, args.steps, args.rtol, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.bidomain_profile_enable(False)
+    prof_ms, prof_launches = lib.bidomain_profile_read(reset=True)
+    assert rc == lib.BD_OK, (rc, info)
+    lib.bidomain_sim_destroy(sim)
+    print(f"[bench] {args.steps} steps in {wall:.3f} s; it_ell {info['it_ell']} it_par {info['it_par']}",
+          file=sys.stderr, flush=True)
+
+    ell_s = info["ms_ell"] * 1e-3
+    value = n * info["it_ell"] / ell_s
+    avg_ms = prof_ms / max(prof_launches, 1)
+    bytes_launch = spmv_bytes(n, nnz)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic_from_profile(n, nnz),
+                    kernel="k_spmv<double, 8, OP_CG_Q> (outer q = A p on the fine operator, with p^T q)",
+                    bytes_per_launch=bytes_launch, avg_launch_ms=round(avg_ms, 5), launches=prof_launches)
+
+    out = {
+        "metric": "elliptic PCG-AMG DOF*iters/s",
+        "value": value,
+        "unit": "DOF*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32-vcycle/f64" if args.mixed else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: Bidomain slab {case.nx}x{case.ny}x{case.nz} Q1 elements, n={n}, "
+                        f"nnz={nnz}, Aliev-Panfilov + parabolic + elliptic AMG-PCG per step, rtol {args.rtol:g}",
+            "elliptic_levels": info_e["n"],
+            "parabolic_levels": info_p["n"],
+            "operator_complexity_ell": round(info_e["operator_complexity"], 3),
+        },
+        "phases_ms_per_step": {"memb": info["ms_memb"] / args.steps, "par": info["ms_par"] / args.steps,
+                               "ell": info["ms_ell"] / args.steps},
+        "iters_per_step": {"par": info["it_par"] / args.steps, "ell": info["it_ell"] / args.steps},
+        "setup_s": round(setup_s, 2),
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

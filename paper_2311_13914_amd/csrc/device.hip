@@ -77,15 +77,38 @@ struct DCsr {
   const int* rp = nullptr;
   const int* ci = nullptr;
   T* v = nullptr;
-  int G = 8;    // lanes per row
-  int tpb = 1;  // row tiles per block
+  int G = 8;    // lanes per row (row-group kernel)
+  int tpb = 1;  // row tiles per block (row-group kernel)
   int nb = 0;   // blocks of a product launch
+  const int* blk = nullptr;  // CSR-stream row blocks (nb + 1 row offsets), or null
 };
 
 int lanes_for(double mean_row) {
   int g = 2;
   while (g < 64 && g * 4 < mean_row) g *= 2;
   return g;
+}
+
+// Short-row matrices (mean row length <= 64, every row fits the staging buffer) use the
+// CSR-stream kernel; the host packs consecutive rows into blocks of at most kStreamRows rows
+// and kStreamCap nonzeros.
+std::vector<int> stream_blocks(const Csr& H) {
+  std::vector<int> blk;
+  if (H.nrows == 0 || (double)H.nnz() > 64.0 * H.nrows) return blk;
+  for (int32_t i = 0; i < H.nrows; ++i)
+    if (H.rp[i + 1] - H.rp[i] > kStreamCap) return blk;
+  blk.push_back(0);
+  int32_t r = 0;
+  while (r < H.nrows) {
+    const int32_t start = r;
+    int64_t cnt = 0;
+    while (r < H.nrows && r - start < kStreamRows && cnt + (H.rp[r + 1] - H.rp[r]) <= kStreamCap) {
+      cnt += H.rp[r + 1] - H.rp[r];
+      ++r;
+    }
+    blk.push_back(r);
+  }
+  return blk;
 }
 
 template <typename T>
@@ -109,18 +132,28 @@ DCsr<T> upload(Arena& ar, const Csr& H, const int* rp_shared, const int* ci_shar
     M.ci = ci_shared;
   } else {
     int* rp = ar.alloc<int>(H.rp.size());
-    int* ci = ar.alloc<int>(H.ci.size());
+    int* ci = ar.alloc<int>(H.ci.size() + kStreamPad);  // padded for 4-entry vector loads
+    HIPCHK(hipMemsetAsync(ci + H.ci.size(), 0, kStreamPad * sizeof(int), st));
     HIPCHK(hipMemcpyAsync(rp, H.rp.data(), H.rp.size() * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(ci, H.ci.data(), H.ci.size() * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     M.rp = rp;
     M.ci = ci;
   }
-  M.v = ar.alloc<T>(H.v.size());
+  M.v = ar.alloc<T>(H.v.size() + kStreamPad);
+  HIPCHK(hipMemsetAsync(M.v + H.v.size(), 0, kStreamPad * sizeof(T), st));
   std::vector<T> tmp(H.v.begin(), H.v.end());
   HIPCHK(hipMemcpyAsync(M.v, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   configure(M, max_blocks);
+  const std::vector<int> blk = stream_blocks(H);
+  if (!blk.empty()) {
+    int* d = ar.alloc<int>(blk.size());
+    HIPCHK(hipMemcpyAsync(d, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    M.blk = d;
+    M.nb = (int)blk.size() - 1;
+  }
   return M;
 }
 
@@ -205,6 +238,11 @@ void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
   a.nrows = M.n;
   a.tpb = M.tpb;
   if (M.n == 0) return;
+  if (M.blk) {
+    k_spmv_stream<T, OP><<<M.nb, kBlock, 0, st>>>(a, M.blk);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   switch (M.G) {
     case 2: k_spmv<T, 2, OP><<<M.nb, kBlock, 0, st>>>(a); break;
     case 4: k_spmv<T, 4, OP><<<M.nb, kBlock, 0, st>>>(a); break;
@@ -213,6 +251,11 @@ void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
     case 32: k_spmv<T, 32, OP><<<M.nb, kBlock, 0, st>>>(a); break;
     default: k_spmv<T, 64, OP><<<M.nb, kBlock, 0, st>>>(a); break;
   }
+  HIPCHK(hipGetLastError());
+}
+
+void finalize(const Solve& sv, int kind, int nb, hipStream_t st) {
+  k_finalize<<<1, kBlock, 0, st>>>(sv, kind, nb);
   HIPCHK(hipGetLastError());
 }
 
@@ -381,13 +424,17 @@ template <typename T>
 void precondition(bd_amg* h, const Solve& sv, bool d_ready, const RedSpec& red, hipStream_t st) {
   auto& L = levels<T>(h);
   const bool fused = vcycle<T>(h, 0, sv, d_ready, red, st);
-  if (!fused && red.red != RED_NONE) {
+  if (red.red == RED_NONE) return;
+  int nb = L[0].A.nb;
+  if (!fused) {
     SpArgs<T> a = args<T>(sv);
     a.nrows = L[0].n;
     a.red = red.red; a.r64 = red.r64; a.r32 = red.r32; a.r32_old = red.r32_old;
-    k_vc_reduce<T><<<vec_blocks(L[0].n), kBlock, 0, st>>>(a, L[0].x);
+    nb = vec_blocks(L[0].n);
+    k_vc_reduce<T><<<nb, kBlock, 0, st>>>(a, L[0].x);
     HIPCHK(hipGetLastError());
   }
+  finalize(sv, red.red == RED_F64 ? FIN_VC64 : FIN_VC32, nb, st);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -455,12 +502,10 @@ void alloc_solve_state(bd_amg* h, hipStream_t st) {
   for (Solve* s : {&h->sv, &h->sv_apply}) {
     s->sc = ar.alloc<double>(S_COUNT);
     s->fl = ar.alloc<int>(F_COUNT);
-    s->cnt = ar.alloc<unsigned>(C_COUNT);
     s->part = ar.alloc<double>(h->part_len);
     s->n = n;
     HIPCHK(hipMemsetAsync(s->sc, 0, S_COUNT * sizeof(double), st));
     HIPCHK(hipMemsetAsync(s->fl, 0, F_COUNT * sizeof(int), st));
-    HIPCHK(hipMemsetAsync(s->cnt, 0, C_COUNT * sizeof(unsigned), st));
   }
   // fine-grained (coherent) pinned memory: the update kernel's system-scope stores are seen
   // by the host as soon as the event after that kernel completes
@@ -502,12 +547,15 @@ int pcg(bd_amg* h, const double* b, double* x, int guess, double rtol, int maxit
 
   const int vb = vec_blocks(n);
   k_init_means<<<vb, kBlock, 0, st>>>(sv, b, guess ? x : nullptr, n);
+  HIPCHK(hipGetLastError());
+  finalize(sv, FIN_MEANS, vb, st);
   k_init_guess<<<vb, kBlock, 0, st>>>(sv, x, guess, n);
   HIPCHK(hipGetLastError());
   {
     SpArgs<double> a = args<double>(sv);
     a.x = x; a.y = h->r; a.b = b;
     launch_spmv<double, OP_INIT_RESID>(h->A0, a, st);
+    finalize(sv, FIN_INIT, h->A0.nb, st);
   }
   int flags[F_COUNT];
   HIPCHK(hipMemcpyAsync(flags, sv.fl, sizeof(flags), hipMemcpyDeviceToHost, st));
@@ -560,12 +608,14 @@ int pcg(bd_amg* h, const double* b, double* x, int guess, double rtol, int maxit
       } else {
         launch_spmv<double, OP_CG_Q>(h->A0, a, st);
       }
+      finalize(sv, FIN_CGQ, h->A0.nb, st);
       // x, r update, convergence test, next V-cycle right-hand side
       float* r32n = mixed ? h->r32[cur ^ 1] : nullptr;
       T* f0 = mixed ? (T*)r32n : (T*)h->r;
       k_cg_update<T><<<vb, kBlock, 0, st>>>(sv, x, h->r, h->p, h->q, r32n, L[0].dinv, fuse0 ? L[0].da : nullptr,
                                            (fuse0 && x0_too) ? L[0].x : nullptr, L[0].c0, n);
       HIPCHK(hipGetLastError());
+      finalize(sv, FIN_UPDATE, vb, st);
       HIPCHK(hipEventRecord(ev[enq & 1], st));
       if (mixed) {
         red.r32_old = h->r32[cur];
@@ -614,9 +664,12 @@ int pcg(bd_amg* h, const double* b, double* x, int guess, double rtol, int maxit
     SpArgs<double> a = args<double>(svx);
     a.x = x; a.b = b;
     launch_spmv<double, OP_TRUE_RESID>(h->A0, a, st);
+    finalize(svx, FIN_TRUE, h->A0.nb, st);
   }
   if (h->o.nullspace == BD_NULL_CONSTANT && !zero_rhs) {
     k_norm_sums<<<vb, kBlock, 0, st>>>(svx, h->w, x, n);
+    HIPCHK(hipGetLastError());
+    finalize(svx, FIN_NORM, vb, st);
     k_norm_apply<<<vb, kBlock, 0, st>>>(svx, x, n);
     HIPCHK(hipGetLastError());
   }

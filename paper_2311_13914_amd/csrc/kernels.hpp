@@ -11,9 +11,11 @@
 //  * the block -> row-tile map is XCD-aware: the hardware deals blocks round-robin over the
 //    8 XCDs, so consecutive block ids are remapped to one contiguous row range per XCD, which
 //    keeps each XCD's L2 working on neighbouring rows (and their shared x entries);
-//  * reductions are deterministic: each block writes a partial from a fixed-order tree, and
-//    the last block to finish (integer atomic counter, no float atomics) sums the partials in
-//    a fixed order and derives the solver scalars on the device;
+//  * reductions are deterministic and atomic-free: each block stores a partial from a
+//    fixed-order tree, and a one-block finalize kernel sums the partials in a fixed order and
+//    derives the solver scalars on the device.  (A "last block finishes" scheme would need a
+//    device-scope release fence per block, which on CDNA writes back the XCD's L2 each time;
+//    the kernel boundary gives the same visibility once.)
 //  * every solve kernel first reads the solve's `done` flag and returns at once when it is set,
 //    so iterations enqueued past convergence cost only their launch.
 #pragma once
@@ -53,13 +55,12 @@ enum Flag : int {
   F_NULLSPACE,
   F_COUNT
 };
-// Reduction counters (one per kernel family so families never share a counter).
-enum Counter : int { C_SPMV = 0, C_UPD, C_VC, C_INIT, C_TRUE, C_NORM, C_COUNT };
+// Finalize kinds (one-block kernels that turn block partials into solver scalars).
+enum Fin : int { FIN_CGQ = 0, FIN_UPDATE, FIN_VC64, FIN_VC32, FIN_INIT, FIN_TRUE, FIN_MEANS, FIN_NORM };
 
 struct Solve {
   double* sc;          // S_COUNT scalars
   int* fl;             // F_COUNT flags
-  unsigned* cnt;       // C_COUNT counters (zero between kernels)
   double* part;        // block partials
   int* host_flags;     // pinned host mirror of (done, iters, status), may be null
   long n;              // fine-level rows
@@ -74,12 +75,6 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 
 __device__ __forceinline__ bool solve_done(const Solve& s) {
   return __hip_atomic_load(&s.fl[F_DONE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-}
-
-// Coherent (L1-bypassing) load of another block's partial.
-template <typename T>
-__device__ __forceinline__ T load_coherent(const T* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -103,16 +98,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NV * 4
   __syncthreads();
 }
 
-// True in exactly one block: the last one to publish its partials.
-__device__ __forceinline__ bool arrive_last(unsigned* counter) {
-  __shared__ int last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-  __syncthreads();
-  return last != 0;
-}
-
 // Fixed-order sum of NV partial arrays (stride nb) by the whole block.
 template <int NV>
 __device__ __forceinline__ void sum_partials(const double* part, int nb, double (&out)[NV], double* lds) {
@@ -120,7 +105,7 @@ __device__ __forceinline__ void sum_partials(const double* part, int nb, double 
   for (int k = 0; k < NV; ++k) out[k] = 0.0;
   for (int i = threadIdx.x; i < nb; i += kBlock)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) out[k] += load_coherent(part + (long)k * nb + i);
+    for (int k = 0; k < NV; ++k) out[k] += part[(long)k * nb + i];
   block_sum<NV>(out, lds);
 }
 
@@ -261,8 +246,74 @@ struct VcAcc {
 };
 
 template <typename T>
-__device__ void vc_finish(VcAcc<T>& v, int red, const Solve& sv, int nb, double* lds, float* lds32);
+__device__ void vc_partials(VcAcc<T>& v, int red, const Solve& sv, int nb, double* lds, float* lds32);
 
+// Fused epilogue of one row (s = (A x)_row); reduction terms accumulate in acc / vc.
+template <typename T, int OP>
+__device__ __forceinline__ void row_epilogue(const SpArgs<T>& a, int row, T s, double (&acc)[3], VcAcc<T>& vc) {
+  if constexpr (OP == OP_Y) {
+    a.y[row] = s;
+  } else if constexpr (OP == OP_ADDY) {
+    a.y[row] += s;
+  } else if constexpr (OP == OP_RESID) {
+    a.y[row] = a.f[row] - s;
+  } else if constexpr (OP == OP_RESTRICT) {
+    a.y[row] = s;
+    const T d = a.c0 * a.dinv2[row] * s;
+    a.y2[row] = d;
+    if (a.xs) a.xs[row] = d;
+  } else if constexpr (OP == OP_CHEB_FIRST) {
+    const T r1 = a.f[row] - s;
+    const T d = a.x[row];
+    const T dn = a.c1 * d + a.c2 * a.dinv[row] * r1;
+    a.xs[row] = d + dn;
+    if (a.store_rd) { a.r[row] = r1; a.y2[row] = dn; }
+  } else if constexpr (OP == OP_CHEB_POST0) {
+    const T r0 = a.f[row] - s;
+    a.r[row] = r0;
+    a.y2[row] = a.c0 * a.dinv[row] * r0;
+  } else if constexpr (OP == OP_CHEB_STEP) {
+    const T r1 = a.r[row] - s;
+    const T d = a.x[row];
+    const T dn = a.c1 * d + a.c2 * a.dinv[row] * r1;
+    const T xn = a.xs[row] + (a.add_d ? d + dn : dn);
+    a.xs[row] = xn;
+    if (a.store_rd) { a.r[row] = r1; a.y2[row] = dn; }
+    vc.add(a.red, (double)xn, (float)xn, row, a);
+  } else if constexpr (OP == OP_JACOBI) {
+    a.y[row] = a.x[row] + a.c0 * a.dinv[row] * (a.f[row] - s);
+  } else if constexpr (OP == OP_CG_Q) {
+    a.y[row] = s;
+    acc[0] += (double)a.x[row] * (double)s;
+  } else if constexpr (OP == OP_INIT_RESID) {
+    const double bh = a.b[row] - a.sv.sc[S_MU_B];
+    const double rr = bh - (double)s;
+    a.y[row] = (T)rr;
+    acc[0] += bh * bh;
+    acc[1] += rr * rr;
+  } else if constexpr (OP == OP_TRUE_RESID) {
+    const double rr = (a.b[row] - a.sv.sc[S_MU_B]) - (double)s;
+    acc[0] += rr * rr;
+  }
+}
+
+// Block partials of the reducing ops (finalized by k_finalize).  Called by every thread.
+template <typename T, int OP>
+__device__ __forceinline__ void block_tail(const SpArgs<T>& a, double (&acc)[3], VcAcc<T>& vc, int nb, double* lds,
+                                           float* lds32) {
+  if constexpr (OP == OP_CG_Q || OP == OP_TRUE_RESID) {
+    block_sum<1>(*reinterpret_cast<double(*)[1]>(acc), lds);
+    if (threadIdx.x == 0) a.sv.part[blockIdx.x] = acc[0];
+  } else if constexpr (OP == OP_INIT_RESID) {
+    block_sum<2>(*reinterpret_cast<double(*)[2]>(acc), lds);
+    if (threadIdx.x == 0) { a.sv.part[blockIdx.x] = acc[0]; a.sv.part[nb + blockIdx.x] = acc[1]; }
+  } else if constexpr (OP == OP_CHEB_STEP) {
+    if (a.red != RED_NONE) vc_partials<T>(vc, a.red, a.sv, nb, lds, lds32);
+  }
+}
+
+// Row-group kernel: G lanes per row, TPB consecutive 256/G-row tiles per block.  Used for
+// matrices with long rows (coarse Galerkin operators, restrictions).
 template <typename T, int G, int OP>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
   if (solve_done(a.sv)) return;
@@ -272,120 +323,96 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
   const int nb = gridDim.x;
   const int tile0 = xcd_tile(blockIdx.x, nb) * a.tpb;
   const int grp = threadIdx.x / G, lane = threadIdx.x % G;
-
   double acc[3] = {0.0, 0.0, 0.0};
   VcAcc<T> vc;
   for (int t = 0; t < a.tpb; ++t) {
     const int row = (tile0 + t) * RPT + grp;
     if (row >= a.nrows) break;
     const T s = row_product<T, G>(a.rp, a.ci, a.av, a.x, row, lane);
-    if (lane != 0) continue;
-    if constexpr (OP == OP_Y) {
-      a.y[row] = s;
-    } else if constexpr (OP == OP_ADDY) {
-      a.y[row] += s;
-    } else if constexpr (OP == OP_RESID) {
-      a.y[row] = a.f[row] - s;
-    } else if constexpr (OP == OP_RESTRICT) {
-      a.y[row] = s;
-      const T d = a.c0 * a.dinv2[row] * s;
-      a.y2[row] = d;
-      if (a.xs) a.xs[row] = d;
-    } else if constexpr (OP == OP_CHEB_FIRST) {
-      const T r1 = a.f[row] - s;
-      const T d = a.x[row];
-      const T dn = a.c1 * d + a.c2 * a.dinv[row] * r1;
-      a.xs[row] = d + dn;
-      if (a.store_rd) { a.r[row] = r1; a.y2[row] = dn; }
-    } else if constexpr (OP == OP_CHEB_POST0) {
-      const T r0 = a.f[row] - s;
-      a.r[row] = r0;
-      a.y2[row] = a.c0 * a.dinv[row] * r0;
-    } else if constexpr (OP == OP_CHEB_STEP) {
-      const T r1 = a.r[row] - s;
-      const T d = a.x[row];
-      const T dn = a.c1 * d + a.c2 * a.dinv[row] * r1;
-      const T xn = a.xs[row] + (a.add_d ? d + dn : dn);
-      a.xs[row] = xn;
-      if (a.store_rd) { a.r[row] = r1; a.y2[row] = dn; }
-      vc.add(a.red, (double)xn, (float)xn, row, a);
-    } else if constexpr (OP == OP_JACOBI) {
-      a.y[row] = a.x[row] + a.c0 * a.dinv[row] * (a.f[row] - s);
-    } else if constexpr (OP == OP_CG_Q) {
-      a.y[row] = s;
-      acc[0] += (double)a.x[row] * (double)s;
-    } else if constexpr (OP == OP_INIT_RESID) {
-      const double bh = a.b[row] - a.sv.sc[S_MU_B];
-      const double rr = bh - (double)s;
-      a.y[row] = (T)rr;
-      acc[0] += bh * bh;
-      acc[1] += rr * rr;
-    } else if constexpr (OP == OP_TRUE_RESID) {
-      const double rr = (a.b[row] - a.sv.sc[S_MU_B]) - (double)s;
-      acc[0] += rr * rr;
-    }
+    if (lane == 0) row_epilogue<T, OP>(a, row, s, acc, vc);
   }
-
-  // ---- reductions and device-side scalar updates
-  if constexpr (OP == OP_CG_Q) {
-    block_sum<1>(*reinterpret_cast<double(*)[1]>(acc), lds);
-    if (threadIdx.x == 0) a.sv.part[blockIdx.x] = acc[0];
-    if (arrive_last(&a.sv.cnt[C_SPMV])) {
-      double tot[1];
-      sum_partials<1>(a.sv.part, nb, tot, lds);
-      if (threadIdx.x == 0) {
-        const double pq = tot[0];
-        a.sv.sc[S_PQ] = pq;
-        if (!(pq > 0.0) || !isfinite(pq)) {
-          a.sv.fl[F_STATUS] = isfinite(pq) ? -4 : -5;
-          a.sv.fl[F_DONE] = 1;
-        } else {
-          a.sv.sc[S_ALPHA] = a.sv.sc[S_RHO] / pq;
-        }
-        a.sv.cnt[C_SPMV] = 0;
-      }
-    }
-  } else if constexpr (OP == OP_INIT_RESID) {
-    block_sum<2>(*reinterpret_cast<double(*)[2]>(acc), lds);
-    if (threadIdx.x == 0) { a.sv.part[blockIdx.x] = acc[0]; a.sv.part[nb + blockIdx.x] = acc[1]; }
-    if (arrive_last(&a.sv.cnt[C_INIT])) {
-      double tot[2];
-      sum_partials<2>(a.sv.part, nb, tot, lds);
-      if (threadIdx.x == 0) {
-        a.sv.sc[S_FNORM2] = tot[0];
-        a.sv.sc[S_RNORM2] = tot[1];
-        const double tol2 = a.sv.sc[S_RTOL2] * tot[0];
-        a.sv.sc[S_TOL2] = tol2;
-        if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-          a.sv.fl[F_STATUS] = -5;
-          a.sv.fl[F_DONE] = 1;
-        } else if (tot[0] == 0.0 || tot[1] <= tol2) {
-          a.sv.fl[F_DONE] = 1;
-        }
-        a.sv.cnt[C_INIT] = 0;
-      }
-    }
-  } else if constexpr (OP == OP_TRUE_RESID) {
-    block_sum<1>(*reinterpret_cast<double(*)[1]>(acc), lds);
-    if (threadIdx.x == 0) a.sv.part[blockIdx.x] = acc[0];
-    if (arrive_last(&a.sv.cnt[C_TRUE])) {
-      double tot[1];
-      sum_partials<1>(a.sv.part, nb, tot, lds);
-      if (threadIdx.x == 0) {
-        a.sv.sc[S_TRUE2] = tot[0];
-        a.sv.cnt[C_TRUE] = 0;
-      }
-    }
-  } else if constexpr (OP == OP_CHEB_STEP) {
-    if (a.red != RED_NONE) vc_finish<T>(vc, a.red, a.sv, nb, lds, lds32);
-  }
+  block_tail<T, OP>(a, acc, vc, nb, lds, lds32);
 }
 
-// Block partials of the level-0 reductions, then (last block) the CG scalars:
-// mu_z = 1^T z / n (projection), rho = r^T (z - mu_z 1) and beta = rho / rho_old (RED_F64);
-// rho = Dot2(z32, r32), beta = (rho - Dot2(z32, r32_old)) / rho_old (RED_F32, flexible CG).
+// CSR-stream kernel (after Greathouse & Daga, SC'14): block b owns rows [blk[b], blk[b+1]),
+// at most kStreamRows rows whose nonzeros fit in kStreamCap.  Phase 1 streams the block's
+// contiguous value/column range with consecutive lanes on consecutive entries (every load
+// instruction covers one contiguous span) and stages the products a_k x_{c_k} in LDS;
+// phase 2 reduces each row from LDS with a power-of-two lane group and applies the epilogue.
+constexpr int kStreamCap = 4096;
+constexpr int kStreamRows = 128;
+constexpr int kStreamPad = 4;   // value/column arrays carry this many padding entries
+constexpr int kStreamChunks = (kStreamCap + 3) / (4 * kBlock) + 1;  // 4-entry chunks per thread
+
+// Four consecutive matrix entries with 16-byte loads (entry index a multiple of 4).
+__device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
+  const double2 a = *reinterpret_cast<const double2*>(p);
+  const double2 b = *reinterpret_cast<const double2*>(p + 2);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+__device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* __restrict__ blk) {
+  if (solve_done(a.sv)) return;
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  __shared__ T prod[kStreamCap];
+  const int nb = gridDim.x;
+  const int b = xcd_tile(blockIdx.x, nb);
+  const int r0 = blk[b], r1 = blk[b + 1];
+  const int beg = a.rp[r0], end = a.rp[r1];
+  // Phase 1: the block's entries [beg, end) in 4-entry chunks aligned to 4, every chunk's
+  // loads issued before any is consumed (the chunk loop is unrolled); entries outside
+  // [beg, end) read the neighbouring rows or the padding and are dropped.
+  const int k0 = beg & ~3;
+  int cidx[kStreamChunks][4];
+  T val[kStreamChunks][4];
+#pragma unroll
+  for (int c = 0; c < kStreamChunks; ++c) {
+    const int k = k0 + 4 * ((int)threadIdx.x + kBlock * c);
+    if (k < end) {
+      const int4 cc = *reinterpret_cast<const int4*>(a.ci + k);
+      cidx[c][0] = cc.x; cidx[c][1] = cc.y; cidx[c][2] = cc.z; cidx[c][3] = cc.w;
+      load4(a.av + k, val[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kStreamChunks; ++c) {
+    const int k = k0 + 4 * ((int)threadIdx.x + kBlock * c);
+    if (k < end) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int kk = k + j;
+        if (kk >= beg && kk < end) prod[kk - beg] = val[c][j] * a.x[cidx[c][j]];
+      }
+    }
+  }
+  __syncthreads();
+  const int nrow = r1 - r0;
+  int g = kBlock / (nrow > 0 ? nrow : 1);  // lanes per row: a power of two, at most 64
+  g = g >= 64 ? 64 : (g >= 32 ? 32 : (g >= 16 ? 16 : (g >= 8 ? 8 : (g >= 4 ? 4 : (g >= 2 ? 2 : 1)))));
+  const int grp = threadIdx.x / g, lane = threadIdx.x % g;
+  double acc[3] = {0.0, 0.0, 0.0};
+  VcAcc<T> vc;
+  const int row = r0 + grp;
+  T s = T(0);
+  if (grp < nrow) {
+    const int lo = a.rp[row] - beg, hi = a.rp[row + 1] - beg;
+    for (int k = lo + lane; k < hi; k += g) s += prod[k];
+  }
+  for (int off = g / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, g);
+  if (grp < nrow && lane == 0) row_epilogue<T, OP>(a, row, s, acc, vc);
+  block_tail<T, OP>(a, acc, vc, nb, lds, lds32);
+}
+
+// Block partials of the level-0 reductions: 1^T z, r^T z, 1^T r (RED_F64) or the two Dot2
+// pairs z32.r32, z32.r32_old and 1^T z (RED_F32).
 template <typename T>
-__device__ void vc_finish(VcAcc<T>& v, int red, const Solve& sv, int nb, double* lds, float* lds32) {
+__device__ void vc_partials(VcAcc<T>& v, int red, const Solve& sv, int nb, double* lds, float* lds32) {
   if (red == RED_F64) {
     block_sum<3>(v.acc, lds);
     if (threadIdx.x == 0) {
@@ -405,40 +432,6 @@ __device__ void vc_finish(VcAcc<T>& v, int red, const Solve& sv, int nb, double*
       sv.part[blockIdx.x] = v.acc[0];
     }
   }
-  if (!arrive_last(&sv.cnt[C_VC])) return;
-  double sz, rz, num;
-  if (red == RED_F64) {
-    double tot[3];
-    sum_partials<3>(sv.part, nb, tot, lds);
-    const double mu = sv.fl[F_NULLSPACE] ? tot[0] / (double)sv.n : 0.0;
-    sz = tot[0];
-    rz = tot[1] - mu * tot[2];
-    num = rz;
-  } else {
-    double tot[1];
-    sum_partials<1>(sv.part, nb, tot, lds);
-    sz = tot[0];
-    Dot2 c[2];
-    const float* pf = reinterpret_cast<const float*>(sv.part + nb);
-    for (int i = threadIdx.x; i < nb; i += kBlock) {  // fixed order per thread, then a fixed tree
-      c[0].merge(load_coherent(pf + 4 * i + 0), load_coherent(pf + 4 * i + 1));
-      c[1].merge(load_coherent(pf + 4 * i + 2), load_coherent(pf + 4 * i + 3));
-    }
-    block_dot2<2>(c, lds32);
-    rz = (double)c[0].p + (double)c[0].s;
-    num = rz - ((double)c[1].p + (double)c[1].s);
-  }
-  if (threadIdx.x == 0) {
-    sv.sc[S_MU_Z] = sv.fl[F_NULLSPACE] ? sz / (double)sv.n : 0.0;
-    const double rho_old = sv.sc[S_RHO];
-    sv.sc[S_BETA] = sv.fl[F_FIRST] ? 0.0 : num / rho_old;
-    sv.sc[S_RHO] = rz;
-    if (!(rz > 0.0) || !isfinite(rz)) {
-      sv.fl[F_STATUS] = isfinite(rz) ? -4 : -5;
-      sv.fl[F_DONE] = 1;
-    }
-    sv.cnt[C_VC] = 0;
-  }
 }
 
 // The level-0 reductions on their own, for V-cycles whose last kernel is not a fused
@@ -451,14 +444,135 @@ __global__ __launch_bounds__(kBlock) void k_vc_reduce(SpArgs<T> a, const T* __re
   VcAcc<T> vc;
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < a.nrows; i += (long)gridDim.x * kBlock)
     vc.add(a.red, (double)z[i], (float)z[i], (int)i, a);
-  vc_finish<T>(vc, a.red, a.sv, gridDim.x, lds, lds32);
+  vc_partials<T>(vc, a.red, a.sv, gridDim.x, lds, lds32);
+}
+
+// One block: sums the partials of the preceding kernel (nb blocks) in a fixed order and
+// updates the solver scalars and flags.
+//   FIN_CGQ    p^T q -> alpha = rho / p^T q            (breakdown if p^T q <= 0)
+//   FIN_UPDATE ||r||^2 -> convergence / cap / non-finite, iteration count, host mirror
+//   FIN_VC64   mu_z = 1^T z / n, rho = r^T (z - mu_z 1), beta = rho / rho_old
+//   FIN_VC32   rho = Dot2(z32, r32), beta = (rho - Dot2(z32, r32_old)) / rho_old (flexible CG)
+//   FIN_INIT   ||b^||^2, ||r0||^2 -> tolerance, early exit
+//   FIN_TRUE   ||b^ - A x||^2
+//   FIN_MEANS  means of b and of the initial guess (projection)
+//   FIN_NORM   w^T x and 1^T w (normalisation)
+__global__ __launch_bounds__(kBlock) void k_finalize(Solve sv, int kind, int nb) {
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  const bool guarded = kind == FIN_CGQ || kind == FIN_UPDATE || kind == FIN_VC64 || kind == FIN_VC32;
+  if (guarded && sv.fl[F_DONE]) {
+    if (kind == FIN_UPDATE && threadIdx.x == 0 && sv.host_flags)
+      __hip_atomic_store(&sv.host_flags[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    return;
+  }
+  const bool t0 = threadIdx.x == 0;
+  if (kind == FIN_CGQ) {
+    double tot[1];
+    sum_partials<1>(sv.part, nb, tot, lds);
+    if (t0) {
+      const double pq = tot[0];
+      sv.sc[S_PQ] = pq;
+      if (!(pq > 0.0) || !isfinite(pq)) {
+        sv.fl[F_STATUS] = isfinite(pq) ? -4 : -5;
+        sv.fl[F_DONE] = 1;
+      } else {
+        sv.sc[S_ALPHA] = sv.sc[S_RHO] / pq;
+      }
+    }
+  } else if (kind == FIN_UPDATE) {
+    double tot[1];
+    sum_partials<1>(sv.part, nb, tot, lds);
+    if (t0) {
+      const double r2 = tot[0];
+      sv.sc[S_RNORM2] = r2;
+      const int it = sv.fl[F_ITERS] + 1;
+      sv.fl[F_ITERS] = it;
+      int done = 0;
+      if (!isfinite(r2)) { sv.fl[F_STATUS] = -5; done = 1; }
+      else if (r2 <= sv.sc[S_TOL2]) { done = 1; }
+      else if (it >= sv.fl[F_MAXIT]) { sv.fl[F_STATUS] = 1; done = 1; }
+      if (done) sv.fl[F_DONE] = 1;
+      if (sv.host_flags) {
+        __hip_atomic_store(&sv.host_flags[1], it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(&sv.host_flags[0], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  } else if (kind == FIN_VC64 || kind == FIN_VC32) {
+    double sz, rz, num;
+    if (kind == FIN_VC64) {
+      double tot[3];
+      sum_partials<3>(sv.part, nb, tot, lds);
+      const double mu = sv.fl[F_NULLSPACE] ? tot[0] / (double)sv.n : 0.0;
+      sz = tot[0];
+      rz = tot[1] - mu * tot[2];
+      num = rz;
+    } else {
+      double tot[1];
+      sum_partials<1>(sv.part, nb, tot, lds);
+      sz = tot[0];
+      Dot2 c[2];
+      const float* pf = reinterpret_cast<const float*>(sv.part + nb);
+      for (int i = threadIdx.x; i < nb; i += kBlock) {  // fixed order per thread, then a fixed tree
+        c[0].merge(pf[4 * i + 0], pf[4 * i + 1]);
+        c[1].merge(pf[4 * i + 2], pf[4 * i + 3]);
+      }
+      block_dot2<2>(c, lds32);
+      rz = (double)c[0].p + (double)c[0].s;
+      num = rz - ((double)c[1].p + (double)c[1].s);
+    }
+    if (t0) {
+      sv.sc[S_MU_Z] = sv.fl[F_NULLSPACE] ? sz / (double)sv.n : 0.0;
+      const double rho_old = sv.sc[S_RHO];
+      sv.sc[S_BETA] = sv.fl[F_FIRST] ? 0.0 : num / rho_old;
+      sv.sc[S_RHO] = rz;
+      if (!(rz > 0.0) || !isfinite(rz)) {
+        sv.fl[F_STATUS] = isfinite(rz) ? -4 : -5;
+        sv.fl[F_DONE] = 1;
+      }
+    }
+  } else if (kind == FIN_INIT) {
+    double tot[2];
+    sum_partials<2>(sv.part, nb, tot, lds);
+    if (t0) {
+      sv.sc[S_FNORM2] = tot[0];
+      sv.sc[S_RNORM2] = tot[1];
+      const double tol2 = sv.sc[S_RTOL2] * tot[0];
+      sv.sc[S_TOL2] = tol2;
+      if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+        sv.fl[F_STATUS] = -5;
+        sv.fl[F_DONE] = 1;
+      } else if (tot[0] == 0.0 || tot[1] <= tol2) {
+        sv.fl[F_DONE] = 1;
+      }
+    }
+  } else if (kind == FIN_TRUE) {
+    double tot[1];
+    sum_partials<1>(sv.part, nb, tot, lds);
+    if (t0) sv.sc[S_TRUE2] = tot[0];
+  } else if (kind == FIN_MEANS) {
+    double tot[2];
+    sum_partials<2>(sv.part, nb, tot, lds);
+    if (t0) {
+      const bool ns = sv.fl[F_NULLSPACE] != 0;
+      sv.sc[S_MU_B] = ns ? tot[0] / (double)sv.n : 0.0;
+      sv.sc[S_MU_X] = ns ? tot[1] / (double)sv.n : 0.0;
+    }
+  } else if (kind == FIN_NORM) {
+    double tot[2];
+    sum_partials<2>(sv.part, nb, tot, lds);
+    if (t0) {
+      sv.sc[S_WX] = tot[0];
+      sv.sc[S_WSUM] = tot[1];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------
 // Pointwise kernels.
 __device__ __forceinline__ long gtid() { return (long)blockIdx.x * kBlock + threadIdx.x; }
 
-// x += alpha p; r -= alpha q; ||r||^2 -> convergence test.  Optionally writes the level-0
+// x += alpha p; r -= alpha q; partial ||r||^2 (convergence test in FIN_UPDATE).  Optionally writes the level-0
 // right-hand side of the float V-cycle (r32 = fl32(r)) and the first pre-smoothing step of
 // level 0 (d0 = c0 dinv0 f0; also x0 = d0 when x0 is given).
 template <typename T>
@@ -485,26 +599,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Solve sv, double* __restri
   }
   block_sum<1>(acc, lds);
   if (threadIdx.x == 0) sv.part[blockIdx.x] = acc[0];
-  if (arrive_last(&sv.cnt[C_UPD])) {
-    double tot[1];
-    sum_partials<1>(sv.part, gridDim.x, tot, lds);
-    if (threadIdx.x == 0) {
-      const double r2 = tot[0];
-      sv.sc[S_RNORM2] = r2;
-      const int it = sv.fl[F_ITERS] + 1;
-      sv.fl[F_ITERS] = it;
-      int done = 0;
-      if (!isfinite(r2)) { sv.fl[F_STATUS] = -5; done = 1; }
-      else if (r2 <= sv.sc[S_TOL2]) { done = 1; }
-      else if (it >= sv.fl[F_MAXIT]) { sv.fl[F_STATUS] = 1; done = 1; }
-      if (done) sv.fl[F_DONE] = 1;
-      if (sv.host_flags) {
-        __hip_atomic_store(&sv.host_flags[1], it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&sv.host_flags[0], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
-      sv.cnt[C_UPD] = 0;
-    }
-  }
 }
 
 // p = (z - mu_z) + beta p   (p = z - mu_z for the first direction).
@@ -562,7 +656,7 @@ __global__ __launch_bounds__(kBlock) void k_coarse_gemv(Solve sv, const double* 
 
 // ---------------------------------------------------------------------------------------
 // Setup / exit kernels of a solve.
-// Sums of b (and of the initial guess) -> means for the projection.
+// Partial sums of b (and of the initial guess) for the projection means (FIN_MEANS).
 __global__ __launch_bounds__(kBlock) void k_init_means(Solve sv, const double* __restrict__ b, const double* __restrict__ x,
                                                        long n) {
   __shared__ double lds[8];
@@ -574,16 +668,6 @@ __global__ __launch_bounds__(kBlock) void k_init_means(Solve sv, const double* _
   block_sum<2>(acc, lds);
   const int nb = gridDim.x;
   if (threadIdx.x == 0) { sv.part[blockIdx.x] = acc[0]; sv.part[nb + blockIdx.x] = acc[1]; }
-  if (arrive_last(&sv.cnt[C_INIT])) {
-    double tot[2];
-    sum_partials<2>(sv.part, nb, tot, lds);
-    if (threadIdx.x == 0) {
-      const bool ns = sv.fl[F_NULLSPACE] != 0;
-      sv.sc[S_MU_B] = ns ? tot[0] / (double)n : 0.0;
-      sv.sc[S_MU_X] = ns ? tot[1] / (double)n : 0.0;
-      sv.cnt[C_INIT] = 0;
-    }
-  }
 }
 
 // x = x - mu_x (guess) or 0; with no guess also r = b - mu_b and the norms of b^.
@@ -592,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_init_guess(Solve sv, double* __restr
   for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) x[i] = guess ? x[i] - mu : 0.0;
 }
 
-// Weighted normalisation x -= (w^T x / sum w) 1 : reduction, then update.
+// Weighted normalisation x -= (w^T x / sum w) 1: partials (FIN_NORM), then the update.
 __global__ __launch_bounds__(kBlock) void k_norm_sums(Solve sv, const double* __restrict__ w, const double* __restrict__ x,
                                                       long n) {
   __shared__ double lds[8];
@@ -605,15 +689,6 @@ __global__ __launch_bounds__(kBlock) void k_norm_sums(Solve sv, const double* __
   block_sum<2>(acc, lds);
   const int nb = gridDim.x;
   if (threadIdx.x == 0) { sv.part[blockIdx.x] = acc[0]; sv.part[nb + blockIdx.x] = acc[1]; }
-  if (arrive_last(&sv.cnt[C_NORM])) {
-    double tot[2];
-    sum_partials<2>(sv.part, nb, tot, lds);
-    if (threadIdx.x == 0) {
-      sv.sc[S_WX] = tot[0];
-      sv.sc[S_WSUM] = tot[1];
-      sv.cnt[C_NORM] = 0;
-    }
-  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_norm_apply(Solve sv, double* __restrict__ x, long n) {
