@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed region, copy 1 GiB once (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solver has no multi-GPU path.",
@@ -132,6 +134,12 @@ def main():
     prof_ms, prof_launches = lib.bidomain_profile_read(reset=True)
     assert rc == lib.BD_OK, (rc, info)
     lib.bidomain_sim_destroy(sim)
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] {args.steps} steps in {wall:.3f} s; it_ell {info['it_ell']} it_par {info['it_par']}",
           file=sys.stderr, flush=True)
 
@@ -142,7 +150,7 @@ def main():
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic_from_profile(n, nnz),
-                    kernel="k_spmv<double, 8, OP_CG_Q> (outer q = A p on the fine operator, with p^T q)",
+                    kernel="k_spmv_stream<double, 8> (OP_CG_Q: outer q = A p on the fine operator, with p^T q)",
                     bytes_per_launch=bytes_launch, avg_launch_ms=round(avg_ms, 5), launches=prof_launches)
 
     out = {

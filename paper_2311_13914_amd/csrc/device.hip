@@ -89,12 +89,13 @@ int lanes_for(double mean_row) {
   return g;
 }
 
-// Short-row matrices (mean row length <= 64, every row fits the staging buffer) use the
-// CSR-stream kernel; the host packs consecutive rows into blocks of at most kStreamRows rows
-// and kStreamCap nonzeros.
+// Matrices whose every row fits the staging buffer use the CSR-stream kernel (measured faster
+// than the lane-group kernel on every level of the slab hierarchies, short and long rows
+// alike); the host packs consecutive rows into blocks of at most kStreamRows rows and
+// kStreamCap nonzeros.  Longer rows fall back to the lane-group kernel.
 std::vector<int> stream_blocks(const Csr& H) {
   std::vector<int> blk;
-  if (H.nrows == 0 || (double)H.nnz() > 64.0 * H.nrows) return blk;
+  if (H.nrows == 0) return blk;
   for (int32_t i = 0; i < H.nrows; ++i)
     if (H.rp[i + 1] - H.rp[i] > kStreamCap) return blk;
   blk.push_back(0);

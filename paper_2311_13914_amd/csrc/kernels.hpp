@@ -168,14 +168,30 @@ __device__ __forceinline__ void block_dot2(Dot2 (&v)[NV], float* lds /* NV * 8 *
 }
 
 // ---------------------------------------------------------------------------------------
-// CSR row product by a group of G lanes; every lane of the group returns the row sum.
+// CSR row product by a group of G lanes; every lane of the group returns the row sum.  Four
+// strided entries per lane per trip, with indices clamped into the row so that the four
+// column loads and the four x gathers are issued together (entries past the row end are
+// gathered but multiplied by zero).
 template <typename T, int G>
 __device__ __forceinline__ T row_product(const int* __restrict__ rp, const int* __restrict__ ci,
                                          const T* __restrict__ av, const T* __restrict__ x, int row,
                                          int lane) {
   T s = T(0);
   const int beg = rp[row], end = rp[row + 1];
-  for (int k = beg + lane; k < end; k += G) s += av[k] * x[ci[k]];
+  if (end > beg) {
+    for (int k = beg + lane; k < end; k += 4 * G) {
+      int kk[4], c[4];
+      T v[4], xv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) kk[j] = min(k + j * G, end - 1);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) { c[j] = ci[kk[j]]; v[j] = av[kk[j]]; }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xv[j] = x[c[j]];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s += (k + j * G < end) ? v[j] * xv[j] : T(0);
+    }
+  }
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
   return s;
@@ -365,29 +381,35 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* 
   const int b = xcd_tile(blockIdx.x, nb);
   const int r0 = blk[b], r1 = blk[b + 1];
   const int beg = a.rp[r0], end = a.rp[r1];
-  // Phase 1: the block's entries [beg, end) in 4-entry chunks aligned to 4, every chunk's
-  // loads issued before any is consumed (the chunk loop is unrolled); entries outside
-  // [beg, end) read the neighbouring rows or the padding and are dropped.
-  const int k0 = beg & ~3;
-  int cidx[kStreamChunks][4];
-  T val[kStreamChunks][4];
+  // Phase 1: the block's entries [beg, end) in 4-entry chunks aligned to 4.  The load phase is
+  // branch-free so that every chunk load and every x gather is in flight at once: chunk
+  // positions past the block are clamped to its last chunk, and entries outside [beg, end)
+  // (neighbouring rows or the zero padding, all valid column indices) are gathered but not
+  // stored.
+  if (end > beg) {
+    const int k0 = beg & ~3;
+    const int klast = (end - 1) & ~3;
+    int cidx[kStreamChunks][4];
+    T val[kStreamChunks][4];
+    T xv[kStreamChunks][4];
 #pragma unroll
-  for (int c = 0; c < kStreamChunks; ++c) {
-    const int k = k0 + 4 * ((int)threadIdx.x + kBlock * c);
-    if (k < end) {
+    for (int c = 0; c < kStreamChunks; ++c) {
+      const int k = min(k0 + 4 * ((int)threadIdx.x + kBlock * c), klast);
       const int4 cc = *reinterpret_cast<const int4*>(a.ci + k);
       cidx[c][0] = cc.x; cidx[c][1] = cc.y; cidx[c][2] = cc.z; cidx[c][3] = cc.w;
       load4(a.av + k, val[c]);
     }
-  }
 #pragma unroll
-  for (int c = 0; c < kStreamChunks; ++c) {
-    const int k = k0 + 4 * ((int)threadIdx.x + kBlock * c);
-    if (k < end) {
+    for (int c = 0; c < kStreamChunks; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xv[c][j] = a.x[cidx[c][j]];
+#pragma unroll
+    for (int c = 0; c < kStreamChunks; ++c) {
+      const int k = k0 + 4 * ((int)threadIdx.x + kBlock * c);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int kk = k + j;
-        if (kk >= beg && kk < end) prod[kk - beg] = val[c][j] * a.x[cidx[c][j]];
+        if (kk >= beg && kk < end) prod[kk - beg] = val[c][j] * xv[c][j];
       }
     }
   }
