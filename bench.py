@@ -79,6 +79,72 @@ def cpu_baseline(case, iters: int):
                        f"{dt:.1f} s timed; oracle setup {t_setup:.1f} s untimed)")
 
 
+def bench_solve(args):
+    """Single elliptic solves (f = -A_i v0, zero guess) with the float64 V-cycle as reference."""
+    import torch
+
+    import bidomain_cases as bc
+    import paper_2311_13914_amd as lib
+
+    case = bc.config_case(args.workload)
+    n = case.n
+    rp, ci, vi, m = lib.bidomain_slab_assemble(case, lib.BD_MAT_AI)
+    rpe, cie, ve, _ = lib.bidomain_slab_assemble(case, lib.BD_MAT_AELL)
+    v0 = bc.nodal_v0(case)
+    import scipy.sparse as sp
+    Ai = sp.csr_matrix((vi, ci, rp), shape=(n, n))
+    f = torch.tensor(-(Ai @ v0), dtype=torch.float64, device="cuda")
+    del Ai, vi
+    coarsening = lib.BD_RS if args.coarsening == "rs" else lib.BD_SA
+    thr = 0.5 if args.coarsening == "rs" else 0.06
+    results = {}
+    for prec in ([lib.BD_F64, lib.BD_F32] if args.mixed else [lib.BD_F64]):
+        t = time.perf_counter()
+        h = lib.bidomain_amg_setup((rpe, cie, ve), lib.bidomain_default_opts(
+            nullspace=1, vcycle_precision=prec, coarsening=coarsening, threshold=thr), m)
+        setup_s = time.perf_counter() - t
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            lib.bidomain_pcg_solve(h, f, x, False, args.rtol, 500)
+        its, secs = 0, 0.0
+        for _ in range(args.steps):
+            rc, info = lib.bidomain_pcg_solve(h, f, x, False, args.rtol, 500)
+            assert rc == lib.BD_OK, info
+            its += info["iterations"]
+            secs += info["seconds"]
+        hinfo = lib.bidomain_amg_info(h)
+        lib.bidomain_amg_destroy(h)
+        results[prec] = dict(x=x, its=its, secs=secs, setup_s=setup_s, levels=hinfo["n"],
+                             opc=hinfo["operator_complexity"], res=info["rel_residual_true"],
+                             bytes=hinfo["device_bytes"])
+        print(f"[bench] {'f32' if prec else 'f64'} {args.coarsening}: setup {setup_s:.1f} s, levels "
+              f"{hinfo['n']}, {its / args.steps:.1f} it/solve, {secs / args.steps * 1e3:.2f} ms/solve",
+              file=sys.stderr, flush=True)
+    key = lib.BD_F32 if args.mixed else lib.BD_F64
+    r = results[key]
+    err = None
+    if args.mixed:
+        x64 = results[lib.BD_F64]["x"]
+        err = float(torch.linalg.norm(r["x"] - x64) / torch.linalg.norm(x64))
+    out = {
+        "metric": "elliptic PCG-AMG DOF*iters/s", "value": n * r["its"] / r["secs"], "unit": "DOF*iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["secs"] * 1e3 / args.steps, "higher_is_better": True, "scaling": "strong",
+        "vs_baseline": None, "dtype": "f32-vcycle/f64" if args.mixed else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: single elliptic solve on the {case.nx}x{case.ny}x{case.nz} "
+                               f"slab, n={n}, {args.coarsening.upper()} hierarchy, rtol {args.rtol:g}",
+                   "levels": r["levels"], "operator_complexity": round(r["opc"], 3),
+                   "device_bytes": r["bytes"]},
+        "iters_per_solve": r["its"] / args.steps, "rel_residual_true": r["res"],
+        "rel_error_vs_f64": err, "setup_s": round(r["setup_s"], 1),
+    }
+    if args.mixed:
+        r64 = results[lib.BD_F64]
+        out["f64_reference"] = {"value": n * r64["its"] / r64["secs"], "iters_per_solve": r64["its"] / args.steps,
+                                "ms_per_solve": r64["secs"] * 1e3 / args.steps}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +155,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
+    ap.add_argument("--mode", default="step", choices=["step", "solve"],
+                    help="step: Bidomain time steps (default); solve: repeated single elliptic solves")
+    ap.add_argument("--coarsening", default="sa", choices=["sa", "rs"])
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region, copy 1 GiB once (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -104,6 +173,8 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.mode == "solve":
+        return bench_solve(args)
     case = bc.config_case(args.workload)
     n, nnz = case.n, case.nnz27
     prec = lib.BD_F32 if args.mixed else lib.BD_F64
