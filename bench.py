@@ -145,6 +145,69 @@ def bench_solve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """A seeded stream of slab cases (log-uniform sizes, Poisson arrivals) through the server:
+    float32 V-cycles inside float64 CG, hierarchies and states resident in HBM, admission by
+    device budget and slots, all running solves batched per round."""
+    import torch
+
+    import bidomain_cases as bc
+    import paper_2311_13914_amd as lib
+
+    reqs = bc.serving_stream(n_cases=args.serve_cases, nsteps=args.serve_steps, rate_per_s=args.rate, seed=4)
+    v0s = {r.ticket: bc.nodal_v0(r.case) for r in reqs}
+    prec = lib.BD_F64 if args.no_mixed_serve else lib.BD_F32
+    oe = lib.bidomain_default_opts(vcycle_precision=prec)
+    op = lib.bidomain_default_opts(vcycle_precision=prec, threshold=0.0)  # parabolic default
+    budget = int(args.budget_gb * (1 << 30))
+    srv = lib.bidomain_serve_create(budget, args.slots, oe, op, args.rtol)
+    done, ticket_of, peak = {}, {}, dict(running=0, bytes=0)
+    t0 = time.perf_counter()
+    nxt = 0
+    while len(done) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt].arrival_s <= now:
+            r = reqs[nxt]
+            ticket_of[lib.bidomain_serve_submit(srv, r.case, v0s[r.ticket], r.nsteps)] = r
+            nxt += 1
+        for res in lib.bidomain_serve_poll(srv):
+            done[res["ticket"]] = res
+        st = lib.bidomain_serve_stats(srv)
+        peak["running"] = max(peak["running"], st["running"])
+        peak["bytes"] = max(peak["bytes"], st["bytes_in_use"])
+        if nxt < len(reqs) and st["running"] + st["setting_up"] + st["queued"] == 0:
+            time.sleep(max(0.0, min(0.01, reqs[nxt].arrival_s - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    lat = lib.bidomain_serve_solve_latencies(srv)
+    st = lib.bidomain_serve_stats(srv)
+    lib.bidomain_serve_destroy(srv)
+    bad = [r for r in done.values() if r["status"] != lib.BD_OK]
+    assert not bad, bad[:3]
+    case_lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()])
+    queue_wait = np.array([r["t_admit"] - r["t_submit"] for r in done.values()])
+    dof_its = sum(ticket_of[t].case.n * (r["it_par"] + r["it_ell"]) for t, r in done.items())
+    out = {
+        "metric": "p50/p99 served solve latency", "value": float(np.percentile(lat, 50) * 1e3), "unit": "ms",
+        "n_gpus": 1, "steps": args.serve_steps, "warmup": 0, "ms_per_step": None,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.no_mixed_serve else "f32-vcycle/f64", "data": "synthetic",
+        "config": {"workload": f"C4: {args.serve_cases} slab cases, elements log-uniform 32x32x16..160x160x64, "
+                               f"{args.serve_steps} IMEX steps each, Poisson arrivals {args.rate:g}/s, budget "
+                               f"{args.budget_gb:g} GB, {args.slots} slots, rtol {args.rtol:g}"},
+        "serving": {
+            "solves": int(len(lat)), "p50_solve_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_solve_ms": float(np.percentile(lat, 99) * 1e3),
+            "p50_case_s": float(np.percentile(case_lat, 50)), "p99_case_s": float(np.percentile(case_lat, 99)),
+            "max_case_s": float(case_lat.max()), "mean_queue_wait_s": float(queue_wait.mean()),
+            "makespan_s": wall, "throughput_dof_iters_per_s": dof_its / wall,
+            "rounds": st["rounds"], "peak_running_cases": peak["running"], "peak_bytes": peak["bytes"],
+            "bytes_per_fine_nnz": [round(r["device_bytes"] / ticket_of[t].case.nnz27, 1) for t, r in
+                                   sorted(done.items(), key=lambda kv: ticket_of[kv[0]].case.nnz27)],
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -155,8 +218,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=12)
     ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
-    ap.add_argument("--mode", default="step", choices=["step", "solve"],
-                    help="step: Bidomain time steps (default); solve: repeated single elliptic solves")
+    ap.add_argument("--mode", default="step", choices=["step", "solve", "serve"],
+                    help="step: Bidomain time steps (default); solve: repeated single elliptic solves; "
+                         "serve: a stream of cases through the batching server")
+    ap.add_argument("--serve-cases", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=20)
+    ap.add_argument("--rate", type=float, default=2.0, help="serve: Poisson arrival rate (cases/s)")
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--no-mixed-serve", action="store_true", help="serve: float64 V-cycles")
     ap.add_argument("--coarsening", default="sa", choices=["sa", "rs"])
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region, copy 1 GiB once (HBM counter calibration under rocprofv3)")
@@ -175,11 +245,13 @@ def main():
     torch.cuda.set_device(0)
     if args.mode == "solve":
         return bench_solve(args)
+    if args.mode == "serve":
+        return bench_serve(args)
     case = bc.config_case(args.workload)
     n, nnz = case.n, case.nnz27
     prec = lib.BD_F32 if args.mixed else lib.BD_F64
     opts_e = lib.bidomain_default_opts(vcycle_precision=prec)
-    opts_p = lib.bidomain_default_opts(vcycle_precision=prec)
+    opts_p = lib.bidomain_default_opts(vcycle_precision=prec, threshold=0.0)  # parabolic default
     v0 = torch.tensor(bc.nodal_v0(case), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 

@@ -204,6 +204,9 @@ typedef struct {
  * Create a simulation: assemble A_i, A_e and M, build the elliptic (ell, nullspace forced to
  * BD_NULL_CONSTANT, normalised with the lumped mass) and parabolic (par) hierarchies once
  * (hierarchy reuse, App. A), copy v0 (and w0, NULL = 0), and solve for u_e^0.
+ * ell = NULL: the App. A defaults.  par = NULL: the same with strength threshold 0 (the paper
+ * sets no AMG options for the parabolic system; its mass term weakens every coupling below
+ * 0.06 on coarse meshes, which leaves slowly coarsening, dense hierarchies).
  * v0_dev, w0_dev: n device doubles (read).
  */
 int bidomain_sim_create(const bd_slab* s, const bd_amg_opts* ell, const bd_amg_opts* par,
@@ -221,6 +224,51 @@ int bidomain_sim_get(bd_sim* sim, int field, double* out_dev, void* stream);
 /* Handles of the two hierarchies (owned by the simulation). */
 bd_amg* bidomain_sim_hierarchy(bd_sim* sim, int which /* 0 elliptic, 1 parabolic */);
 void bidomain_sim_destroy(bd_sim* sim);
+
+/* ---- serving: continuous batching of many cases ----------------------------------------- */
+/*
+ * A server admits slab cases (bd_slab + initial v, a number of IMEX steps each) in arrival order
+ * whenever a slot and enough of the device budget are free, builds each case's two hierarchies
+ * on a host worker thread while the GPU serves the admitted ones, keeps every hierarchy and state
+ * vector in HBM for the whole case, and advances all running solves together: one CG iteration of
+ * every running solve per round, each round's products, V-cycle steps (levels aligned across
+ * cases) and reductions issued as multi-task launches that serve all cases at once.  Each solve
+ * computes exactly what it computes alone (its own block partials, fixed reduction order).
+ * Requires the Chebyshev smoother of degree 2 and the same V-cycle precision for both systems.
+ * Times are seconds since bidomain_serve_create.
+ */
+typedef struct bd_server bd_server;
+typedef struct {
+  uint64_t ticket;
+  int32_t status;           /* BD_OK or the first failing status of the case's solves      */
+  int32_t steps;
+  int32_t it_par, it_ell;   /* iterations summed over the case (initial u_e solve included) */
+  double t_submit, t_admit, t_ready, t_done;
+  double max_rel_residual;  /* largest true relative residual over the case's solves       */
+  int64_t device_bytes;     /* HBM the case held while running                             */
+} bd_case_result;
+typedef struct {
+  int32_t queued, setting_up, running, done;
+  int64_t bytes_in_use, budget;
+  int64_t rounds, solves;
+} bd_serve_stats;
+
+/* budget_bytes: HBM the server may hold for cases; max_slots: cases admitted at once. */
+int bidomain_serve_create(int64_t budget_bytes, int32_t max_slots, const bd_amg_opts* ell,
+                          const bd_amg_opts* par, double rtol, void* stream, bd_server** out);
+/* Queue a case (v0_host: n host doubles, copied).  BD_E_BUDGET if it can never fit. */
+int bidomain_serve_submit(bd_server* srv, const bd_slab* slab, const double* v0_host, int32_t nsteps,
+                          uint64_t* ticket);
+/* The device footprint the server assumes for a case before it is on the device (admission). */
+int bidomain_serve_estimate(const bd_server* srv, const bd_slab* slab, int64_t* bytes);
+/* Admit what fits, run one round, and return up to max_results newly completed cases. */
+int bidomain_serve_poll(bd_server* srv, bd_case_result* results, int32_t max_results, int32_t* n_results);
+/* Final v and u_e of a completed case (n host doubles each, either may be NULL); releases them. */
+int bidomain_serve_fetch(bd_server* srv, uint64_t ticket, double* v_host, double* ue_host);
+int bidomain_serve_stats(const bd_server* srv, bd_serve_stats* st);
+/* Wall time of every completed solve (start of its first kernel enqueue to detection). */
+int bidomain_serve_solve_latencies(const bd_server* srv, double* out, int32_t cap, int32_t* count);
+void bidomain_serve_destroy(bd_server* srv);
 
 /*
  * Instrumentation: when enabled, every launch of the fine-level outer product q = A p

@@ -13,6 +13,8 @@ Readings:
     eps^n = eps0 + mu1 w^n / (u^n + mu2), dt' = dt / 12.9;
   * I_ion = -c_m (105 / 12.9) [k u (u - a)(1 - u) - u w^{n+1}] (mA/cm^3), entering the
     parabolic right-hand side as -M I_ion (eq. (1) has I_ion on the left-hand side);
+  * the parabolic hierarchy defaults to strength threshold 0 (the paper sets no AMG options for
+    that system; its mass term weakens the couplings below 0.06 on coarse meshes);
   * order within a step: membrane, parabolic (with u_e^n), elliptic (with v^{n+1}); this is
     the recurrence of eqs. (4)-(7) shifted by half a step, and u_e^0 comes from an elliptic
     solve with v^0.
@@ -69,7 +71,7 @@ def _solve(A, f, h, x0, rtol, m, mixed):
 def create(case, v0, w0=None, rtol=1e-8, ell_opts=None, par_opts=None, mixed=False):
     ops = fem.assemble_operators(case)
     ell_opts = ell_opts or amg.AMGOptions(nullspace=True)
-    par_opts = par_opts or amg.AMGOptions(nullspace=False)
+    par_opts = par_opts or amg.AMGOptions(nullspace=False, threshold=0.0)
     h_ell = amg.setup(ops["Aell"], ell_opts)
     h_par = amg.setup(ops["Apar"], par_opts)
     v = np.array(v0, np.float64)

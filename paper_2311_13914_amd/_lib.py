@@ -70,6 +70,17 @@ class bd_step_info(C.Structure):
                 ("rel_res_ell", C.c_double), ("status", C.c_int32)]
 
 
+class bd_case_result(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("status", C.c_int32), ("steps", C.c_int32), ("it_par", C.c_int32),
+                ("it_ell", C.c_int32), ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_ready", C.c_double),
+                ("t_done", C.c_double), ("max_rel_residual", C.c_double), ("device_bytes", C.c_int64)]
+
+
+class bd_serve_stats(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("setting_up", C.c_int32), ("running", C.c_int32), ("done", C.c_int32),
+                ("bytes_in_use", C.c_int64), ("budget", C.c_int64), ("rounds", C.c_int64), ("solves", C.c_int64)]
+
+
 _vp = C.c_void_p
 _SIGS = {
     "bidomain_default_opts": (None, [C.POINTER(bd_amg_opts)]),
@@ -93,6 +104,16 @@ _SIGS = {
     "bidomain_sim_destroy": (None, [_vp]),
     "bidomain_profile_enable": (None, [C.c_int]),
     "bidomain_profile_read": (None, [C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]),
+    "bidomain_serve_create": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(bd_amg_opts), C.POINTER(bd_amg_opts),
+                                        C.c_double, _vp, C.POINTER(_vp)]),
+    "bidomain_serve_submit": (C.c_int, [_vp, C.POINTER(bd_slab), C.POINTER(C.c_double), C.c_int32,
+                                        C.POINTER(C.c_uint64)]),
+    "bidomain_serve_estimate": (C.c_int, [_vp, C.POINTER(bd_slab), C.POINTER(C.c_int64)]),
+    "bidomain_serve_poll": (C.c_int, [_vp, C.POINTER(bd_case_result), C.c_int32, C.POINTER(C.c_int32)]),
+    "bidomain_serve_fetch": (C.c_int, [_vp, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "bidomain_serve_stats": (C.c_int, [_vp, C.POINTER(bd_serve_stats)]),
+    "bidomain_serve_solve_latencies": (C.c_int, [_vp, C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
+    "bidomain_serve_destroy": (None, [_vp]),
     "bidomain_last_error": (C.c_char_p, []),
 }
 
@@ -348,3 +369,68 @@ def bidomain_profile_read(reset: bool = False):
 
 def bidomain_last_error() -> str:
     return load().bidomain_last_error().decode()
+
+
+# ---- serving -------------------------------------------------------------------------------
+def bidomain_serve_create(budget_bytes: int, max_slots: int, ell_opts=None, par_opts=None, rtol: float = 1e-8,
+                          stream=None):
+    out = _vp()
+    _check(load().bidomain_serve_create(int(budget_bytes), int(max_slots), C.byref(ell_opts) if ell_opts else None,
+                                        C.byref(par_opts) if par_opts else None, float(rtol), _stream(stream),
+                                        C.byref(out)), "bidomain_serve_create")
+    return out.value
+
+
+def bidomain_serve_submit(srv, case, v0, nsteps: int) -> int:
+    """v0: host array of n doubles. Returns the ticket; raises BidomainError (BD_E_BUDGET) if the
+    case can never fit the budget."""
+    s = make_slab(case)
+    n = (s.nx + 1) * (s.ny + 1) * (s.nz + 1)
+    v, pv = _f64(v0)
+    if v.size != n:
+        raise ValueError("v0 must have n entries")
+    t = C.c_uint64()
+    _check(load().bidomain_serve_submit(_vp(srv), C.byref(s), pv, int(nsteps), C.byref(t)), "bidomain_serve_submit")
+    return t.value
+
+
+def bidomain_serve_estimate(srv, case) -> int:
+    s = make_slab(case)
+    b = C.c_int64()
+    _check(load().bidomain_serve_estimate(_vp(srv), C.byref(s), C.byref(b)), "bidomain_serve_estimate")
+    return b.value
+
+
+def bidomain_serve_poll(srv, max_results: int = 64):
+    res = (bd_case_result * max_results)()
+    cnt = C.c_int32()
+    _check(load().bidomain_serve_poll(_vp(srv), res, int(max_results), C.byref(cnt)), "bidomain_serve_poll")
+    return [{f[0]: getattr(res[i], f[0]) for f in bd_case_result._fields_} for i in range(cnt.value)]
+
+
+def bidomain_serve_fetch(srv, ticket: int, n: int):
+    v = np.empty(n, np.float64)
+    ue = np.empty(n, np.float64)
+    _check(load().bidomain_serve_fetch(_vp(srv), C.c_uint64(ticket), v.ctypes.data_as(C.POINTER(C.c_double)),
+                                       ue.ctypes.data_as(C.POINTER(C.c_double))), "bidomain_serve_fetch")
+    return v, ue
+
+
+def bidomain_serve_stats(srv) -> dict:
+    st = bd_serve_stats()
+    _check(load().bidomain_serve_stats(_vp(srv), C.byref(st)), "bidomain_serve_stats")
+    return {f[0]: getattr(st, f[0]) for f in bd_serve_stats._fields_}
+
+
+def bidomain_serve_solve_latencies(srv):
+    cnt = C.c_int32()
+    _check(load().bidomain_serve_solve_latencies(_vp(srv), None, 0, C.byref(cnt)), "bidomain_serve_solve_latencies")
+    out = np.empty(cnt.value, np.float64)
+    _check(load().bidomain_serve_solve_latencies(_vp(srv), out.ctypes.data_as(C.POINTER(C.c_double)), cnt.value,
+                                                 C.byref(cnt)), "bidomain_serve_solve_latencies")
+    return out
+
+
+def bidomain_serve_destroy(srv):
+    if srv:
+        load().bidomain_serve_destroy(_vp(srv))

@@ -761,6 +761,24 @@ __global__ __launch_bounds__(kBlock) void k_neg_spmv(const int* __restrict__ rp,
   if (lane == 0) y[row] = -s;
 }
 
+// Second half of the setup phase: copy a host-built hierarchy into HBM and allocate the
+// solve state.  weights: n host doubles (normalisation weights) or null.
+void device_upload(bd_amg* h, const double* weights, hipStream_t st) {
+  h->A0 = upload<double>(h->ar, h->H.lv[0].A, nullptr, nullptr, st, kMaxBlocksSpmv);
+  if (h->mixed) build_levels<float>(h, st);
+  else build_levels<double>(h, st);
+  if (h->H.coarse_mode == 0) {
+    h->nM = h->H.lv.back().A.nrows;
+    h->G = upload_vec<double>(h->ar, h->H.G, st);
+  }
+  if (h->o.nullspace == BD_NULL_CONSTANT && weights) {
+    std::vector<double> wv(weights, weights + h->n);
+    h->w = upload_vec<double>(h->ar, wv, st);
+  }
+  alloc_solve_state(h, st);
+  h->host_only = false;
+}
+
 int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, hipStream_t st, bd_amg** out,
                bool host_only = false) {
   if (!A || !out) throw Failure{BD_E_INVALID, "null argument"};
@@ -792,27 +810,83 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   const int rc = build_hierarchy(H, o, h->H, err);
   if (rc != BD_OK) throw Failure{rc, err};
   h->M = (int)h->H.lv.size() - 1;
-  h->host_only = host_only;
-  if (host_only) {
-    *out = h.release();
-    return BD_OK;
-  }
-
-  h->A0 = upload<double>(h->ar, h->H.lv[0].A, nullptr, nullptr, st, kMaxBlocksSpmv);
-  if (h->mixed) build_levels<float>(h.get(), st);
-  else build_levels<double>(h.get(), st);
-  if (h->H.coarse_mode == 0) {
-    h->nM = h->H.lv.back().A.nrows;
-    h->G = upload_vec<double>(h->ar, h->H.G, st);
-  }
-  if (o.nullspace == BD_NULL_CONSTANT && weights) {
-    std::vector<double> wv(weights, weights + A->n);
-    h->w = upload_vec<double>(h->ar, wv, st);
-  }
-  alloc_solve_state(h.get(), st);
+  h->host_only = true;
+  if (!host_only) device_upload(h.get(), weights, st);
   *out = h.release();
   return BD_OK;
 }
+
+// Host half of a simulation: assembled operators and host-built hierarchies (no device work,
+// so it may run on a worker thread while the GPU serves other cases).
+struct SimHost {
+  bd_slab s{};
+  Csr Ai;
+  std::vector<double> m;
+  bd_amg* hell = nullptr;
+  bd_amg* hpar = nullptr;
+  ~SimHost() {
+    delete hell;
+    delete hpar;
+  }
+};
+
+std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell, const bd_amg_opts* par) {
+  std::unique_ptr<SimHost> H(new SimHost());
+  H->s = s;
+  const int n = (int)slab_nodes(s);
+  Csr Ae;
+  assemble_slab_stiffness(s, s.sig_il, s.sig_it, H->Ai);
+  assemble_slab_stiffness(s, s.sig_el, s.sig_et, Ae);
+  slab_lumped_mass(s, H->m);
+  Csr Aell = H->Ai, Apar = H->Ai;
+  for (size_t k = 0; k < Aell.v.size(); ++k) Aell.v[k] += Ae.v[k];
+  for (int32_t i = 0; i < Apar.nrows; ++i)
+    for (int32_t k = Apar.rp[i]; k < Apar.rp[i + 1]; ++k)
+      if (Apar.ci[k] == i) Apar.v[k] += s.cm / s.dt * H->m[i];
+  bd_amg_opts oe, op;
+  bidomain_default_opts(&oe);
+  bidomain_default_opts(&op);
+  op.threshold = 0.0;  // parabolic default: see bidomain_sim_create
+  if (ell) oe = *ell;
+  if (par) op = *par;
+  oe.nullspace = BD_NULL_CONSTANT;
+  op.nullspace = BD_NULL_NONE;
+  bd_csr ce{n, Aell.nnz(), Aell.rp.data(), Aell.ci.data(), Aell.v.data()};
+  bd_csr cp{n, Apar.nnz(), Apar.rp.data(), Apar.ci.data(), Apar.v.data()};
+  setup_impl(&ce, &oe, nullptr, nullptr, &H->hell, true);
+  setup_impl(&cp, &op, nullptr, nullptr, &H->hpar, true);
+  return H;
+}
+
+// Device half: hierarchies, A_i, the lumped mass and the state vectors in HBM (takes the
+// hierarchies from H).  v0 / w0: n doubles on the device or the host (w0 may be null: w = 0).
+std::unique_ptr<bd_sim> upload_sim(SimHost& H, const double* v0, bool v0_dev, const double* w0, bool w0_dev,
+                                   hipStream_t st) {
+  std::unique_ptr<bd_sim> S(new bd_sim());
+  S->s = H.s;
+  S->n = (int)slab_nodes(H.s);
+  const int n = S->n;
+  S->hell = H.hell;
+  S->hpar = H.hpar;
+  H.hell = H.hpar = nullptr;
+  device_upload(S->hell, H.m.data(), st);
+  device_upload(S->hpar, nullptr, st);
+  S->Ai = upload<double>(S->ar, H.Ai, S->hell->A0.rp, S->hell->A0.ci, st, kMaxBlocksSpmv);
+  S->v = S->ar.alloc<double>(n);
+  S->ue = S->ar.alloc<double>(n);
+  S->w = S->ar.alloc<double>(n);
+  S->rhs = S->ar.alloc<double>(n);
+  S->fell = S->ar.alloc<double>(n);
+  S->m = upload_vec<double>(S->ar, H.m, st);
+  HIPCHK(hipMemcpyAsync(S->v, v0, sizeof(double) * n, v0_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  if (w0) HIPCHK(hipMemcpyAsync(S->w, w0, sizeof(double) * n, w0_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
+  else HIPCHK(hipMemsetAsync(S->w, 0, sizeof(double) * n, st));
+  HIPCHK(hipMemsetAsync(S->ue, 0, sizeof(double) * n, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return S;
+}
+
+int64_t sim_device_bytes(const bd_sim* S) { return S->ar.bytes + S->hell->ar.bytes + S->hpar->ar.bytes; }
 
 }  // namespace bd
 
@@ -1036,42 +1110,8 @@ int bidomain_sim_create(const bd_slab* s, const bd_amg_opts* ell, const bd_amg_o
     check_slab(s);
     if (!v0_dev || !out || !(rtol > 0)) throw Failure{BD_E_INVALID, "invalid simulation arguments"};
     hipStream_t st = (hipStream_t)stream;
-    std::unique_ptr<bd_sim> S(new bd_sim());
-    S->s = *s;
-    S->n = (int)slab_nodes(*s);
-    const int n = S->n;
-    Csr Ai, Ae;
-    std::vector<double> m;
-    assemble_slab_stiffness(*s, s->sig_il, s->sig_it, Ai);
-    assemble_slab_stiffness(*s, s->sig_el, s->sig_et, Ae);
-    slab_lumped_mass(*s, m);
-    Csr Aell = Ai, Apar = Ai;
-    for (size_t k = 0; k < Ai.v.size(); ++k) Aell.v[k] += Ae.v[k];
-    for (int32_t i = 0; i < Ai.nrows; ++i)
-      for (int32_t k = Ai.rp[i]; k < Ai.rp[i + 1]; ++k)
-        if (Ai.ci[k] == i) Apar.v[k] += s->cm / s->dt * m[i];
-    bd_amg_opts oe, op;
-    bidomain_default_opts(&oe);
-    bidomain_default_opts(&op);
-    if (ell) oe = *ell;
-    if (par) op = *par;
-    oe.nullspace = BD_NULL_CONSTANT;
-    op.nullspace = BD_NULL_NONE;
-    bd_csr ce{n, Aell.nnz(), Aell.rp.data(), Aell.ci.data(), Aell.v.data()};
-    bd_csr cp{n, Apar.nnz(), Apar.rp.data(), Apar.ci.data(), Apar.v.data()};
-    setup_impl(&ce, &oe, m.data(), st, &S->hell);
-    setup_impl(&cp, &op, nullptr, st, &S->hpar);
-    S->Ai = upload<double>(S->ar, Ai, S->hell->A0.rp, S->hell->A0.ci, st, kMaxBlocksSpmv);
-    S->v = S->ar.alloc<double>(n);
-    S->ue = S->ar.alloc<double>(n);
-    S->w = S->ar.alloc<double>(n);
-    S->rhs = S->ar.alloc<double>(n);
-    S->fell = S->ar.alloc<double>(n);
-    S->m = upload_vec<double>(S->ar, m, st);
-    HIPCHK(hipMemcpyAsync(S->v, v0_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    if (w0_dev) HIPCHK(hipMemcpyAsync(S->w, w0_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    else HIPCHK(hipMemsetAsync(S->w, 0, sizeof(double) * n, st));
-    HIPCHK(hipMemsetAsync(S->ue, 0, sizeof(double) * n, st));
+    std::unique_ptr<SimHost> H = build_sim_host(*s, ell, par);
+    std::unique_ptr<bd_sim> S = upload_sim(*H, v0_dev, true, w0_dev, true, st);
     // u_e^0 from v^0 (eq. (6))
     launch_neg_spmv(S.get(), S->v, S->fell, st);
     bd_solve_info inf;
@@ -1154,5 +1194,690 @@ void bidomain_profile_read(double* total_ms, int64_t* launches, int reset) {
     g_prof.launches = 0;
   }
 }
+
+}  // extern "C"
+
+// ==========================================================================================
+// Serving: continuous batching of many Bidomain cases.
+#include <array>
+#include <chrono>
+#include <deque>
+#include <functional>
+#include <future>
+#include <map>
+#include <thread>
+
+namespace bd {
+
+// Task tables of the multi-task launches: each launch copies its table from a pinned host ring
+// into the same slice of a device buffer (the ring restarts after each round's synchronisation).
+struct Staging {
+  char* host = nullptr;
+  char* dev = nullptr;
+  size_t cap = 0, used = 0;
+  void init(size_t bytes) {
+    HIPCHK(hipHostMalloc(&host, bytes, hipHostMallocDefault));
+    HIPCHK(hipMalloc(&dev, bytes));
+    cap = bytes;
+  }
+  ~Staging() {
+    if (host) (void)hipHostFree(host);
+    if (dev) (void)hipFree(dev);
+  }
+  template <class Task>
+  const Task* push(const std::vector<Task>& v, hipStream_t st) {
+    const size_t bytes = v.size() * sizeof(Task);
+    const size_t off = (used + 255) & ~size_t(255);
+    if (off + bytes > cap) throw Failure{BD_E_NOMEM, "serving task staging buffer exhausted"};
+    std::memcpy(host + off, v.data(), bytes);
+    HIPCHK(hipMemcpyAsync(dev + off, host + off, bytes, hipMemcpyHostToDevice, st));
+    used = off + bytes;
+    return reinterpret_cast<const Task*>(dev + off);
+  }
+};
+
+template <class Task, class Launch>
+void launch_tasks(std::vector<Task>& v, hipStream_t st, Staging& stg, Launch launch) {
+  if (v.empty()) return;
+  int off = 0;
+  for (auto& t : v) {
+    t.off = off;
+    off += t.nb;
+  }
+  const Task* d = stg.push(v, st);
+  launch(d, (int)v.size(), off);
+  HIPCHK(hipGetLastError());
+  v.clear();
+}
+
+// One sub-step of a round across all solves: the ops it collects are independent.
+template <typename T>
+struct Batch {
+  std::vector<SpTask<T>> sp[OP_TRUE_RESID + 1];
+  std::vector<SpTask<double>> cgq;  // outer products (always float64)
+  std::vector<UpdTask<T>> upd;
+  std::vector<DirTask<T>> dir;
+  std::vector<GemvTask<T>> gemv;
+  std::vector<FinTask> fin;
+  std::vector<std::function<void()>> single;  // ops without a multi-task kernel, launched alone
+
+  template <int OP>
+  void add(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
+    if (M.n == 0) return;
+    if (!M.blk) {  // rows longer than the staging buffer: lane-group kernel, one launch
+      single.push_back([=] { launch_spmv<T, OP>(M, a, st); });
+      return;
+    }
+    a.rp = M.rp;
+    a.ci = M.ci;
+    a.av = M.v;
+    a.nrows = M.n;
+    a.tpb = M.tpb;
+    SpTask<T> t;
+    t.a = a;
+    t.blk = M.blk;
+    t.nb = M.nb;
+    t.off = 0;
+    sp[OP].push_back(t);
+  }
+
+  void flush(hipStream_t st, Staging& stg) {
+    for (auto& f : single) f();
+    single.clear();
+#define BD_SPL(OPV)                                                                                      \
+  launch_tasks(sp[OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                                \
+    k_spmv_stream_multi<T, OPV><<<nb, kBlock, 0, st>>>(d, n);                                            \
+  });
+    BD_SPL(OP_Y)
+    BD_SPL(OP_ADDY)
+    BD_SPL(OP_RESID)
+    BD_SPL(OP_RESTRICT)
+    BD_SPL(OP_CHEB_FIRST)
+    BD_SPL(OP_CHEB_POST0)
+    BD_SPL(OP_CHEB_STEP)
+#undef BD_SPL
+    launch_tasks(cgq, st, stg, [&](const SpTask<double>* d, int n, int nb) {
+      k_spmv_stream_multi<double, OP_CG_Q><<<nb, kBlock, 0, st>>>(d, n);
+    });
+    launch_tasks(upd, st, stg, [&](const UpdTask<T>* d, int n, int nb) { k_cg_update_multi<T><<<nb, kBlock, 0, st>>>(d, n); });
+    launch_tasks(dir, st, stg, [&](const DirTask<T>* d, int n, int nb) { k_cg_direction_multi<T><<<nb, kBlock, 0, st>>>(d, n); });
+    launch_tasks(gemv, st, stg, [&](const GemvTask<T>* d, int n, int nb) { k_coarse_gemv_multi<T><<<nb, kBlock, 0, st>>>(d, n); });
+    launch_tasks(fin, st, stg, [&](const FinTask* d, int n, int nb) { k_finalize_multi<<<nb, kBlock, 0, st>>>(d, n); });
+  }
+};
+
+// One PCG / FCG solve in flight on a hierarchy.
+struct BInst {
+  bd_amg* h = nullptr;
+  const double* b = nullptr;
+  double* x = nullptr;
+  int guess = 0;
+  double rtol = 1e-8;
+  int maxit = 1000;
+  int state = -1;  // -1 idle, 0 new (initial phase enqueued this round), 1 running
+  int cur = 0;     // float right-hand-side buffer in use (mixed form)
+  RedSpec red;
+  std::chrono::steady_clock::time_point t0;
+};
+
+FinTask fin_task(const Solve& sv, int kind, int nb_part) {
+  FinTask f;
+  f.sv = sv;
+  f.kind = kind;
+  f.nb_part = nb_part;
+  f.nb = 1;
+  f.off = 0;
+  return f;
+}
+
+// Initial phase of a solve (as in pcg(), without the host synchronisation).
+template <typename T>
+void inst_begin(BInst& I, hipStream_t st) {
+  bd_amg* h = I.h;
+  const Solve& sv = h->sv;
+  const int n = h->n;
+  const int vb = vec_blocks(n);
+  h->host_flags[0] = h->host_flags[1] = 0;
+  k_solve_control<<<1, 64, 0, st>>>(sv, 0, I.maxit, h->o.nullspace == BD_NULL_CONSTANT, I.rtol * I.rtol);
+  k_init_means<<<vb, kBlock, 0, st>>>(sv, I.b, I.guess ? I.x : nullptr, n);
+  HIPCHK(hipGetLastError());
+  finalize(sv, FIN_MEANS, vb, st);
+  k_init_guess<<<vb, kBlock, 0, st>>>(sv, I.x, I.guess, n);
+  HIPCHK(hipGetLastError());
+  SpArgs<double> a = args<double>(sv);
+  a.x = I.x;
+  a.y = h->r;
+  a.b = I.b;
+  launch_spmv<double, OP_INIT_RESID>(h->A0, a, st);
+  finalize(sv, FIN_INIT, h->A0.nb, st);
+  auto& L = levels<T>(h);
+  I.cur = 0;
+  I.red = RedSpec{};
+  if (h->mixed) {
+    k_convert<double, float><<<vb, kBlock, 0, st>>>(h->r, h->r32[0], n);
+    HIPCHK(hipGetLastError());
+    L[0].f = (T*)h->r32[0];
+    I.red.red = RED_F32;
+    I.red.r32 = h->r32[0];
+    I.red.r32_old = h->r32[0];
+  } else {
+    L[0].f = (T*)h->r;
+    I.red.red = RED_F64;
+    I.red.r64 = h->r;
+  }
+  I.state = 0;
+}
+
+// V-cycles of several solves at once (Alg. 2), levels aligned: the down sweep visits level k
+// of every solve whose hierarchy reaches it (a solve whose coarsest level is k solves there),
+// then the up sweep returns.  Chebyshev degree 2.
+template <typename T>
+void batched_vcycle(std::vector<BInst*>& I, Batch<T>& B, hipStream_t st, Staging& stg) {
+  int maxM = 0;
+  for (BInst* i : I) maxM = std::max(maxM, i->h->M);
+  for (int k = 0; k <= maxM; ++k) {
+    if (k == 0)
+      for (BInst* i : I) {
+        bd_amg* h = i->h;
+        DLevel<T>& L0 = levels<T>(h)[0];
+        if (i->state == 0 && smoothed_level(h, 0)) {
+          const Solve sv = h->sv;
+          B.single.push_back([=] {
+            k_cheb_pre0<T><<<vec_blocks(L0.n), kBlock, 0, st>>>(sv, L0.f, L0.dinv, L0.da, nullptr, L0.c0, L0.n);
+          });
+        }
+      }
+    B.flush(st, stg);
+    for (BInst* i : I) {  // pre-smoothing step 1, or the coarsest solve
+      bd_amg* h = i->h;
+      if (k > h->M) continue;
+      DLevel<T>& Lk = levels<T>(h)[k];
+      if (k == h->M && h->H.coarse_mode == 0) {
+        GemvTask<T> g;
+        g.sv = h->sv; g.G = h->G; g.f = Lk.f; g.x = Lk.x; g.n = h->nM; g.nb = (h->nM + 3) / 4; g.off = 0;
+        B.gemv.push_back(g);
+      } else {
+        SpArgs<T> a = args<T>(h->sv);
+        a.x = Lk.da; a.xs = Lk.x; a.f = Lk.f; a.dinv = Lk.dinv; a.c1 = Lk.c1[0]; a.c2 = Lk.c2[0];
+        a.store_rd = 0; a.r = Lk.r; a.y2 = Lk.db;
+        B.template add<OP_CHEB_FIRST>(Lk.A, a, st);
+      }
+    }
+    B.flush(st, stg);
+    for (BInst* i : I) {  // residual
+      bd_amg* h = i->h;
+      if (k >= h->M) continue;
+      DLevel<T>& Lk = levels<T>(h)[k];
+      SpArgs<T> a = args<T>(h->sv);
+      a.x = Lk.x; a.f = Lk.f; a.y = Lk.r;
+      B.template add<OP_RESID>(Lk.A, a, st);
+    }
+    B.flush(st, stg);
+    for (BInst* i : I) {  // restriction (+ first smoothing step of the next level)
+      bd_amg* h = i->h;
+      if (k >= h->M) continue;
+      auto& L = levels<T>(h);
+      DLevel<T>& Lk = L[k];
+      DLevel<T>& Ln = L[k + 1];
+      SpArgs<T> a = args<T>(h->sv);
+      a.x = Lk.r; a.y = Ln.f;
+      if (smoothed_level(h, k + 1)) {
+        a.y2 = Ln.da; a.dinv2 = Ln.dinv; a.c0 = Ln.c0; a.xs = nullptr;
+        B.template add<OP_RESTRICT>(Lk.R, a, st);
+      } else {
+        B.template add<OP_Y>(Lk.R, a, st);
+      }
+    }
+    B.flush(st, stg);
+  }
+  for (int k = maxM - 1; k >= 0; --k) {
+    for (BInst* i : I) {  // prolongation and correction
+      bd_amg* h = i->h;
+      if (k >= h->M) continue;
+      auto& L = levels<T>(h);
+      SpArgs<T> a = args<T>(h->sv);
+      a.x = L[k + 1].x; a.y = L[k].x;
+      B.template add<OP_ADDY>(L[k].P, a, st);
+    }
+    B.flush(st, stg);
+    for (BInst* i : I) {  // post-smoothing step 0
+      bd_amg* h = i->h;
+      if (k >= h->M) continue;
+      DLevel<T>& Lk = levels<T>(h)[k];
+      SpArgs<T> a = args<T>(h->sv);
+      a.x = Lk.x; a.f = Lk.f; a.r = Lk.r; a.y2 = Lk.da; a.dinv = Lk.dinv; a.c0 = Lk.c0;
+      B.template add<OP_CHEB_POST0>(Lk.A, a, st);
+    }
+    B.flush(st, stg);
+    for (BInst* i : I) {  // post-smoothing step 1 (+ level-0 CG reductions)
+      bd_amg* h = i->h;
+      if (k >= h->M) continue;
+      DLevel<T>& Lk = levels<T>(h)[k];
+      SpArgs<T> a = args<T>(h->sv);
+      a.x = Lk.da; a.xs = Lk.x; a.r = Lk.r; a.dinv = Lk.dinv; a.c1 = Lk.c1[0]; a.c2 = Lk.c2[0];
+      a.add_d = 1; a.store_rd = 0; a.y2 = Lk.db;
+      if (k == 0) {
+        a.red = i->red.red; a.r64 = i->red.r64; a.r32 = i->red.r32; a.r32_old = i->red.r32_old;
+      }
+      B.template add<OP_CHEB_STEP>(Lk.A, a, st);
+    }
+    B.flush(st, stg);
+  }
+}
+
+// One round: one CG iteration of every running solve, and the first V-cycle of every new one.
+template <typename T>
+void batched_round(std::vector<BInst*>& I, hipStream_t st, Staging& stg) {
+  Batch<T> B;
+  std::vector<BInst*> run;
+  for (BInst* i : I)
+    if (i->state == 1) run.push_back(i);
+  for (BInst* i : run) {  // q = A p
+    const DCsr<double>& M = i->h->A0;
+    SpArgs<double> a = args<double>(i->h->sv);
+    a.x = i->h->p; a.y = i->h->q;
+    if (M.blk) {
+      a.rp = M.rp; a.ci = M.ci; a.av = M.v; a.nrows = M.n; a.tpb = M.tpb;
+      SpTask<double> t;
+      t.a = a; t.blk = M.blk; t.nb = M.nb; t.off = 0;
+      B.cgq.push_back(t);
+    } else {
+      const DCsr<double> Mc = M;
+      B.single.push_back([=] { launch_spmv<double, OP_CG_Q>(Mc, a, st); });
+    }
+  }
+  B.flush(st, stg);
+  for (BInst* i : run) B.fin.push_back(fin_task(i->h->sv, FIN_CGQ, i->h->A0.nb));
+  B.flush(st, stg);
+  for (BInst* i : run) {  // x, r update and the next V-cycle's right-hand side
+    bd_amg* h = i->h;
+    auto& L = levels<T>(h);
+    const bool fuse0 = smoothed_level(h, 0);
+    UpdTask<T> u;
+    u.sv = h->sv; u.x = i->x; u.r = h->r; u.p = h->p; u.q = h->q;
+    u.r32 = h->mixed ? h->r32[i->cur ^ 1] : nullptr;
+    u.dinv0 = L[0].dinv; u.d0 = fuse0 ? L[0].da : nullptr; u.x0 = nullptr; u.c0 = L[0].c0;
+    u.n = h->n; u.nb = vec_blocks(h->n); u.off = 0;
+    B.upd.push_back(u);
+    if (h->mixed) {
+      i->red.r32_old = h->r32[i->cur];
+      i->red.r32 = h->r32[i->cur ^ 1];
+      L[0].f = (T*)h->r32[i->cur ^ 1];
+      i->cur ^= 1;
+    }
+  }
+  B.flush(st, stg);
+  for (BInst* i : run) B.fin.push_back(fin_task(i->h->sv, FIN_UPDATE, vec_blocks(i->h->n)));
+  B.flush(st, stg);
+  batched_vcycle<T>(I, B, st, stg);
+  for (BInst* i : I) {  // level-0 reductions -> rho, beta
+    bd_amg* h = i->h;
+    const int kind = i->red.red == RED_F64 ? FIN_VC64 : FIN_VC32;
+    if (h->M == 0) {  // no fused post-smoothing on level 0
+      DLevel<T>& L0 = levels<T>(h)[0];
+      SpArgs<T> a = args<T>(h->sv);
+      a.nrows = L0.n; a.red = i->red.red; a.r64 = i->red.r64; a.r32 = i->red.r32; a.r32_old = i->red.r32_old;
+      const int nb = vec_blocks(L0.n);
+      const T* z = L0.x;
+      B.single.push_back([=] { k_vc_reduce<T><<<nb, kBlock, 0, st>>>(a, z); });
+      B.flush(st, stg);
+      B.fin.push_back(fin_task(h->sv, kind, nb));
+    } else {
+      B.fin.push_back(fin_task(h->sv, kind, levels<T>(h)[0].A.nb));
+    }
+  }
+  B.flush(st, stg);
+  for (BInst* i : I) {
+    DirTask<T> d;
+    d.sv = i->h->sv; d.p = i->h->p; d.z = levels<T>(i->h)[0].x; d.n = i->h->n; d.nb = vec_blocks(i->h->n); d.off = 0;
+    B.dir.push_back(d);
+  }
+  B.flush(st, stg);
+  for (BInst* i : I)
+    if (i->state == 0) {
+      k_clear_first<<<1, 64, 0, st>>>(i->h->sv);
+      HIPCHK(hipGetLastError());
+      i->state = 1;
+    }
+}
+
+// Exit phase of a finished solve: true residual and null-space normalisation.
+void inst_exit(BInst& I, hipStream_t st) {
+  bd_amg* h = I.h;
+  const Solve& sv = h->sv;
+  const int vb = vec_blocks(h->n);
+  k_solve_control<<<1, 64, 0, st>>>(sv, 1, 0, 0, 0.0);
+  SpArgs<double> a = args<double>(sv);
+  a.x = I.x;
+  a.b = I.b;
+  launch_spmv<double, OP_TRUE_RESID>(h->A0, a, st);
+  finalize(sv, FIN_TRUE, h->A0.nb, st);
+  if (h->o.nullspace == BD_NULL_CONSTANT) {
+    k_norm_sums<<<vb, kBlock, 0, st>>>(sv, h->w, I.x, h->n);
+    HIPCHK(hipGetLastError());
+    finalize(sv, FIN_NORM, vb, st);
+    k_norm_apply<<<vb, kBlock, 0, st>>>(sv, I.x, h->n);
+    HIPCHK(hipGetLastError());
+  }
+}
+
+}  // namespace bd
+
+struct ServedCase {
+  uint64_t ticket = 0;
+  bd_slab s{};
+  int nsteps = 0;
+  std::vector<double> v0;
+  double t_submit = 0, t_admit = 0, t_ready = 0, t_done = 0;
+  int state = 0;  // 0 queued, 1 host setup, 2 running, 3 done, 4 fetched
+  int64_t est = 0, bytes = 0;
+  std::future<std::unique_ptr<SimHost>> fut;
+  std::unique_ptr<bd_sim> sim;
+  int stage = 0;  // 0 initial elliptic solve, 1 parabolic, 2 elliptic
+  int steps_done = 0;
+  BInst inst;
+  int it_par = 0, it_ell = 0;
+  double max_res = 0.0;
+  int status = BD_OK;
+  std::vector<double> v_out, ue_out;
+};
+
+struct bd_server {
+  int64_t budget = 0, used = 0;
+  int max_slots = 1, admitted = 0, setups = 0;
+  bd_amg_opts oe{}, op{};
+  double rtol = 1e-8;
+  hipStream_t st = nullptr;
+  bool mixed = false;
+  std::deque<ServedCase*> queue;
+  std::vector<std::unique_ptr<ServedCase>> cases;
+  std::map<uint64_t, ServedCase*> by_ticket;
+  std::vector<ServedCase*> live;
+  std::deque<ServedCase*> unreported;
+  Staging stg;
+  std::vector<double> solve_lat;
+  int64_t rounds = 0, solves = 0;
+  uint64_t next_ticket = 1;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+  ~bd_server() {
+    for (auto& c : cases)
+      if (c->fut.valid()) c->fut.wait();
+  }
+};
+
+namespace bd {
+
+constexpr int kMaxConcurrentSetups = 2;
+
+// Device footprint estimate used for admission (bytes per 27-point nonzero of the fine mesh,
+// covering both hierarchies, A_i and the state vectors); replaced by the measured footprint
+// once the case is on the device.
+int64_t case_estimate(const bd_slab& s) { return (int64_t)120 * ((int64_t)(3 * s.nx + 1) * (3 * s.ny + 1) * (3 * s.nz + 1)); }
+
+void start_solve(bd_server* S, ServedCase* c, bd_amg* h, const double* b, double* x, int guess) {
+  c->inst = BInst{};
+  c->inst.h = h;
+  c->inst.b = b;
+  c->inst.x = x;
+  c->inst.guess = guess;
+  c->inst.rtol = S->rtol;
+  c->inst.maxit = 1000;
+  c->inst.t0 = std::chrono::steady_clock::now();
+  if (S->mixed) inst_begin<float>(c->inst, S->st);
+  else inst_begin<double>(c->inst, S->st);
+}
+
+int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_results) {
+  hipStream_t st = S->st;
+  // admission in arrival order, against free slots and the device budget
+  while (!S->queue.empty() && S->admitted < S->max_slots && S->setups < kMaxConcurrentSetups) {
+    ServedCase* c = S->queue.front();
+    if (S->used + c->est > S->budget) break;
+    S->queue.pop_front();
+    S->admitted++;
+    S->setups++;
+    S->used += c->est;
+    c->state = 1;
+    c->t_admit = S->now();
+    const bd_slab slab = c->s;
+    const bd_amg_opts oe = S->oe, op = S->op;
+    c->fut = std::async(std::launch::async, [slab, oe, op] { return build_sim_host(slab, &oe, &op); });
+    S->live.push_back(c);
+  }
+  // cases whose host setup finished: upload and start the initial elliptic solve
+  for (ServedCase* c : S->live) {
+    if (c->state != 1 || c->fut.wait_for(std::chrono::seconds(0)) != std::future_status::ready) continue;
+    S->setups--;
+    std::unique_ptr<SimHost> H;
+    try {
+      H = c->fut.get();
+    } catch (const Failure& e) {
+      c->status = e.code;
+    } catch (...) {
+      c->status = BD_E_INVALID;
+    }
+    if (!H) {  // host setup failed: retire the case
+      S->used -= c->est;
+      S->admitted--;
+      c->state = 3;
+      c->t_done = S->now();
+      S->unreported.push_back(c);
+      continue;
+    }
+    c->sim = upload_sim(*H, c->v0.data(), false, nullptr, false, st);
+    c->bytes = sim_device_bytes(c->sim.get());
+    S->used += c->bytes - c->est;
+    c->state = 2;
+    c->t_ready = S->now();
+    c->stage = 0;
+    launch_neg_spmv(c->sim.get(), c->sim->v, c->sim->fell, st);
+    start_solve(S, c, c->sim->hell, c->sim->fell, c->sim->ue, 0);
+  }
+  std::vector<BInst*> act;
+  std::vector<ServedCase*> act_cases;
+  for (ServedCase* c : S->live)
+    if (c->state == 2) {
+      act.push_back(&c->inst);
+      act_cases.push_back(c);
+    }
+  if (!act.empty()) {
+    S->stg.used = 0;
+    if (S->mixed) batched_round<float>(act, st, S->stg);
+    else batched_round<double>(act, st, S->stg);
+    HIPCHK(hipStreamSynchronize(st));
+    S->rounds++;
+    // finished solves: exit phase, then read their scalars
+    std::vector<ServedCase*> fin;
+    for (ServedCase* c : act_cases)
+      if (__atomic_load_n(&c->inst.h->host_flags[0], __ATOMIC_ACQUIRE)) fin.push_back(c);
+    for (ServedCase* c : fin) inst_exit(c->inst, st);
+    std::vector<std::array<double, S_COUNT>> sc(fin.size());
+    std::vector<std::array<int, F_COUNT>> fl(fin.size());
+    for (size_t j = 0; j < fin.size(); ++j) {
+      HIPCHK(hipMemcpyAsync(sc[j].data(), fin[j]->inst.h->sv.sc, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(fl[j].data(), fin[j]->inst.h->sv.fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    const auto tnow = std::chrono::steady_clock::now();
+    for (size_t j = 0; j < fin.size(); ++j) {
+      ServedCase* c = fin[j];
+      S->solves++;
+      S->solve_lat.push_back(std::chrono::duration<double>(tnow - c->inst.t0).count());
+      const double fn = sc[j][S_FNORM2];
+      const double res = fn > 0 ? std::sqrt(sc[j][S_TRUE2] / fn) : 0.0;
+      c->max_res = std::max(c->max_res, res);
+      if (fl[j][F_STATUS] != 0 && c->status == BD_OK) c->status = fl[j][F_STATUS];
+      if (fn == 0.0) HIPCHK(hipMemsetAsync(c->inst.x, 0, sizeof(double) * c->inst.h->n, st));
+      if (c->stage == 1) c->it_par += fl[j][F_ITERS]; else c->it_ell += fl[j][F_ITERS];
+      c->inst.state = -1;
+      bd_sim* sim = c->sim.get();
+      if (c->stage == 0 || c->stage == 2) {
+        if (c->stage == 2) c->steps_done++;
+        if (c->steps_done >= c->nsteps || c->status < 0) {
+          c->v_out.resize(sim->n);
+          c->ue_out.resize(sim->n);
+          HIPCHK(hipMemcpyAsync(c->v_out.data(), sim->v, sizeof(double) * sim->n, hipMemcpyDeviceToHost, st));
+          HIPCHK(hipMemcpyAsync(c->ue_out.data(), sim->ue, sizeof(double) * sim->n, hipMemcpyDeviceToHost, st));
+          HIPCHK(hipStreamSynchronize(st));
+          c->sim.reset();
+          S->used -= c->bytes;
+          S->admitted--;
+          c->state = 3;
+          c->t_done = S->now();
+          S->unreported.push_back(c);
+        } else {
+          c->stage = 1;  // next step: membrane update + parabolic solve (eqs. (4), (7))
+          launch_membrane(sim, st);
+          start_solve(S, c, sim->hpar, sim->rhs, sim->v, 1);
+        }
+      } else {
+        c->stage = 2;  // elliptic solve with the new potential (eq. (6))
+        launch_neg_spmv(sim, sim->v, sim->fell, st);
+        start_solve(S, c, sim->hell, sim->fell, sim->ue, 1);
+      }
+    }
+  } else if (S->setups > 0) {
+    std::this_thread::sleep_for(std::chrono::microseconds(200));  // only host setups in flight
+  }
+  {
+    std::vector<ServedCase*> keep;
+    for (ServedCase* c : S->live)
+      if (c->state != 3) keep.push_back(c);
+    S->live.swap(keep);
+  }
+  int k = 0;
+  while (k < max_results && !S->unreported.empty()) {
+    ServedCase* c = S->unreported.front();
+    S->unreported.pop_front();
+    bd_case_result& r = results[k++];
+    r.ticket = c->ticket;
+    r.status = c->status;
+    r.steps = c->steps_done;
+    r.it_par = c->it_par;
+    r.it_ell = c->it_ell;
+    r.t_submit = c->t_submit;
+    r.t_admit = c->t_admit;
+    r.t_ready = c->t_ready;
+    r.t_done = c->t_done;
+    r.max_rel_residual = c->max_res;
+    r.device_bytes = c->bytes;
+  }
+  if (n_results) *n_results = k;
+  return BD_OK;
+}
+
+}  // namespace bd
+
+extern "C" {
+
+int bidomain_serve_create(int64_t budget_bytes, int32_t max_slots, const bd_amg_opts* ell, const bd_amg_opts* par,
+                          double rtol, void* stream, bd_server** out) {
+  return guarded([&] {
+    if (!out || budget_bytes <= 0 || max_slots < 1 || !(rtol > 0)) throw Failure{BD_E_INVALID, "invalid server arguments"};
+    std::unique_ptr<bd_server> S(new bd_server());
+    bidomain_default_opts(&S->oe);
+    bidomain_default_opts(&S->op);
+    if (ell) S->oe = *ell;
+    if (par) S->op = *par;
+    for (const bd_amg_opts* o : {&S->oe, &S->op})
+      if (o->smoother != BD_CHEBYSHEV || o->smoother_degree != 2)
+        throw Failure{BD_E_INVALID, "serving needs the Chebyshev smoother of degree 2"};
+    if (S->oe.vcycle_precision != S->op.vcycle_precision)
+      throw Failure{BD_E_INVALID, "both systems must use the same V-cycle precision when served"};
+    S->mixed = S->oe.vcycle_precision == BD_F32;
+    S->budget = budget_bytes;
+    S->max_slots = max_slots;
+    S->rtol = rtol;
+    S->st = (hipStream_t)stream;
+    S->stg.init(size_t(16) << 20);
+    *out = S.release();
+    return BD_OK;
+  });
+}
+
+int bidomain_serve_submit(bd_server* S, const bd_slab* slab, const double* v0_host, int32_t nsteps, uint64_t* ticket) {
+  return guarded([&] {
+    if (!S || !v0_host || nsteps < 0 || !ticket) throw Failure{BD_E_INVALID, "invalid submit arguments"};
+    check_slab(slab);
+    const int64_t est = case_estimate(*slab);
+    if (est > S->budget) {
+      g_last_error = "the case needs more device memory than the whole budget";
+      return BD_E_BUDGET;
+    }
+    std::unique_ptr<ServedCase> c(new ServedCase());
+    c->ticket = S->next_ticket++;
+    c->s = *slab;
+    c->nsteps = nsteps;
+    c->v0.assign(v0_host, v0_host + slab_nodes(*slab));
+    c->est = est;
+    c->t_submit = S->now();
+    *ticket = c->ticket;
+    S->by_ticket[c->ticket] = c.get();
+    S->queue.push_back(c.get());
+    S->cases.push_back(std::move(c));
+    return BD_OK;
+  });
+}
+
+int bidomain_serve_estimate(const bd_server* S, const bd_slab* slab, int64_t* bytes) {
+  return guarded([&] {
+    if (!S || !bytes) throw Failure{BD_E_INVALID, "null argument"};
+    check_slab(slab);
+    *bytes = case_estimate(*slab);
+    return BD_OK;
+  });
+}
+
+int bidomain_serve_poll(bd_server* S, bd_case_result* results, int32_t max_results, int32_t* n_results) {
+  return guarded([&] {
+    if (!S || (max_results > 0 && !results)) throw Failure{BD_E_INVALID, "invalid poll arguments"};
+    return serve_poll(S, results, max_results, n_results);
+  });
+}
+
+int bidomain_serve_fetch(bd_server* S, uint64_t ticket, double* v_host, double* ue_host) {
+  return guarded([&] {
+    auto it = S ? S->by_ticket.find(ticket) : decltype(S->by_ticket)::iterator();
+    if (!S || it == S->by_ticket.end() || it->second->state != 3) throw Failure{BD_E_INVALID, "no completed case with that ticket"};
+    ServedCase* c = it->second;
+    if (v_host) std::copy(c->v_out.begin(), c->v_out.end(), v_host);
+    if (ue_host) std::copy(c->ue_out.begin(), c->ue_out.end(), ue_host);
+    std::vector<double>().swap(c->v_out);
+    std::vector<double>().swap(c->ue_out);
+    c->state = 4;
+    return BD_OK;
+  });
+}
+
+int bidomain_serve_stats(const bd_server* S, bd_serve_stats* st) {
+  return guarded([&] {
+    if (!S || !st) throw Failure{BD_E_INVALID, "null argument"};
+    std::memset(st, 0, sizeof(*st));
+    for (const auto& c : S->cases) {
+      if (c->state == 0) st->queued++;
+      else if (c->state == 1) st->setting_up++;
+      else if (c->state == 2) st->running++;
+      else st->done++;
+    }
+    st->bytes_in_use = S->used;
+    st->budget = S->budget;
+    st->rounds = S->rounds;
+    st->solves = S->solves;
+    return BD_OK;
+  });
+}
+
+int bidomain_serve_solve_latencies(const bd_server* S, double* out, int32_t cap, int32_t* count) {
+  return guarded([&] {
+    if (!S || !count || (cap > 0 && !out)) throw Failure{BD_E_INVALID, "invalid arguments"};
+    const int n = (int)std::min<size_t>(S->solve_lat.size(), (size_t)std::max(cap, 0));
+    std::copy(S->solve_lat.begin(), S->solve_lat.begin() + n, out);
+    *count = (int)S->solve_lat.size();
+    return BD_OK;
+  });
+}
+
+void bidomain_serve_destroy(bd_server* S) { delete S; }
 
 }  // extern "C"

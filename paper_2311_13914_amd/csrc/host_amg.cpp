@@ -58,7 +58,7 @@ Csr spgemm(const Csr& A, const Csr& B) {
   {
     std::vector<int32_t>& mk = mark[omp_get_thread_num()];
     mk.assign(B.ncols, -1);
-#pragma omp for schedule(dynamic, 256)
+#pragma omp for schedule(dynamic, 16)
     for (int32_t i = 0; i < A.nrows; ++i) {
       int32_t cnt = 0;
       for (int32_t ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
@@ -82,7 +82,7 @@ Csr spgemm(const Csr& A, const Csr& B) {
     std::fill(mk.begin(), mk.end(), -1);
     std::vector<double> acc(B.ncols, 0.0);
     std::vector<int32_t> cols;
-#pragma omp for schedule(dynamic, 256)
+#pragma omp for schedule(dynamic, 16)
     for (int32_t i = 0; i < A.nrows; ++i) {
       cols.clear();
       for (int32_t ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
@@ -184,40 +184,58 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
 
 }  // namespace
 
+namespace {
+// Dot product in a fixed order independent of the thread count: 4096-entry blocks summed in
+// parallel, then the block sums in index order.
+double fixed_dot(const std::vector<double>& a, const std::vector<double>& b) {
+  const int64_t n = (int64_t)a.size(), nb = (n + 4095) / 4096;
+  std::vector<double> part(nb, 0.0);
+#pragma omp parallel for schedule(static)
+  for (int64_t blk = 0; blk < nb; ++blk) {
+    double s = 0.0;
+    for (int64_t i = blk * 4096; i < std::min(n, (blk + 1) * 4096); ++i) s += a[i] * b[i];
+    part[blk] = s;
+  }
+  double s = 0.0;
+  for (double v : part) s += v;
+  return s;
+}
+}  // namespace
+
 double lambda_estimate(const Csr& A, const std::vector<double>& Dinv, int iters, uint64_t seed) {
   const int32_t n = A.nrows;
   std::vector<double> r(n), z(n), p(n), q(n);
-  for (int32_t i = 0; i < n; ++i)
-    r[i] = 2.0 * ((double)(splitmix64_at(seed, (uint64_t)i) >> 11) * 0x1.0p-53) - 1.0;
-  double rho = 0.0;
+#pragma omp parallel for schedule(static)
   for (int32_t i = 0; i < n; ++i) {
+    r[i] = 2.0 * ((double)(splitmix64_at(seed, (uint64_t)i) >> 11) * 0x1.0p-53) - 1.0;
     z[i] = Dinv[i] * r[i];
     p[i] = z[i];
-    rho += r[i] * z[i];
   }
+  double rho = fixed_dot(r, z);
   const double rho0 = rho;
   std::vector<double> alpha, beta;
   for (int j = 0; j < iters; ++j) {
-    double pq = 0.0;
+#pragma omp parallel for schedule(dynamic, 256)
     for (int32_t i = 0; i < n; ++i) {
       double s = 0.0;
       for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * p[A.ci[k]];
       q[i] = s;
-      pq += p[i] * s;
     }
+    const double pq = fixed_dot(p, q);
     if (!(pq > 0.0)) break;
     const double al = rho / pq;
     alpha.push_back(al);
     if (j == iters - 1) break;
-    double rn = 0.0;
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i) {
       r[i] -= al * q[i];
       z[i] = Dinv[i] * r[i];
-      rn += r[i] * z[i];
     }
+    const double rn = fixed_dot(r, z);
     if (!(rn > 1e-28 * rho0)) break;
     const double be = rn / rho;
     beta.push_back(be);
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
     rho = rn;
   }
@@ -488,28 +506,20 @@ Csr rs_interpolation(const Csr& A, const Csr& S, const std::vector<uint8_t>& st)
 }
 
 // ------------------------------------------------------------------------------------------
-// (A + A^T) / 2 on the union of the two patterns.
+// (A + A^T) / 2.  The Galerkin product R A P with R = P^T has a symmetric pattern (A's is), so
+// every entry's mirror is found by a binary search in the mirror row; rows are independent.
 Csr symmetrize(const Csr& A) {
-  const Csr T = transpose(A);
-  Csr C;
-  C.nrows = A.nrows;
-  C.ncols = A.ncols;
-  C.rp.assign(A.nrows + 1, 0);
-  for (int32_t i = 0; i < A.nrows; ++i) {
-    int32_t a = A.rp[i], b = T.rp[i];
-    while (a < A.rp[i + 1] || b < T.rp[i + 1]) {
-      const int32_t ca = a < A.rp[i + 1] ? A.ci[a] : INT32_MAX;
-      const int32_t cb = b < T.rp[i + 1] ? T.ci[b] : INT32_MAX;
-      double va = 0.0, vb = 0.0;
-      int32_t c;
-      if (ca == cb) { c = ca; va = A.v[a++]; vb = T.v[b++]; }
-      else if (ca < cb) { c = ca; va = A.v[a++]; }
-      else { c = cb; vb = T.v[b++]; }
-      C.ci.push_back(c);
-      C.v.push_back(0.5 * (va + vb));
+  Csr C = A;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int32_t i = 0; i < A.nrows; ++i)
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+      const int32_t j = A.ci[k];
+      const int32_t* lo = A.ci.data() + A.rp[j];
+      const int32_t* hi = A.ci.data() + A.rp[j + 1];
+      const int32_t* m = std::lower_bound(lo, hi, i);
+      const double aji = (m != hi && *m == i) ? A.v[m - A.ci.data()] : 0.0;
+      C.v[k] = 0.5 * (A.v[k] + aji);
     }
-    C.rp[i + 1] = (int32_t)C.ci.size();
-  }
   return C;
 }
 

@@ -262,7 +262,7 @@ struct VcAcc {
 };
 
 template <typename T>
-__device__ void vc_partials(VcAcc<T>& v, int red, const Solve& sv, int nb, double* lds, float* lds32);
+__device__ void vc_partials(VcAcc<T>& v, int red, const Solve& sv, int bi, int nb, double* lds, float* lds32);
 
 // Fused epilogue of one row (s = (A x)_row); reduction terms accumulate in acc / vc.
 template <typename T, int OP>
@@ -315,16 +315,16 @@ __device__ __forceinline__ void row_epilogue(const SpArgs<T>& a, int row, T s, d
 
 // Block partials of the reducing ops (finalized by k_finalize).  Called by every thread.
 template <typename T, int OP>
-__device__ __forceinline__ void block_tail(const SpArgs<T>& a, double (&acc)[3], VcAcc<T>& vc, int nb, double* lds,
-                                           float* lds32) {
+__device__ __forceinline__ void block_tail(const SpArgs<T>& a, double (&acc)[3], VcAcc<T>& vc, int bi, int nb,
+                                           double* lds, float* lds32) {
   if constexpr (OP == OP_CG_Q || OP == OP_TRUE_RESID) {
     block_sum<1>(*reinterpret_cast<double(*)[1]>(acc), lds);
-    if (threadIdx.x == 0) a.sv.part[blockIdx.x] = acc[0];
+    if (threadIdx.x == 0) a.sv.part[bi] = acc[0];
   } else if constexpr (OP == OP_INIT_RESID) {
     block_sum<2>(*reinterpret_cast<double(*)[2]>(acc), lds);
-    if (threadIdx.x == 0) { a.sv.part[blockIdx.x] = acc[0]; a.sv.part[nb + blockIdx.x] = acc[1]; }
+    if (threadIdx.x == 0) { a.sv.part[bi] = acc[0]; a.sv.part[nb + bi] = acc[1]; }
   } else if constexpr (OP == OP_CHEB_STEP) {
-    if (a.red != RED_NONE) vc_partials<T>(vc, a.red, a.sv, nb, lds, lds32);
+    if (a.red != RED_NONE) vc_partials<T>(vc, a.red, a.sv, bi, nb, lds, lds32);
   }
 }
 
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
     const T s = row_product<T, G>(a.rp, a.ci, a.av, a.x, row, lane);
     if (lane == 0) row_epilogue<T, OP>(a, row, s, acc, vc);
   }
-  block_tail<T, OP>(a, acc, vc, nb, lds, lds32);
+  block_tail<T, OP>(a, acc, vc, blockIdx.x, nb, lds, lds32);
 }
 
 // CSR-stream kernel (after Greathouse & Daga, SC'14): block b owns rows [blk[b], blk[b+1]),
@@ -371,14 +371,10 @@ __device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
+// Body of the CSR-stream product for row block b of nb (b also indexes the block partials).
 template <typename T, int OP>
-__global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* __restrict__ blk) {
-  if (solve_done(a.sv)) return;
-  __shared__ double lds[16];
-  __shared__ float lds32[24];
-  __shared__ T prod[kStreamCap];
-  const int nb = gridDim.x;
-  const int b = xcd_tile(blockIdx.x, nb);
+__device__ __forceinline__ void stream_body(const SpArgs<T>& a, const int* __restrict__ blk, int b, int nb, T* prod,
+                                            double* lds, float* lds32) {
   const int r0 = blk[b], r1 = blk[b + 1];
   const int beg = a.rp[r0], end = a.rp[r1];
   // Phase 1: the block's entries [beg, end) in 4-entry chunks aligned to 4.  The load phase is
@@ -428,30 +424,40 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* 
   }
   for (int off = g / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, g);
   if (grp < nrow && lane == 0) row_epilogue<T, OP>(a, row, s, acc, vc);
-  block_tail<T, OP>(a, acc, vc, nb, lds, lds32);
+  block_tail<T, OP>(a, acc, vc, b, nb, lds, lds32);
 }
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* __restrict__ blk) {
+  if (solve_done(a.sv)) return;
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  __shared__ T prod[kStreamCap];
+  stream_body<T, OP>(a, blk, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, prod, lds, lds32);
+}
+
 
 // Block partials of the level-0 reductions: 1^T z, r^T z, 1^T r (RED_F64) or the two Dot2
 // pairs z32.r32, z32.r32_old and 1^T z (RED_F32).
 template <typename T>
-__device__ void vc_partials(VcAcc<T>& v, int red, const Solve& sv, int nb, double* lds, float* lds32) {
+__device__ void vc_partials(VcAcc<T>& v, int red, const Solve& sv, int bi, int nb, double* lds, float* lds32) {
   if (red == RED_F64) {
     block_sum<3>(v.acc, lds);
     if (threadIdx.x == 0) {
-      sv.part[blockIdx.x] = v.acc[0];
-      sv.part[nb + blockIdx.x] = v.acc[1];
-      sv.part[2 * nb + blockIdx.x] = v.acc[2];
+      sv.part[bi] = v.acc[0];
+      sv.part[nb + bi] = v.acc[1];
+      sv.part[2 * nb + bi] = v.acc[2];
     }
   } else {
     block_dot2<2>(v.dd, lds32);
     block_sum<1>(*reinterpret_cast<double(*)[1]>(v.acc), lds);
     if (threadIdx.x == 0) {
       float* pf = reinterpret_cast<float*>(sv.part + nb);
-      pf[4 * blockIdx.x + 0] = v.dd[0].p;
-      pf[4 * blockIdx.x + 1] = v.dd[0].s;
-      pf[4 * blockIdx.x + 2] = v.dd[1].p;
-      pf[4 * blockIdx.x + 3] = v.dd[1].s;
-      sv.part[blockIdx.x] = v.acc[0];
+      pf[4 * bi + 0] = v.dd[0].p;
+      pf[4 * bi + 1] = v.dd[0].s;
+      pf[4 * bi + 2] = v.dd[1].p;
+      pf[4 * bi + 3] = v.dd[1].s;
+      sv.part[bi] = v.acc[0];
     }
   }
 }
@@ -466,7 +472,7 @@ __global__ __launch_bounds__(kBlock) void k_vc_reduce(SpArgs<T> a, const T* __re
   VcAcc<T> vc;
   for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < a.nrows; i += (long)gridDim.x * kBlock)
     vc.add(a.red, (double)z[i], (float)z[i], (int)i, a);
-  vc_partials<T>(vc, a.red, a.sv, gridDim.x, lds, lds32);
+  vc_partials<T>(vc, a.red, a.sv, blockIdx.x, gridDim.x, lds, lds32);
 }
 
 // One block: sums the partials of the preceding kernel (nb blocks) in a fixed order and
@@ -479,12 +485,10 @@ __global__ __launch_bounds__(kBlock) void k_vc_reduce(SpArgs<T> a, const T* __re
 //   FIN_TRUE   ||b^ - A x||^2
 //   FIN_MEANS  means of b and of the initial guess (projection)
 //   FIN_NORM   w^T x and 1^T w (normalisation)
-__global__ __launch_bounds__(kBlock) void k_finalize(Solve sv, int kind, int nb) {
-  __shared__ double lds[16];
-  __shared__ float lds32[24];
+__device__ __forceinline__ void finalize_body(const Solve& sv, int kind, int nb, double* lds, float* lds32) {
   const bool guarded = kind == FIN_CGQ || kind == FIN_UPDATE || kind == FIN_VC64 || kind == FIN_VC32;
   if (guarded && sv.fl[F_DONE]) {
-    if (kind == FIN_UPDATE && threadIdx.x == 0 && sv.host_flags)
+    if (threadIdx.x == 0 && sv.host_flags)
       __hip_atomic_store(&sv.host_flags[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     return;
   }
@@ -515,10 +519,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Solve sv, int kind, int nb)
       else if (r2 <= sv.sc[S_TOL2]) { done = 1; }
       else if (it >= sv.fl[F_MAXIT]) { sv.fl[F_STATUS] = 1; done = 1; }
       if (done) sv.fl[F_DONE] = 1;
-      if (sv.host_flags) {
-        __hip_atomic_store(&sv.host_flags[1], it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-        __hip_atomic_store(&sv.host_flags[0], done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-      }
     }
   } else if (kind == FIN_VC64 || kind == FIN_VC32) {
     double sz, rz, num;
@@ -588,6 +588,17 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Solve sv, int kind, int nb)
       sv.sc[S_WSUM] = tot[1];
     }
   }
+  // pinned host mirror of (done, iterations) for the solve loops' convergence polling
+  if (threadIdx.x == 0 && sv.host_flags && (guarded || kind == FIN_INIT)) {
+    __hip_atomic_store(&sv.host_flags[1], sv.fl[F_ITERS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&sv.host_flags[0], sv.fl[F_DONE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_finalize(Solve sv, int kind, int nb) {
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  finalize_body(sv, kind, nb, lds, lds32);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -598,15 +609,14 @@ __device__ __forceinline__ long gtid() { return (long)blockIdx.x * kBlock + thre
 // right-hand side of the float V-cycle (r32 = fl32(r)) and the first pre-smoothing step of
 // level 0 (d0 = c0 dinv0 f0; also x0 = d0 when x0 is given).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_update(Solve sv, double* __restrict__ x, double* __restrict__ r,
-                                                      const double* __restrict__ p, const double* __restrict__ q,
-                                                      float* __restrict__ r32, const T* __restrict__ dinv0,
-                                                      T* __restrict__ d0, T* __restrict__ x0, T c0, long n) {
-  if (solve_done(sv)) return;
-  __shared__ double lds[4];
+__device__ __forceinline__ void cg_update_body(const Solve& sv, double* __restrict__ x, double* __restrict__ r,
+                                               const double* __restrict__ p, const double* __restrict__ q,
+                                               float* __restrict__ r32, const T* __restrict__ dinv0,
+                                               T* __restrict__ d0, T* __restrict__ x0, T c0, long n, int bi, int nb,
+                                               double* lds) {
   const double alpha = sv.sc[S_ALPHA];
   double acc[1] = {0.0};
-  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) {
+  for (long i = (long)bi * kBlock + threadIdx.x; i < n; i += (long)nb * kBlock) {
     x[i] += alpha * p[i];
     const double rn = r[i] - alpha * q[i];
     r[i] = rn;
@@ -620,25 +630,56 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(Solve sv, double* __restri
     }
   }
   block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) sv.part[blockIdx.x] = acc[0];
+  if (threadIdx.x == 0) sv.part[bi] = acc[0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update(Solve sv, double* __restrict__ x, double* __restrict__ r,
+                                                      const double* __restrict__ p, const double* __restrict__ q,
+                                                      float* __restrict__ r32, const T* __restrict__ dinv0,
+                                                      T* __restrict__ d0, T* __restrict__ x0, T c0, long n) {
+  if (solve_done(sv)) return;
+  __shared__ double lds[4];
+  cg_update_body<T>(sv, x, r, p, q, r32, dinv0, d0, x0, c0, n, blockIdx.x, gridDim.x, lds);
 }
 
 // p = (z - mu_z) + beta p   (p = z - mu_z for the first direction).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cg_direction(Solve sv, double* __restrict__ p, const T* __restrict__ z, long n) {
-  if (solve_done(sv)) return;
+__device__ __forceinline__ void cg_direction_body(const Solve& sv, double* __restrict__ p, const T* __restrict__ z, long n,
+                                                  int bi, int nb) {
   const double mu = sv.sc[S_MU_Z], beta = sv.sc[S_BETA];
   const int first = sv.fl[F_FIRST];
-  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) {
+  for (long i = (long)bi * kBlock + threadIdx.x; i < n; i += (long)nb * kBlock) {
     const double zi = (double)z[i] - mu;
     p[i] = first ? zi : zi + beta * p[i];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_direction(Solve sv, double* __restrict__ p, const T* __restrict__ z, long n) {
+  if (solve_done(sv)) return;
+  cg_direction_body<T>(sv, p, z, n, blockIdx.x, gridDim.x);
 }
 
 // Marks the first direction as formed (a separate launch, so that every block of
 // k_cg_direction has read the flag before it changes).
 __global__ void k_clear_first(Solve sv) {
   if (threadIdx.x == 0) sv.fl[F_FIRST] = 0;
+}
+
+// Solve-state control from the device queue: mode 0 starts a solve (flags, iteration cap,
+// null-space switch, rtol^2), mode 1 clears `done` (exit-phase kernels then run).
+__global__ void k_solve_control(Solve sv, int mode, int maxit, int nullspace, double rtol2) {
+  if (threadIdx.x != 0) return;
+  if (mode == 0) {
+    for (int f = 0; f < F_COUNT; ++f) sv.fl[f] = 0;
+    sv.fl[F_FIRST] = 1;
+    sv.fl[F_MAXIT] = maxit;
+    sv.fl[F_NULLSPACE] = nullspace;
+    sv.sc[S_RTOL2] = rtol2;
+  } else {
+    sv.fl[F_DONE] = 0;
+  }
 }
 
 // d = c0 dinv f, and x = d when x is given (first smoothing step from a zero guess, when it
@@ -663,10 +704,9 @@ __global__ __launch_bounds__(kBlock) void k_add(Solve sv, T* __restrict__ x, con
 
 // Coarsest level: x = G f with the dense float64 operator G (one wave per row).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_coarse_gemv(Solve sv, const double* __restrict__ G, const T* __restrict__ f,
-                                                        T* __restrict__ x, int n) {
-  if (solve_done(sv)) return;
-  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+__device__ __forceinline__ void coarse_gemv_body(const double* __restrict__ G, const T* __restrict__ f, T* __restrict__ x,
+                                                 int n, int bi) {
+  const int row = bi * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   double s = 0.0;
@@ -675,6 +715,14 @@ __global__ __launch_bounds__(kBlock) void k_coarse_gemv(Solve sv, const double* 
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (lane == 0) x[row] = (T)s;
 }
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv(Solve sv, const double* __restrict__ G, const T* __restrict__ f,
+                                                        T* __restrict__ x, int n) {
+  if (solve_done(sv)) return;
+  coarse_gemv_body<T>(G, f, x, n, blockIdx.x);
+}
+
 
 // ---------------------------------------------------------------------------------------
 // Setup / exit kernels of a solve.
@@ -716,6 +764,108 @@ __global__ __launch_bounds__(kBlock) void k_norm_sums(Solve sv, const double* __
 __global__ __launch_bounds__(kBlock) void k_norm_apply(Solve sv, double* __restrict__ x, long n) {
   const double s = sv.sc[S_WX] / sv.sc[S_WSUM];
   for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) x[i] -= s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Multi-task launches (batched solves): one launch serves several independent solves.  Each
+// task owns the contiguous block range [off, off + nb) of the grid; a block finds its task,
+// reads the task's arguments (uniform per block) and runs the single-solve body with its
+// local block index, so every solve computes exactly what it computes alone.
+template <typename Task>
+__device__ __forceinline__ int task_of(const Task* __restrict__ tasks, int ntasks) {
+  __shared__ int t_sh;
+  if (threadIdx.x == 0) {
+    int t = 0;
+    while (t + 1 < ntasks && tasks[t + 1].off <= (int)blockIdx.x) ++t;
+    t_sh = t;
+  }
+  __syncthreads();
+  return t_sh;
+}
+
+template <typename T>
+struct SpTask {
+  SpArgs<T> a;
+  const int* blk;
+  int nb, off;
+};
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_spmv_stream_multi(const SpTask<T>* __restrict__ tasks, int ntasks) {
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  __shared__ T prod[kStreamCap];
+  const SpTask<T>& tk = tasks[task_of(tasks, ntasks)];
+  const SpArgs<T> a = tk.a;
+  if (solve_done(a.sv)) return;
+  stream_body<T, OP>(a, tk.blk, xcd_tile((int)blockIdx.x - tk.off, tk.nb), tk.nb, prod, lds, lds32);
+}
+
+template <typename T>
+struct UpdTask {
+  Solve sv;
+  double *x, *r;
+  const double *p, *q;
+  float* r32;
+  const T* dinv0;
+  T *d0, *x0;
+  T c0;
+  long n;
+  int nb, off;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_update_multi(const UpdTask<T>* __restrict__ tasks, int ntasks) {
+  __shared__ double lds[4];
+  const UpdTask<T>& k = tasks[task_of(tasks, ntasks)];
+  if (solve_done(k.sv)) return;
+  cg_update_body<T>(k.sv, k.x, k.r, k.p, k.q, k.r32, k.dinv0, k.d0, k.x0, k.c0, k.n, (int)blockIdx.x - k.off, k.nb, lds);
+}
+
+template <typename T>
+struct DirTask {
+  Solve sv;
+  double* p;
+  const T* z;
+  long n;
+  int nb, off;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cg_direction_multi(const DirTask<T>* __restrict__ tasks, int ntasks) {
+  const DirTask<T>& k = tasks[task_of(tasks, ntasks)];
+  if (solve_done(k.sv)) return;
+  cg_direction_body<T>(k.sv, k.p, k.z, k.n, (int)blockIdx.x - k.off, k.nb);
+}
+
+template <typename T>
+struct GemvTask {
+  Solve sv;
+  const double* G;
+  const T* f;
+  T* x;
+  int n;
+  int nb, off;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_coarse_gemv_multi(const GemvTask<T>* __restrict__ tasks, int ntasks) {
+  const GemvTask<T>& k = tasks[task_of(tasks, ntasks)];
+  if (solve_done(k.sv)) return;
+  coarse_gemv_body<T>(k.G, k.f, k.x, k.n, (int)blockIdx.x - k.off);
+}
+
+struct FinTask {
+  Solve sv;
+  int kind, nb_part;
+  int nb, off;  // one block per task
+};
+
+__global__ __launch_bounds__(kBlock) void k_finalize_multi(const FinTask* __restrict__ tasks, int ntasks) {
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  const FinTask& k = tasks[task_of(tasks, ntasks)];
+  finalize_body(k.sv, k.kind, k.nb_part, lds, lds32);
 }
 
 // ---------------------------------------------------------------------------------------

@@ -135,11 +135,11 @@ def test_parabolic_solve_matches_oracle(torch, dims):
     ops = fem.assemble_operators(c)
     A = ops["Apar"]
     f = A @ bc.nodal_v0(c) + 0.1 * ops["m"] * bc.random_vector(c.n, 2)
-    h_or = amg.setup(A, amg.AMGOptions())
+    h_or = amg.setup(A, amg.AMGOptions(threshold=0.0))
     ref = krylov.amg_pcg(A, f, h_or, rtol=1e-12)
     or8 = krylov.amg_pcg(A, f, h_or, rtol=1e-8)
     print(f"[gpu] parabolic dims={dims} levels={h_or.nlevels} oracle_its={or8.iterations}", flush=True)
-    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts())
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(threshold=0.0))
     try:
         x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
         rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-8, 200)
@@ -229,7 +229,7 @@ def test_time_steps_match_oracle(torch, mixed):
     prec = lib.BD_F32 if mixed else lib.BD_F64
     sim = lib.bidomain_sim_create(c, dev(torch, v0), rtol=1e-10,
                                   ell_opts=lib.bidomain_default_opts(vcycle_precision=prec),
-                                  par_opts=lib.bidomain_default_opts(vcycle_precision=prec))
+                                  par_opts=lib.bidomain_default_opts(vcycle_precision=prec, threshold=0.0))
     try:
         out = torch.empty(c.n, dtype=torch.float64, device="cuda")
         for s in range(4):
