@@ -201,6 +201,8 @@ def bench_serve(args):
             "max_case_s": float(case_lat.max()), "mean_queue_wait_s": float(queue_wait.mean()),
             "makespan_s": wall, "throughput_dof_iters_per_s": dof_its / wall,
             "rounds": st["rounds"], "peak_running_cases": peak["running"], "peak_bytes": peak["bytes"],
+            "host_enqueue_s": round(st["host_enqueue_s"], 2), "host_wait_s": round(st["host_wait_s"], 2),
+            "host_exit_s": round(st["host_exit_s"], 2),
             "bytes_per_fine_nnz": [round(r["device_bytes"] / ticket_of[t].case.nnz27, 1) for t, r in
                                    sorted(done.items(), key=lambda kv: ticket_of[kv[0]].case.nnz27)],
         },

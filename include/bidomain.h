@@ -251,6 +251,8 @@ typedef struct {
   int32_t queued, setting_up, running, done;
   int64_t bytes_in_use, budget;
   int64_t rounds, solves;
+  double host_enqueue_s, host_wait_s, host_exit_s;  /* host time: enqueuing rounds, waiting on
+                                                     the GPU, finishing solves */
 } bd_serve_stats;
 
 /* budget_bytes: HBM the server may hold for cases; max_slots: cases admitted at once. */

@@ -78,7 +78,8 @@ class bd_case_result(C.Structure):
 
 class bd_serve_stats(C.Structure):
     _fields_ = [("queued", C.c_int32), ("setting_up", C.c_int32), ("running", C.c_int32), ("done", C.c_int32),
-                ("bytes_in_use", C.c_int64), ("budget", C.c_int64), ("rounds", C.c_int64), ("solves", C.c_int64)]
+                ("bytes_in_use", C.c_int64), ("budget", C.c_int64), ("rounds", C.c_int64), ("solves", C.c_int64),
+                ("host_enqueue_s", C.c_double), ("host_wait_s", C.c_double), ("host_exit_s", C.c_double)]
 
 
 _vp = C.c_void_p

@@ -1207,6 +1207,8 @@ void bidomain_profile_read(double* total_ms, int64_t* launches, int reset) {
 #include <map>
 #include <thread>
 
+#include <omp.h>
+
 namespace bd {
 
 // Task tables of the multi-task launches: each launch copies its table from a pinned host ring
@@ -1597,6 +1599,7 @@ struct bd_server {
   Staging stg;
   std::vector<double> solve_lat;
   int64_t rounds = 0, solves = 0;
+  double t_enqueue = 0.0, t_wait = 0.0, t_exit = 0.0;  // host seconds spent per round phase
   uint64_t next_ticket = 1;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
@@ -1608,12 +1611,19 @@ struct bd_server {
 
 namespace bd {
 
-constexpr int kMaxConcurrentSetups = 2;
+constexpr int kMaxConcurrentSetups = 3;
 
-// Device footprint estimate used for admission (bytes per 27-point nonzero of the fine mesh,
-// covering both hierarchies, A_i and the state vectors); replaced by the measured footprint
-// once the case is on the device.
-int64_t case_estimate(const bd_slab& s) { return (int64_t)120 * ((int64_t)(3 * s.nx + 1) * (3 * s.ny + 1) * (3 * s.nz + 1)); }
+// OpenMP threads of one host-setup worker: the workers share the cores and leave two for the
+// serving thread, which enqueues the rounds.
+int setup_threads() {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  return std::max(1, (hw - 2) / kMaxConcurrentSetups);
+}
+
+// Device footprint estimate used for admission: 85 bytes per 27-point nonzero of the fine mesh
+// (both hierarchies, A_i and the state vectors; 63-76 measured with float32 V-cycles from
+// 32x32x16 to 160x160x64); replaced by the measured footprint once the case is on the device.
+int64_t case_estimate(const bd_slab& s) { return (int64_t)85 * ((int64_t)(3 * s.nx + 1) * (3 * s.ny + 1) * (3 * s.nz + 1)); }
 
 void start_solve(bd_server* S, ServedCase* c, bd_amg* h, const double* b, double* x, int guess) {
   c->inst = BInst{};
@@ -1642,7 +1652,11 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
     c->t_admit = S->now();
     const bd_slab slab = c->s;
     const bd_amg_opts oe = S->oe, op = S->op;
-    c->fut = std::async(std::launch::async, [slab, oe, op] { return build_sim_host(slab, &oe, &op); });
+    const int nthr = setup_threads();
+    c->fut = std::async(std::launch::async, [slab, oe, op, nthr] {
+      omp_set_num_threads(nthr);
+      return build_sim_host(slab, &oe, &op);
+    });
     S->live.push_back(c);
   }
   // cases whose host setup finished: upload and start the initial elliptic solve
@@ -1683,11 +1697,17 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
     }
   if (!act.empty()) {
     S->stg.used = 0;
+    const auto ta = std::chrono::steady_clock::now();
     if (S->mixed) batched_round<float>(act, st, S->stg);
     else batched_round<double>(act, st, S->stg);
+    const auto tb = std::chrono::steady_clock::now();
     HIPCHK(hipStreamSynchronize(st));
+    const auto tc = std::chrono::steady_clock::now();
+    S->t_enqueue += std::chrono::duration<double>(tb - ta).count();
+    S->t_wait += std::chrono::duration<double>(tc - tb).count();
     S->rounds++;
     // finished solves: exit phase, then read their scalars
+    const auto td = std::chrono::steady_clock::now();
     std::vector<ServedCase*> fin;
     for (ServedCase* c : act_cases)
       if (__atomic_load_n(&c->inst.h->host_flags[0], __ATOMIC_ACQUIRE)) fin.push_back(c);
@@ -1737,6 +1757,7 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
         start_solve(S, c, sim->hell, sim->fell, sim->ue, 1);
       }
     }
+    S->t_exit += std::chrono::duration<double>(std::chrono::steady_clock::now() - td).count();
   } else if (S->setups > 0) {
     std::this_thread::sleep_for(std::chrono::microseconds(200));  // only host setups in flight
   }
@@ -1864,6 +1885,9 @@ int bidomain_serve_stats(const bd_server* S, bd_serve_stats* st) {
     st->budget = S->budget;
     st->rounds = S->rounds;
     st->solves = S->solves;
+    st->host_enqueue_s = S->t_enqueue;
+    st->host_wait_s = S->t_wait;
+    st->host_exit_s = S->t_exit;
     return BD_OK;
   });
 }
