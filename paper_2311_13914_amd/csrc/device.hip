@@ -80,7 +80,7 @@ struct DCsr {
   int G = 8;    // lanes per row (row-group kernel)
   int tpb = 1;  // row tiles per block (row-group kernel)
   int nb = 0;   // blocks of a product launch
-  const int* blk = nullptr;  // CSR-stream row blocks (nb + 1 row offsets), or null
+  const int* blk = nullptr;  // CSR-stream row tiles (nb + 1 row boundaries), or null
 };
 
 int lanes_for(double mean_row) {
@@ -89,27 +89,36 @@ int lanes_for(double mean_row) {
   return g;
 }
 
-// Matrices whose every row fits the staging buffer use the CSR-stream kernel (measured faster
-// than the lane-group kernel on every level of the slab hierarchies, short and long rows
-// alike); the host packs consecutive rows into blocks of at most kStreamRows rows and
-// kStreamCap nonzeros.  Longer rows fall back to the lane-group kernel.
-std::vector<int> stream_blocks(const Csr& H) {
-  std::vector<int> blk;
-  if (H.nrows == 0) return blk;
-  for (int32_t i = 0; i < H.nrows; ++i)
-    if (H.rp[i + 1] - H.rp[i] > kStreamCap) return blk;
-  blk.push_back(0);
+// Greedy packing of consecutive rows into tiles of at most max_rows rows and max_nnz entries
+// (row boundaries, nb + 1 of them).
+std::vector<int> pack_tiles(const Csr& H, int max_rows, int64_t max_nnz) {
+  std::vector<int> blk(1, 0);
   int32_t r = 0;
   while (r < H.nrows) {
     const int32_t start = r;
     int64_t cnt = 0;
-    while (r < H.nrows && r - start < kStreamRows && cnt + (H.rp[r + 1] - H.rp[r]) <= kStreamCap) {
+    while (r < H.nrows && r - start < max_rows && cnt + (H.rp[r + 1] - H.rp[r]) <= max_nnz) {
       cnt += H.rp[r + 1] - H.rp[r];
       ++r;
     }
     blk.push_back(r);
   }
   return blk;
+}
+
+// Row tiles of the CSR-stream kernel (nb + 1 row boundaries).  Matrices whose every row fits
+// the staging buffer use it (measured faster than the lane-group kernel on every level of the
+// slab hierarchies, short and long rows alike); longer rows fall back to the lane-group kernel
+// (empty result).  Tiles hold at most kStreamCap entries and kStreamRows / 2 rows, or
+// kStreamRows rows for short rows, so that a tile of a prolongator still streams a few thousand
+// entries.  (Shrinking tiles so that their count fills whole rounds of resident blocks measured
+// slower on every level.)
+std::vector<int> stream_blocks(const Csr& H) {
+  if (H.nrows == 0) return {};
+  for (int32_t i = 0; i < H.nrows; ++i)
+    if (H.rp[i + 1] - H.rp[i] > kStreamCap) return {};
+  const int max_rows = (double)H.nnz() / H.nrows <= 12.0 ? kStreamRows : kStreamRows / 2;
+  return pack_tiles(H, max_rows, kStreamCap);
 }
 
 template <typename T>
@@ -256,7 +265,7 @@ void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
 }
 
 void finalize(const Solve& sv, int kind, int nb, hipStream_t st) {
-  k_finalize<<<1, kBlock, 0, st>>>(sv, kind, nb);
+  k_finalize<<<1, kFinBlock, 0, st>>>(sv, kind, nb);
   HIPCHK(hipGetLastError());
 }
 

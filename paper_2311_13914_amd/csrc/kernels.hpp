@@ -79,8 +79,12 @@ __device__ __forceinline__ bool solve_done(const Solve& s) {
 
 // ---------------------------------------------------------------------------------------
 // Reductions.
-template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NV * 4 */) {
+// Sum over a block of NT threads (NT / 64 waves, a power of two): wave shuffles, then a fixed
+// pairwise tree over the waves; every thread returns the totals.
+template <int NV, int NT = kBlock>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NV * NT / 64 */) {
+  constexpr int W = NT / 64;
+  static_assert(W >= 1 && (W & (W - 1)) == 0, "a power-of-two number of waves");
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     double t = v[k];
@@ -91,23 +95,50 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds /* NV * 4
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) lds[k * 4 + wave] = v[k];
+    for (int k = 0; k < NV; ++k) lds[k * W + wave] = v[k];
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < NV; ++k) v[k] = (lds[k * 4 + 0] + lds[k * 4 + 1]) + (lds[k * 4 + 2] + lds[k * 4 + 3]);
+  for (int k = 0; k < NV; ++k) {
+    double t[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) t[w] = lds[k * W + w];
+#pragma unroll
+    for (int st = 1; st < W; st *= 2)
+#pragma unroll
+      for (int w = 0; w < W; w += 2 * st) t[w] += t[w + st];
+    v[k] = t[0];
+  }
   __syncthreads();
 }
 
-// Fixed-order sum of NV partial arrays (stride nb) by the whole block.
-template <int NV>
+// Fixed-order sum of NV partial arrays (stride nb) by the whole block.  Each thread keeps
+// kSumLanes independent accumulators so that that many loads are in flight at once (a single
+// chain would wait out one memory latency per partial).
+constexpr int kSumLanes = 8;
+template <int NV, int NT = kBlock>
 __device__ __forceinline__ void sum_partials(const double* part, int nb, double (&out)[NV], double* lds) {
+  double acc[NV][kSumLanes];
 #pragma unroll
-  for (int k = 0; k < NV; ++k) out[k] = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kBlock)
+  for (int k = 0; k < NV; ++k)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) out[k] += part[(long)k * nb + i];
-  block_sum<NV>(out, lds);
+    for (int u = 0; u < kSumLanes; ++u) acc[k][u] = 0.0;
+  int i = threadIdx.x;
+  for (; i + (kSumLanes - 1) * NT < nb; i += kSumLanes * NT)
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+      for (int u = 0; u < kSumLanes; ++u) acc[k][u] += part[(long)k * nb + i + u * NT];
+#pragma unroll
+  for (int u = 0; u < kSumLanes; ++u)
+    if (i + u * NT < nb)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k][u] += part[(long)k * nb + i + u * NT];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    out[k] = ((acc[k][0] + acc[k][1]) + (acc[k][2] + acc[k][3])) + ((acc[k][4] + acc[k][5]) + (acc[k][6] + acc[k][7]));
+  block_sum<NV, NT>(out, lds);
 }
+static_assert(kSumLanes == 8, "the combining tree above is written for 8 lanes");
 
 // Compensated float arithmetic (Ogita, Rump & Oishi, SIAM J. Sci. Comput. 26 (2005)):
 // TwoSum (Knuth) and TwoProduct with a fused multiply-add.
@@ -136,8 +167,9 @@ struct Dot2 {
   }
 };
 
-template <int NV>
-__device__ __forceinline__ void block_dot2(Dot2 (&v)[NV], float* lds /* NV * 8 */) {
+template <int NV, int NT = kBlock>
+__device__ __forceinline__ void block_dot2(Dot2 (&v)[NV], float* lds /* NV * 2 * NT / 64 */) {
+  constexpr int W = NT / 64;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
 #pragma unroll
@@ -155,13 +187,13 @@ __device__ __forceinline__ void block_dot2(Dot2 (&v)[NV], float* lds /* NV * 8 *
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (lane == 0)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) { lds[k * 8 + wave * 2] = v[k].p; lds[k * 8 + wave * 2 + 1] = v[k].s; }
+    for (int k = 0; k < NV; ++k) { lds[k * 2 * W + wave * 2] = v[k].p; lds[k * 2 * W + wave * 2 + 1] = v[k].s; }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     Dot2 a;
-    a.p = lds[k * 8 + 0]; a.s = lds[k * 8 + 1];
-    for (int w = 1; w < 4; ++w) a.merge(lds[k * 8 + 2 * w], lds[k * 8 + 2 * w + 1]);
+    a.p = lds[k * 2 * W + 0]; a.s = lds[k * 2 * W + 1];
+    for (int w = 1; w < W; ++w) a.merge(lds[k * 2 * W + 2 * w], lds[k * 2 * W + 2 * w + 1]);
     v[k] = a;
   }
   __syncthreads();
@@ -247,15 +279,16 @@ template <typename T>
 struct VcAcc {
   double acc[3] = {0.0, 0.0, 0.0};
   Dot2 dd[2];
-  __device__ __forceinline__ void add(int red, double z64, float z32, int row, const SpArgs<T>& a) {
+  // z: the V-cycle output at a row; rr: the CG residual there (RED_F64); r32 / r32o: the
+  // current and previous level-0 right-hand sides (RED_F32)
+  __device__ __forceinline__ void add(int red, double z64, float z32, double rr, float r32, float r32o) {
     if (red == RED_F64) {
-      const double rr = a.r64[row];
       acc[0] += z64;
       acc[1] += rr * z64;
       acc[2] += rr;
     } else if (red == RED_F32) {
-      dd[0].add(z32, a.r32[row]);
-      dd[1].add(z32, a.r32_old[row]);
+      dd[0].add(z32, r32);
+      dd[1].add(z32, r32o);
       acc[0] += (double)z32;
     }
   }
@@ -264,53 +297,106 @@ struct VcAcc {
 template <typename T>
 __device__ void vc_partials(VcAcc<T>& v, int red, const Solve& sv, int bi, int nb, double* lds, float* lds32);
 
-// Fused epilogue of one row (s = (A x)_row); reduction terms accumulate in acc / vc.
+// Row operands of the fused epilogue, read right after the gathers so that their latency
+// overlaps the product's.  Every field an OP uses is read from a valid address whatever the
+// run-time flags (unused reduction operands read solve scalar 0), so the reads are
+// unconditional and never split the kernel's load sequence into branches.
+template <typename T>
+struct RowIn {
+  T f = T(0), x = T(0), dinv = T(0), r = T(0), xs = T(0), y = T(0);
+  double r64 = 0.0, b = 0.0;
+  float r32 = 0.f, r32o = 0.f;
+};
+
 template <typename T, int OP>
-__device__ __forceinline__ void row_epilogue(const SpArgs<T>& a, int row, T s, double (&acc)[3], VcAcc<T>& vc) {
+__device__ __forceinline__ RowIn<T> row_fetch(const SpArgs<T>& a, int row) {
+  RowIn<T> in;
+  if constexpr (OP == OP_ADDY) {
+    in.y = a.y[row];
+  } else if constexpr (OP == OP_RESID) {
+    in.f = a.f[row];
+  } else if constexpr (OP == OP_RESTRICT) {
+    in.dinv = a.dinv2[row];
+  } else if constexpr (OP == OP_CHEB_FIRST || OP == OP_JACOBI) {
+    in.f = a.f[row];
+    in.x = a.x[row];
+    in.dinv = a.dinv[row];
+  } else if constexpr (OP == OP_CHEB_POST0) {
+    in.f = a.f[row];
+    in.dinv = a.dinv[row];
+  } else if constexpr (OP == OP_CHEB_STEP) {
+    in.r = a.r[row];
+    in.x = a.x[row];
+    in.dinv = a.dinv[row];
+    in.xs = a.xs[row];
+    const bool f64 = a.red == RED_F64, f32 = a.red == RED_F32;
+    const float* s32 = reinterpret_cast<const float*>(a.sv.sc);
+    in.r64 = (f64 ? a.r64 : a.sv.sc)[f64 ? row : 0];
+    in.r32 = (f32 ? a.r32 : s32)[f32 ? row : 0];
+    in.r32o = (f32 ? a.r32_old : s32)[f32 ? row : 0];
+  } else if constexpr (OP == OP_CG_Q) {
+    in.x = a.x[row];
+  } else if constexpr (OP == OP_INIT_RESID || OP == OP_TRUE_RESID) {
+    in.b = a.b[row];
+  }
+  return in;
+}
+
+// Fused epilogue of one row (s = (A x)_row, in = row_fetch of the same row); reduction terms
+// accumulate in acc / vc.  The reduction operands are never stored by the same launch (the
+// host does not combine store_rd with a level-0 reduction), so reading them first is exact.
+template <typename T, int OP>
+__device__ __forceinline__ void row_apply(const SpArgs<T>& a, int row, T s, const RowIn<T>& in, double (&acc)[3],
+                                          VcAcc<T>& vc) {
   if constexpr (OP == OP_Y) {
     a.y[row] = s;
   } else if constexpr (OP == OP_ADDY) {
-    a.y[row] += s;
+    a.y[row] = in.y + s;
   } else if constexpr (OP == OP_RESID) {
-    a.y[row] = a.f[row] - s;
+    a.y[row] = in.f - s;
   } else if constexpr (OP == OP_RESTRICT) {
     a.y[row] = s;
-    const T d = a.c0 * a.dinv2[row] * s;
+    const T d = a.c0 * in.dinv * s;
     a.y2[row] = d;
     if (a.xs) a.xs[row] = d;
   } else if constexpr (OP == OP_CHEB_FIRST) {
-    const T r1 = a.f[row] - s;
-    const T d = a.x[row];
-    const T dn = a.c1 * d + a.c2 * a.dinv[row] * r1;
+    const T r1 = in.f - s;
+    const T d = in.x;
+    const T dn = a.c1 * d + a.c2 * in.dinv * r1;
     a.xs[row] = d + dn;
     if (a.store_rd) { a.r[row] = r1; a.y2[row] = dn; }
   } else if constexpr (OP == OP_CHEB_POST0) {
-    const T r0 = a.f[row] - s;
+    const T r0 = in.f - s;
     a.r[row] = r0;
-    a.y2[row] = a.c0 * a.dinv[row] * r0;
+    a.y2[row] = a.c0 * in.dinv * r0;
   } else if constexpr (OP == OP_CHEB_STEP) {
-    const T r1 = a.r[row] - s;
-    const T d = a.x[row];
-    const T dn = a.c1 * d + a.c2 * a.dinv[row] * r1;
-    const T xn = a.xs[row] + (a.add_d ? d + dn : dn);
+    const T r1 = in.r - s;
+    const T d = in.x;
+    const T dn = a.c1 * d + a.c2 * in.dinv * r1;
+    const T xn = in.xs + (a.add_d ? d + dn : dn);
     a.xs[row] = xn;
     if (a.store_rd) { a.r[row] = r1; a.y2[row] = dn; }
-    vc.add(a.red, (double)xn, (float)xn, row, a);
+    vc.add(a.red, (double)xn, (float)xn, in.r64, in.r32, in.r32o);
   } else if constexpr (OP == OP_JACOBI) {
-    a.y[row] = a.x[row] + a.c0 * a.dinv[row] * (a.f[row] - s);
+    a.y[row] = in.x + a.c0 * in.dinv * (in.f - s);
   } else if constexpr (OP == OP_CG_Q) {
     a.y[row] = s;
-    acc[0] += (double)a.x[row] * (double)s;
+    acc[0] += (double)in.x * (double)s;
   } else if constexpr (OP == OP_INIT_RESID) {
-    const double bh = a.b[row] - a.sv.sc[S_MU_B];
+    const double bh = in.b - a.sv.sc[S_MU_B];
     const double rr = bh - (double)s;
     a.y[row] = (T)rr;
     acc[0] += bh * bh;
     acc[1] += rr * rr;
   } else if constexpr (OP == OP_TRUE_RESID) {
-    const double rr = (a.b[row] - a.sv.sc[S_MU_B]) - (double)s;
+    const double rr = (in.b - a.sv.sc[S_MU_B]) - (double)s;
     acc[0] += rr * rr;
   }
+}
+
+template <typename T, int OP>
+__device__ __forceinline__ void row_epilogue(const SpArgs<T>& a, int row, T s, double (&acc)[3], VcAcc<T>& vc) {
+  row_apply<T, OP>(a, row, s, row_fetch<T, OP>(a, row), acc, vc);
 }
 
 // Block partials of the reducing ops (finalized by k_finalize).  Called by every thread.
@@ -350,15 +436,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
   block_tail<T, OP>(a, acc, vc, blockIdx.x, nb, lds, lds32);
 }
 
-// CSR-stream kernel (after Greathouse & Daga, SC'14): block b owns rows [blk[b], blk[b+1]),
-// at most kStreamRows rows whose nonzeros fit in kStreamCap.  Phase 1 streams the block's
+// CSR-stream kernel (after Greathouse & Daga, SC'14): tile b owns rows [blk[b], blk[b+1]),
+// at most kStreamRows rows whose nonzeros fit in kStreamCap.  Phase 1 streams the tile's
 // contiguous value/column range with consecutive lanes on consecutive entries (every load
 // instruction covers one contiguous span) and stages the products a_k x_{c_k} in LDS;
 // phase 2 reduces each row from LDS with a power-of-two lane group and applies the epilogue.
-constexpr int kStreamCap = 4096;
-constexpr int kStreamRows = 128;
+// 4028 entries: the staging buffer (kStageLen doubles) plus the reduction scratch stay within
+// 32 KiB of LDS, so five blocks fit a CU's 160 KiB (4 aligned 4-entry chunks per thread)
+constexpr int kStreamCap = 4028;
+constexpr int kStreamRows = kBlock;  // phase 2 gives each row at least one lane
 constexpr int kStreamPad = 4;   // value/column arrays carry this many padding entries
-constexpr int kStreamChunks = (kStreamCap + 3) / (4 * kBlock) + 1;  // 4-entry chunks per thread
+// aligned 4-entry chunks spanned by kStreamCap entries at the worst alignment, per thread
+constexpr int kStreamChunks = ((kStreamCap + 2) / 4 + 1 + kBlock - 1) / kBlock;
+static_assert((kStreamCap + 2) / 4 + 1 <= kStreamChunks * kBlock, "chunks must cover an unaligned tile");
 
 // Four consecutive matrix entries with 16-byte loads (entry index a multiple of 4).
 __device__ __forceinline__ void load4(const double* p, double (&v)[4]) {
@@ -371,68 +461,130 @@ __device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
   v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
 }
 
-// Body of the CSR-stream product for row block b of nb (b also indexes the block partials).
+// Rows and entry range of one tile, plus the row-offset pair of this thread's phase-2 row.
+struct Tile {
+  int r0, r1, beg, end;
+  int k0;      // beg rounded down to a multiple of 4: LDS slot 0 holds entry k0
+  int lo, hi;  // rp[row], rp[row + 1] of this thread's phase-2 row
+  int g;       // lanes per row in phase 2: a power of two, at most 64
+};
+
+// Matrix entries of one tile held in registers between phase 1's loads and its gathers.
+template <typename T>
+struct TileRegs {
+  int c[kStreamChunks][4];
+  T v[kStreamChunks][4];
+};
+
+// LDS entries of the product staging buffer: slot k - k0 of every chunk a tile of at most
+// kStreamCap entries spans at the worst alignment (clamped chunks reuse the last slot).
+constexpr int kStageLen = 4 * ((kStreamCap + 2) / 4 + 1);
+static_assert(kStageLen <= kStreamChunks * 4 * kBlock, "every spanned chunk has a thread");
+
+__device__ __forceinline__ Tile tile_open(const int* __restrict__ rp, const int* __restrict__ blk, int b) {
+  Tile t;
+  t.r0 = blk[b];
+  t.r1 = blk[b + 1];
+  t.beg = rp[t.r0];
+  t.end = rp[t.r1];
+  t.k0 = t.beg & ~3;
+  const int nrow = t.r1 - t.r0;
+  int g = kBlock / (nrow > 0 ? nrow : 1);
+  t.g = g >= 64 ? 64 : (g >= 32 ? 32 : (g >= 16 ? 16 : (g >= 8 ? 8 : (g >= 4 ? 4 : (g >= 2 ? 2 : 1)))));
+  // this thread's phase-2 row, clamped into the tile so that the reads are unconditional
+  const int row = min(t.r0 + (int)threadIdx.x / t.g, t.r1 - 1);
+  t.lo = rp[row];
+  t.hi = rp[row + 1];
+  return t;
+}
+
+// Phase 1, loads: the 4-entry chunks (aligned to 4) spanning the tile's entries [beg, end).
+// Branch-free so that every chunk load is in flight at once: chunk positions past the tile are
+// clamped to its last chunk.  Entries outside [beg, end) are neighbouring rows' or the zero
+// padding of the arrays (kStreamPad entries past nnz), so every loaded column index is valid.
+template <typename T>
+__device__ __forceinline__ void tile_load(const SpArgs<T>& a, const Tile& t, TileRegs<T>& R) {
+  const int klast = max(t.k0, (t.end - 1) & ~3);
+#pragma unroll
+  for (int c = 0; c < kStreamChunks; ++c) {
+    const int k = min(t.k0 + 4 * ((int)threadIdx.x + kBlock * c), klast);
+    const int4 cc = *reinterpret_cast<const int4*>(a.ci + k);
+    R.c[c][0] = cc.x; R.c[c][1] = cc.y; R.c[c][2] = cc.z; R.c[c][3] = cc.w;
+    load4(a.av + k, R.v[c]);
+  }
+}
+
+// Phase 1, gathers of x at the loaded columns (issued together).
+template <typename T>
+__device__ __forceinline__ void tile_gather(const SpArgs<T>& a, const TileRegs<T>& R, T (&xv)[kStreamChunks][4]) {
+#pragma unroll
+  for (int c = 0; c < kStreamChunks; ++c)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xv[c][j] = a.x[R.c[c][j]];
+}
+
+// Phase 1, products a_k x_{c_k} into LDS slot k - k0.  Every chunk is stored whole: entries of
+// neighbouring rows land in slots phase 2 does not read, and a clamped chunk rewrites the
+// tile's last chunk with identical values.
+template <typename T>
+__device__ __forceinline__ void tile_stage(const Tile& t, const TileRegs<T>& R, const T (&xv)[kStreamChunks][4],
+                                           T* prod) {
+  const int klast = max(t.k0, (t.end - 1) & ~3);
+#pragma unroll
+  for (int c = 0; c < kStreamChunks; ++c) {
+    const int k = min(t.k0 + 4 * ((int)threadIdx.x + kBlock * c), klast) - t.k0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) prod[k + j] = R.v[c][j] * xv[c][j];
+  }
+}
+
+// This thread's phase-2 row (clamped into the tile) and its epilogue operands.
+template <typename T, int OP>
+__device__ __forceinline__ RowIn<T> tile_fetch(const SpArgs<T>& a, const Tile& t) {
+  return row_fetch<T, OP>(a, min(t.r0 + (int)threadIdx.x / t.g, t.r1 - 1));
+}
+
+// Phase 2: row sums from LDS, the fused epilogue, and the tile's reduction partials (slot bi
+// of nb).  Called by every thread after a barrier that follows tile_stage.
+template <typename T, int OP>
+__device__ __forceinline__ void tile_reduce(const SpArgs<T>& a, const Tile& t, const RowIn<T>& in, int bi, int nb,
+                                            const T* prod, double* lds, float* lds32) {
+  const int grp = threadIdx.x / t.g, lane = threadIdx.x % t.g;
+  double acc[3] = {0.0, 0.0, 0.0};
+  VcAcc<T> vc;
+  const int row = t.r0 + grp;
+  const bool own = grp < t.r1 - t.r0;
+  T s = T(0);
+  const int hi = own ? t.hi - t.k0 : 0;
+  for (int k = t.lo - t.k0 + lane; k < hi; k += t.g) s += prod[k];
+  for (int off = t.g / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, t.g);
+  if (own && lane == 0) row_apply<T, OP>(a, row, s, in, acc, vc);
+  block_tail<T, OP>(a, acc, vc, bi, nb, lds, lds32);
+}
+
+// Body of the CSR-stream product for row tile b of nb (b also indexes the block partials).
+// (Testing the solve's done flag only after the tile's reads are issued, to overlap its
+// latency, measured slower: the branch keeps every loaded register live across it.)
 template <typename T, int OP>
 __device__ __forceinline__ void stream_body(const SpArgs<T>& a, const int* __restrict__ blk, int b, int nb, T* prod,
                                             double* lds, float* lds32) {
-  const int r0 = blk[b], r1 = blk[b + 1];
-  const int beg = a.rp[r0], end = a.rp[r1];
-  // Phase 1: the block's entries [beg, end) in 4-entry chunks aligned to 4.  The load phase is
-  // branch-free so that every chunk load and every x gather is in flight at once: chunk
-  // positions past the block are clamped to its last chunk, and entries outside [beg, end)
-  // (neighbouring rows or the zero padding, all valid column indices) are gathered but not
-  // stored.
-  if (end > beg) {
-    const int k0 = beg & ~3;
-    const int klast = (end - 1) & ~3;
-    int cidx[kStreamChunks][4];
-    T val[kStreamChunks][4];
-    T xv[kStreamChunks][4];
-#pragma unroll
-    for (int c = 0; c < kStreamChunks; ++c) {
-      const int k = min(k0 + 4 * ((int)threadIdx.x + kBlock * c), klast);
-      const int4 cc = *reinterpret_cast<const int4*>(a.ci + k);
-      cidx[c][0] = cc.x; cidx[c][1] = cc.y; cidx[c][2] = cc.z; cidx[c][3] = cc.w;
-      load4(a.av + k, val[c]);
-    }
-#pragma unroll
-    for (int c = 0; c < kStreamChunks; ++c)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) xv[c][j] = a.x[cidx[c][j]];
-#pragma unroll
-    for (int c = 0; c < kStreamChunks; ++c) {
-      const int k = k0 + 4 * ((int)threadIdx.x + kBlock * c);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int kk = k + j;
-        if (kk >= beg && kk < end) prod[kk - beg] = val[c][j] * xv[c][j];
-      }
-    }
-  }
+  if (solve_done(a.sv)) return;
+  const Tile t = tile_open(a.rp, blk, b);
+  TileRegs<T> R;
+  T xv[kStreamChunks][4];
+  tile_load(a, t, R);
+  tile_gather(a, R, xv);
+  const RowIn<T> in = tile_fetch<T, OP>(a, t);
+  tile_stage(t, R, xv, prod);
   __syncthreads();
-  const int nrow = r1 - r0;
-  int g = kBlock / (nrow > 0 ? nrow : 1);  // lanes per row: a power of two, at most 64
-  g = g >= 64 ? 64 : (g >= 32 ? 32 : (g >= 16 ? 16 : (g >= 8 ? 8 : (g >= 4 ? 4 : (g >= 2 ? 2 : 1)))));
-  const int grp = threadIdx.x / g, lane = threadIdx.x % g;
-  double acc[3] = {0.0, 0.0, 0.0};
-  VcAcc<T> vc;
-  const int row = r0 + grp;
-  T s = T(0);
-  if (grp < nrow) {
-    const int lo = a.rp[row] - beg, hi = a.rp[row + 1] - beg;
-    for (int k = lo + lane; k < hi; k += g) s += prod[k];
-  }
-  for (int off = g / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, g);
-  if (grp < nrow && lane == 0) row_epilogue<T, OP>(a, row, s, acc, vc);
-  block_tail<T, OP>(a, acc, vc, b, nb, lds, lds32);
+  tile_reduce<T, OP>(a, t, in, b, nb, prod, lds, lds32);
 }
 
 template <typename T, int OP>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* __restrict__ blk) {
-  if (solve_done(a.sv)) return;
   __shared__ double lds[16];
   __shared__ float lds32[24];
-  __shared__ T prod[kStreamCap];
+  __shared__ T prod[kStageLen];
   stream_body<T, OP>(a, blk, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, prod, lds, lds32);
 }
 
@@ -470,8 +622,17 @@ __global__ __launch_bounds__(kBlock) void k_vc_reduce(SpArgs<T> a, const T* __re
   __shared__ double lds[16];
   __shared__ float lds32[24];
   VcAcc<T> vc;
-  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < a.nrows; i += (long)gridDim.x * kBlock)
-    vc.add(a.red, (double)z[i], (float)z[i], (int)i, a);
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < a.nrows; i += (long)gridDim.x * kBlock) {
+    double rr = 0.0;
+    float r32 = 0.f, r32o = 0.f;
+    if (a.red == RED_F64) {
+      rr = a.r64[i];
+    } else if (a.red == RED_F32) {
+      r32 = a.r32[i];
+      r32o = a.r32_old[i];
+    }
+    vc.add(a.red, (double)z[i], (float)z[i], rr, r32, r32o);
+  }
   vc_partials<T>(vc, a.red, a.sv, blockIdx.x, gridDim.x, lds, lds32);
 }
 
@@ -485,120 +646,125 @@ __global__ __launch_bounds__(kBlock) void k_vc_reduce(SpArgs<T> a, const T* __re
 //   FIN_TRUE   ||b^ - A x||^2
 //   FIN_MEANS  means of b and of the initial guess (projection)
 //   FIN_NORM   w^T x and 1^T w (normalisation)
+template <int NT>
 __device__ __forceinline__ void finalize_body(const Solve& sv, int kind, int nb, double* lds, float* lds32) {
   const bool guarded = kind == FIN_CGQ || kind == FIN_UPDATE || kind == FIN_VC64 || kind == FIN_VC32;
-  if (guarded && sv.fl[F_DONE]) {
-    if (threadIdx.x == 0 && sv.host_flags)
+  // Flags and scalars are read before the partial sums so that every read is in flight at
+  // once; a solve that was already done skips the updates (its partials are stale but valid
+  // memory).
+  const bool was_done = guarded && sv.fl[F_DONE] != 0;
+  const int iters = sv.fl[F_ITERS], maxit = sv.fl[F_MAXIT];
+  const bool first = sv.fl[F_FIRST] != 0, ns = sv.fl[F_NULLSPACE] != 0;
+  const double rho_old = sv.sc[S_RHO], tol2_in = sv.sc[S_TOL2], rtol2 = sv.sc[S_RTOL2];
+  double tot[3] = {0.0, 0.0, 0.0};
+  Dot2 c[2];
+  if (kind == FIN_VC64) {
+    sum_partials<3, NT>(sv.part, nb, tot, lds);
+  } else if (kind == FIN_INIT || kind == FIN_MEANS || kind == FIN_NORM) {
+    sum_partials<2, NT>(sv.part, nb, *reinterpret_cast<double(*)[2]>(tot), lds);
+  } else {
+    sum_partials<1, NT>(sv.part, nb, *reinterpret_cast<double(*)[1]>(tot), lds);
+  }
+  if (kind == FIN_VC32) {
+    // fixed order per thread (i, i + NT, ...), then a fixed tree; loads in batches
+    const float* pf = reinterpret_cast<const float*>(sv.part + nb);
+    for (int i0 = threadIdx.x; i0 < nb; i0 += kSumLanes * NT) {
+      float v[kSumLanes][4];
+#pragma unroll
+      for (int u = 0; u < kSumLanes; ++u) {
+        const int i = min(i0 + u * NT, nb - 1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[u][j] = pf[4 * i + j];
+      }
+#pragma unroll
+      for (int u = 0; u < kSumLanes; ++u)
+        if (i0 + u * NT < nb) {
+          c[0].merge(v[u][0], v[u][1]);
+          c[1].merge(v[u][2], v[u][3]);
+        }
+    }
+    block_dot2<2, NT>(c, lds32);
+  }
+  const bool t0 = threadIdx.x == 0;
+  if (was_done) {
+    if (t0 && sv.host_flags)
       __hip_atomic_store(&sv.host_flags[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     return;
   }
-  const bool t0 = threadIdx.x == 0;
-  if (kind == FIN_CGQ) {
-    double tot[1];
-    sum_partials<1>(sv.part, nb, tot, lds);
-    if (t0) {
+  int iters_out = iters, done_out = 0;
+  if (t0) {
+    if (kind == FIN_CGQ) {
       const double pq = tot[0];
       sv.sc[S_PQ] = pq;
       if (!(pq > 0.0) || !isfinite(pq)) {
         sv.fl[F_STATUS] = isfinite(pq) ? -4 : -5;
-        sv.fl[F_DONE] = 1;
+        done_out = 1;
       } else {
-        sv.sc[S_ALPHA] = sv.sc[S_RHO] / pq;
+        sv.sc[S_ALPHA] = rho_old / pq;
       }
-    }
-  } else if (kind == FIN_UPDATE) {
-    double tot[1];
-    sum_partials<1>(sv.part, nb, tot, lds);
-    if (t0) {
+    } else if (kind == FIN_UPDATE) {
       const double r2 = tot[0];
       sv.sc[S_RNORM2] = r2;
-      const int it = sv.fl[F_ITERS] + 1;
-      sv.fl[F_ITERS] = it;
-      int done = 0;
-      if (!isfinite(r2)) { sv.fl[F_STATUS] = -5; done = 1; }
-      else if (r2 <= sv.sc[S_TOL2]) { done = 1; }
-      else if (it >= sv.fl[F_MAXIT]) { sv.fl[F_STATUS] = 1; done = 1; }
-      if (done) sv.fl[F_DONE] = 1;
-    }
-  } else if (kind == FIN_VC64 || kind == FIN_VC32) {
-    double sz, rz, num;
-    if (kind == FIN_VC64) {
-      double tot[3];
-      sum_partials<3>(sv.part, nb, tot, lds);
-      const double mu = sv.fl[F_NULLSPACE] ? tot[0] / (double)sv.n : 0.0;
-      sz = tot[0];
-      rz = tot[1] - mu * tot[2];
-      num = rz;
-    } else {
-      double tot[1];
-      sum_partials<1>(sv.part, nb, tot, lds);
-      sz = tot[0];
-      Dot2 c[2];
-      const float* pf = reinterpret_cast<const float*>(sv.part + nb);
-      for (int i = threadIdx.x; i < nb; i += kBlock) {  // fixed order per thread, then a fixed tree
-        c[0].merge(pf[4 * i + 0], pf[4 * i + 1]);
-        c[1].merge(pf[4 * i + 2], pf[4 * i + 3]);
+      iters_out = iters + 1;
+      sv.fl[F_ITERS] = iters_out;
+      if (!isfinite(r2)) { sv.fl[F_STATUS] = -5; done_out = 1; }
+      else if (r2 <= tol2_in) { done_out = 1; }
+      else if (iters_out >= maxit) { sv.fl[F_STATUS] = 1; done_out = 1; }
+    } else if (kind == FIN_VC64 || kind == FIN_VC32) {
+      double sz, rz, num;
+      if (kind == FIN_VC64) {
+        const double mu = ns ? tot[0] / (double)sv.n : 0.0;
+        sz = tot[0];
+        rz = tot[1] - mu * tot[2];
+        num = rz;
+      } else {
+        sz = tot[0];
+        rz = (double)c[0].p + (double)c[0].s;
+        num = rz - ((double)c[1].p + (double)c[1].s);
       }
-      block_dot2<2>(c, lds32);
-      rz = (double)c[0].p + (double)c[0].s;
-      num = rz - ((double)c[1].p + (double)c[1].s);
-    }
-    if (t0) {
-      sv.sc[S_MU_Z] = sv.fl[F_NULLSPACE] ? sz / (double)sv.n : 0.0;
-      const double rho_old = sv.sc[S_RHO];
-      sv.sc[S_BETA] = sv.fl[F_FIRST] ? 0.0 : num / rho_old;
+      sv.sc[S_MU_Z] = ns ? sz / (double)sv.n : 0.0;
+      sv.sc[S_BETA] = first ? 0.0 : num / rho_old;
       sv.sc[S_RHO] = rz;
       if (!(rz > 0.0) || !isfinite(rz)) {
         sv.fl[F_STATUS] = isfinite(rz) ? -4 : -5;
-        sv.fl[F_DONE] = 1;
+        done_out = 1;
       }
-    }
-  } else if (kind == FIN_INIT) {
-    double tot[2];
-    sum_partials<2>(sv.part, nb, tot, lds);
-    if (t0) {
+    } else if (kind == FIN_INIT) {
       sv.sc[S_FNORM2] = tot[0];
       sv.sc[S_RNORM2] = tot[1];
-      const double tol2 = sv.sc[S_RTOL2] * tot[0];
+      const double tol2 = rtol2 * tot[0];
       sv.sc[S_TOL2] = tol2;
       if (!isfinite(tot[0]) || !isfinite(tot[1])) {
         sv.fl[F_STATUS] = -5;
-        sv.fl[F_DONE] = 1;
+        done_out = 1;
       } else if (tot[0] == 0.0 || tot[1] <= tol2) {
-        sv.fl[F_DONE] = 1;
+        done_out = 1;
       }
-    }
-  } else if (kind == FIN_TRUE) {
-    double tot[1];
-    sum_partials<1>(sv.part, nb, tot, lds);
-    if (t0) sv.sc[S_TRUE2] = tot[0];
-  } else if (kind == FIN_MEANS) {
-    double tot[2];
-    sum_partials<2>(sv.part, nb, tot, lds);
-    if (t0) {
-      const bool ns = sv.fl[F_NULLSPACE] != 0;
+    } else if (kind == FIN_TRUE) {
+      sv.sc[S_TRUE2] = tot[0];
+    } else if (kind == FIN_MEANS) {
       sv.sc[S_MU_B] = ns ? tot[0] / (double)sv.n : 0.0;
       sv.sc[S_MU_X] = ns ? tot[1] / (double)sv.n : 0.0;
-    }
-  } else if (kind == FIN_NORM) {
-    double tot[2];
-    sum_partials<2>(sv.part, nb, tot, lds);
-    if (t0) {
+    } else if (kind == FIN_NORM) {
       sv.sc[S_WX] = tot[0];
       sv.sc[S_WSUM] = tot[1];
     }
-  }
-  // pinned host mirror of (done, iterations) for the solve loops' convergence polling
-  if (threadIdx.x == 0 && sv.host_flags && (guarded || kind == FIN_INIT)) {
-    __hip_atomic_store(&sv.host_flags[1], sv.fl[F_ITERS], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(&sv.host_flags[0], sv.fl[F_DONE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (done_out) sv.fl[F_DONE] = 1;
+    // pinned host mirror of (done, iterations) for the solve loops' convergence polling
+    if (sv.host_flags && (guarded || kind == FIN_INIT)) {
+      __hip_atomic_store(&sv.host_flags[1], iters_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(&sv.host_flags[0], done_out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_finalize(Solve sv, int kind, int nb) {
-  __shared__ double lds[16];
-  __shared__ float lds32[24];
-  finalize_body(sv, kind, nb, lds, lds32);
+// One block of kFinBlock threads: the partials are few thousand values spread over the XCDs'
+// caches, so the sum is bound by memory latency and wants many reads in flight.
+constexpr int kFinBlock = 1024;
+__global__ __launch_bounds__(kFinBlock) void k_finalize(Solve sv, int kind, int nb) {
+  __shared__ double lds[3 * kFinBlock / 64];
+  __shared__ float lds32[2 * 2 * kFinBlock / 64];
+  finalize_body<kFinBlock>(sv, kind, nb, lds, lds32);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -794,10 +960,9 @@ template <typename T, int OP>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream_multi(const SpTask<T>* __restrict__ tasks, int ntasks) {
   __shared__ double lds[16];
   __shared__ float lds32[24];
-  __shared__ T prod[kStreamCap];
+  __shared__ T prod[kStageLen];
   const SpTask<T>& tk = tasks[task_of(tasks, ntasks)];
   const SpArgs<T> a = tk.a;
-  if (solve_done(a.sv)) return;
   stream_body<T, OP>(a, tk.blk, xcd_tile((int)blockIdx.x - tk.off, tk.nb), tk.nb, prod, lds, lds32);
 }
 
@@ -865,7 +1030,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize_multi(const FinTask* __rest
   __shared__ double lds[16];
   __shared__ float lds32[24];
   const FinTask& k = tasks[task_of(tasks, ntasks)];
-  finalize_body(k.sv, k.kind, k.nb_part, lds, lds32);
+  finalize_body<kBlock>(k.sv, k.kind, k.nb_part, lds, lds32);
 }
 
 // ---------------------------------------------------------------------------------------
