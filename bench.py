@@ -38,10 +38,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def spmv_bytes(n: int, nnz: int, s: int = 8) -> int:
-    """Algorithmic bytes of y = A x in CSR: values + column indices + row offsets, x read once,
-    y written once (the p^T q partials are negligible)."""
-    return nnz * (s + 4) + n * (4 + 2 * s)
+def spmv_bytes(n: int, nnz: int, s: int = 8, col_bytes: int = 4, tiles: int = 0) -> int:
+    """Algorithmic bytes of y = A x in CSR: values + column indices (4 bytes, or 2-byte offsets
+    from a per-tile base) + row offsets, x read once, y written once, the tile table (and the
+    per-tile column bases with 2-byte offsets); the p^T q partials are negligible."""
+    b = nnz * (s + col_bytes) + n * (4 + 2 * s)
+    if tiles:
+        b += 4 * (tiles + 1) + (4 * tiles if col_bytes == 2 else 0)
+    return b
 
 
 def traffic_from_profile(n, nnz):
@@ -291,12 +295,13 @@ def main():
     ell_s = info["ms_ell"] * 1e-3
     value = n * info["it_ell"] / ell_s
     avg_ms = prof_ms / max(prof_launches, 1)
-    bytes_launch = spmv_bytes(n, nnz)
+    bytes_launch = spmv_bytes(n, nnz, 8, info_e["col_bytes"][0], info_e["tiles"][0])
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic_from_profile(n, nnz),
                     kernel="k_spmv_stream<double, 8> (OP_CG_Q: outer q = A p on the fine operator, with p^T q)",
-                    bytes_per_launch=bytes_launch, avg_launch_ms=round(avg_ms, 5), launches=prof_launches)
+                    bytes_per_launch=bytes_launch, column_index_bytes=info_e["col_bytes"][0],
+                    avg_launch_ms=round(avg_ms, 5), launches=prof_launches)
 
     out = {
         "metric": "elliptic PCG-AMG DOF*iters/s",

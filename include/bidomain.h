@@ -106,6 +106,11 @@ typedef struct {
   double operator_complexity;
   double grid_complexity;
   int64_t device_bytes;           /* device memory owned by the handle                    */
+  /* The level operator's product on the device (0 on a host-only handle): bytes per column
+   * index it reads (4, or 2 for 16-bit offsets from a per-tile column base) and its row
+   * tiles (0 when rows are too long for the staging buffer and a lane-group kernel runs). */
+  int32_t col_bytes[BD_MAX_LEVELS];
+  int64_t tiles[BD_MAX_LEVELS];
 } bd_amg_stats;
 
 /*

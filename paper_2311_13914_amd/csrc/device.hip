@@ -70,17 +70,25 @@ struct Arena {
   }
 };
 
-template <typename T>
-struct DCsr {
+// Sparsity pattern of a device matrix and its launch plan (shared by matrices with the same
+// pattern, e.g. the float64 and float32 copies of the fine operator).
+struct DPat {
   int n = 0, ncols = 0;
   int64_t nnz = 0;
   const int* rp = nullptr;
-  const int* ci = nullptr;
-  T* v = nullptr;
+  const int* ci = nullptr;        // 32-bit column indices, or null when only cs is kept
+  const uint16_t* cs = nullptr;   // CSR-stream: column - cbase[tile] (16 bits), or null
+  const int* cbase = nullptr;     // CSR-stream: per-tile column base, with cs
   int G = 8;    // lanes per row (row-group kernel)
   int tpb = 1;  // row tiles per block (row-group kernel)
   int nb = 0;   // blocks of a product launch
   const int* blk = nullptr;  // CSR-stream row tiles (nb + 1 row boundaries), or null
+  int col_bytes() const { return cs ? 2 : 4; }
+};
+
+template <typename T>
+struct DCsr : DPat {
+  T* v = nullptr;
 };
 
 int lanes_for(double mean_row) {
@@ -121,8 +129,7 @@ std::vector<int> stream_blocks(const Csr& H) {
   return pack_tiles(H, max_rows, kStreamCap);
 }
 
-template <typename T>
-void configure(DCsr<T>& M, int max_blocks) {
+void configure(DPat& M, int max_blocks) {
   M.G = lanes_for(M.n ? (double)M.nnz / M.n : 1.0);
   const int rpt = kBlock / M.G;
   const int64_t tiles = (M.n + rpt - 1) / rpt;
@@ -130,40 +137,76 @@ void configure(DCsr<T>& M, int max_blocks) {
   M.nb = (int)std::max<int64_t>(1, (tiles + M.tpb - 1) / M.tpb);
 }
 
+// Per-tile 16-bit column offsets: every tile's columns span fewer than 65,536 values (a
+// 27-point stencil spans two grid planes around a tile's rows), so each entry stores
+// column - cbase[tile] in 16 bits instead of a 32-bit index.  Empty result if some tile spans
+// more (the matrix then keeps 32-bit indices).
+bool compact_columns(const Csr& H, const std::vector<int>& blk, std::vector<uint16_t>& cs, std::vector<int>& cbase) {
+  const int nb = (int)blk.size() - 1;
+  cbase.assign(nb, 0);
+  cs.assign(H.ci.size(), 0);
+  for (int t = 0; t < nb; ++t) {
+    const int32_t beg = H.rp[blk[t]], end = H.rp[blk[t + 1]];
+    if (end == beg) continue;
+    int32_t lo = H.ci[beg], hi = H.ci[beg];
+    for (int32_t k = beg; k < end; ++k) {
+      lo = std::min(lo, H.ci[k]);
+      hi = std::max(hi, H.ci[k]);
+    }
+    if (hi - lo > 65535) return false;
+    cbase[t] = lo;
+    for (int32_t k = beg; k < end; ++k) cs[k] = (uint16_t)(H.ci[k] - lo);
+  }
+  return true;
+}
+
+template <typename U>
+U* upload_padded(Arena& ar, const U* src, size_t count, hipStream_t st) {
+  U* d = ar.alloc<U>(count + kStreamPad);  // padded for 4-entry vector loads
+  HIPCHK(hipMemsetAsync(d + count, 0, kStreamPad * sizeof(U), st));
+  if (count) HIPCHK(hipMemcpyAsync(d, src, count * sizeof(U), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return d;
+}
+
+// Device copy of H with values of type T.  share: a pattern uploaded before for the same H
+// (reused as is), or null.  need_ci: keep the 32-bit column indices even where the product
+// reads 16-bit offsets (for kernels outside the product that read them).
 template <typename T>
-DCsr<T> upload(Arena& ar, const Csr& H, const int* rp_shared, const int* ci_shared, hipStream_t st,
-               int max_blocks) {
+DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, bool need_ci, hipStream_t st, int max_blocks) {
   DCsr<T> M;
-  M.n = H.nrows;
-  M.ncols = H.ncols;
-  M.nnz = H.nnz();
-  if (rp_shared) {
-    M.rp = rp_shared;
-    M.ci = ci_shared;
+  if (share) {
+    static_cast<DPat&>(M) = *share;
   } else {
+    M.n = H.nrows;
+    M.ncols = H.ncols;
+    M.nnz = H.nnz();
     int* rp = ar.alloc<int>(H.rp.size());
-    int* ci = ar.alloc<int>(H.ci.size() + kStreamPad);  // padded for 4-entry vector loads
-    HIPCHK(hipMemsetAsync(ci + H.ci.size(), 0, kStreamPad * sizeof(int), st));
     HIPCHK(hipMemcpyAsync(rp, H.rp.data(), H.rp.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ci, H.ci.data(), H.ci.size() * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
     M.rp = rp;
-    M.ci = ci;
+    configure(M, max_blocks);
+    const std::vector<int> blk = stream_blocks(H);
+    std::vector<uint16_t> cs;
+    std::vector<int> cbase;
+    const bool compact = !blk.empty() && compact_columns(H, blk, cs, cbase);
+    if (!blk.empty()) {
+      int* d = ar.alloc<int>(blk.size());
+      HIPCHK(hipMemcpyAsync(d, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+      M.blk = d;
+      M.nb = (int)blk.size() - 1;
+    }
+    if (compact) {
+      M.cs = upload_padded<uint16_t>(ar, cs.data(), cs.size(), st);
+      int* d = ar.alloc<int>(cbase.size());
+      HIPCHK(hipMemcpyAsync(d, cbase.data(), cbase.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+      M.cbase = d;
+    }
+    if (!compact || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
   }
-  M.v = ar.alloc<T>(H.v.size() + kStreamPad);
-  HIPCHK(hipMemsetAsync(M.v + H.v.size(), 0, kStreamPad * sizeof(T), st));
-  std::vector<T> tmp(H.v.begin(), H.v.end());
-  HIPCHK(hipMemcpyAsync(M.v, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
-  configure(M, max_blocks);
-  const std::vector<int> blk = stream_blocks(H);
-  if (!blk.empty()) {
-    int* d = ar.alloc<int>(blk.size());
-    HIPCHK(hipMemcpyAsync(d, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
-    M.blk = d;
-    M.nb = (int)blk.size() - 1;
-  }
+  M.v = upload_padded<T>(ar, std::vector<T>(H.v.begin(), H.v.end()).data(), H.v.size(), st);
   return M;
 }
 
@@ -240,16 +283,26 @@ namespace bd {
 
 // ------------------------------------------------------------------------------------------
 // Kernel launch helpers.
-template <typename T, int OP>
-void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
+// The matrix fields of a product's arguments.
+template <typename T>
+void bind(SpArgs<T>& a, const DCsr<T>& M) {
   a.rp = M.rp;
   a.ci = M.ci;
+  a.cs = M.cs;
+  a.cbase = M.cbase;
+  a.ncols = M.ncols;
   a.av = M.v;
   a.nrows = M.n;
   a.tpb = M.tpb;
+}
+
+template <typename T, int OP>
+void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
+  bind(a, M);
   if (M.n == 0) return;
   if (M.blk) {
-    k_spmv_stream<T, OP><<<M.nb, kBlock, 0, st>>>(a, M.blk);
+    if (M.cs) k_spmv_stream<T, OP, true><<<M.nb, kBlock, 0, st>>>(a, M.blk);
+    else k_spmv_stream<T, OP, false><<<M.nb, kBlock, 0, st>>>(a, M.blk);
     HIPCHK(hipGetLastError());
     return;
   }
@@ -462,10 +515,10 @@ void build_levels(bd_amg* h, hipStream_t st) {
       if (k == 0) D.A = h->A0;  // level 0 of the float64 V-cycle is the outer operator itself
     }
     if (D.A.n == 0)
-      D.A = upload<T>(h->ar, HL[k].A, k == 0 ? h->A0.rp : nullptr, k == 0 ? h->A0.ci : nullptr, st, kMaxBlocksSpmv);
+      D.A = upload<T>(h->ar, HL[k].A, k == 0 ? &h->A0 : nullptr, false, st, kMaxBlocksSpmv);
     if (k < nl - 1) {
-      D.P = upload<T>(h->ar, HL[k].P, nullptr, nullptr, st, kMaxBlocksSpmv);
-      D.R = upload<T>(h->ar, HL[k].R, nullptr, nullptr, st, kMaxBlocksSpmv);
+      D.P = upload<T>(h->ar, HL[k].P, nullptr, false, st, kMaxBlocksSpmv);
+      D.R = upload<T>(h->ar, HL[k].R, nullptr, false, st, kMaxBlocksSpmv);
     }
     D.dinv = upload_vec<T>(h->ar, HL[k].Dinv, st);
     if (k > 0) D.f = h->ar.alloc<T>(D.n);
@@ -772,8 +825,10 @@ __global__ __launch_bounds__(kBlock) void k_neg_spmv(const int* __restrict__ rp,
 
 // Second half of the setup phase: copy a host-built hierarchy into HBM and allocate the
 // solve state.  weights: n host doubles (normalisation weights) or null.
-void device_upload(bd_amg* h, const double* weights, hipStream_t st) {
-  h->A0 = upload<double>(h->ar, h->H.lv[0].A, nullptr, nullptr, st, kMaxBlocksSpmv);
+// need_ci: keep the fine operator's 32-bit column indices (a simulation's A_i shares its
+// pattern and the step kernels read them).
+void device_upload(bd_amg* h, const double* weights, bool need_ci, hipStream_t st) {
+  h->A0 = upload<double>(h->ar, h->H.lv[0].A, nullptr, need_ci, st, kMaxBlocksSpmv);
   if (h->mixed) build_levels<float>(h, st);
   else build_levels<double>(h, st);
   if (h->H.coarse_mode == 0) {
@@ -820,7 +875,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   if (rc != BD_OK) throw Failure{rc, err};
   h->M = (int)h->H.lv.size() - 1;
   h->host_only = true;
-  if (!host_only) device_upload(h.get(), weights, st);
+  if (!host_only) device_upload(h.get(), weights, false, st);
   *out = h.release();
   return BD_OK;
 }
@@ -878,9 +933,9 @@ std::unique_ptr<bd_sim> upload_sim(SimHost& H, const double* v0, bool v0_dev, co
   S->hell = H.hell;
   S->hpar = H.hpar;
   H.hell = H.hpar = nullptr;
-  device_upload(S->hell, H.m.data(), st);
-  device_upload(S->hpar, nullptr, st);
-  S->Ai = upload<double>(S->ar, H.Ai, S->hell->A0.rp, S->hell->A0.ci, st, kMaxBlocksSpmv);
+  device_upload(S->hell, H.m.data(), true, st);
+  device_upload(S->hpar, nullptr, false, st);
+  S->Ai = upload<double>(S->ar, H.Ai, &S->hell->A0, false, st, kMaxBlocksSpmv);
   S->v = S->ar.alloc<double>(n);
   S->ue = S->ar.alloc<double>(n);
   S->w = S->ar.alloc<double>(n);
@@ -960,6 +1015,14 @@ int bidomain_amg_info(const bd_amg* h, bd_amg_stats* s) {
       s->lambda[k] = L[k].lam;
       nnz += (double)L[k].A.nnz();
       nn += L[k].A.nrows;
+    }
+    if (!h->host_only) {
+      for (size_t k = 0; k < L.size() && k < BD_MAX_LEVELS; ++k) {
+        const DPat& M = k == 0 ? static_cast<const DPat&>(h->A0)
+                               : (h->mixed ? static_cast<const DPat&>(h->L32[k].A) : static_cast<const DPat&>(h->L64[k].A));
+        s->col_bytes[k] = M.col_bytes();
+        s->tiles[k] = M.blk ? M.nb : 0;
+      }
     }
     s->coarse_mode = h->H.coarse_mode;
     s->operator_complexity = nnz / (double)L[0].A.nnz();
@@ -1264,8 +1327,9 @@ void launch_tasks(std::vector<Task>& v, hipStream_t st, Staging& stg, Launch lau
 // One sub-step of a round across all solves: the ops it collects are independent.
 template <typename T>
 struct Batch {
-  std::vector<SpTask<T>> sp[OP_TRUE_RESID + 1];
-  std::vector<SpTask<double>> cgq;  // outer products (always float64)
+  // products by index form (0: 32-bit columns, 1: 16-bit offsets) and op
+  std::vector<SpTask<T>> sp[2][OP_TRUE_RESID + 1];
+  std::vector<SpTask<double>> cgq[2];  // outer products (always float64)
   std::vector<UpdTask<T>> upd;
   std::vector<DirTask<T>> dir;
   std::vector<GemvTask<T>> gemv;
@@ -1279,25 +1343,24 @@ struct Batch {
       single.push_back([=] { launch_spmv<T, OP>(M, a, st); });
       return;
     }
-    a.rp = M.rp;
-    a.ci = M.ci;
-    a.av = M.v;
-    a.nrows = M.n;
-    a.tpb = M.tpb;
+    bind(a, M);
     SpTask<T> t;
     t.a = a;
     t.blk = M.blk;
     t.nb = M.nb;
     t.off = 0;
-    sp[OP].push_back(t);
+    sp[M.cs ? 1 : 0][OP].push_back(t);
   }
 
   void flush(hipStream_t st, Staging& stg) {
     for (auto& f : single) f();
     single.clear();
 #define BD_SPL(OPV)                                                                                      \
-  launch_tasks(sp[OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                                \
-    k_spmv_stream_multi<T, OPV><<<nb, kBlock, 0, st>>>(d, n);                                            \
+  launch_tasks(sp[0][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                             \
+    k_spmv_stream_multi<T, OPV, false><<<nb, kBlock, 0, st>>>(d, n);                                     \
+  });                                                                                                    \
+  launch_tasks(sp[1][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                             \
+    k_spmv_stream_multi<T, OPV, true><<<nb, kBlock, 0, st>>>(d, n);                                      \
   });
     BD_SPL(OP_Y)
     BD_SPL(OP_ADDY)
@@ -1307,8 +1370,11 @@ struct Batch {
     BD_SPL(OP_CHEB_POST0)
     BD_SPL(OP_CHEB_STEP)
 #undef BD_SPL
-    launch_tasks(cgq, st, stg, [&](const SpTask<double>* d, int n, int nb) {
-      k_spmv_stream_multi<double, OP_CG_Q><<<nb, kBlock, 0, st>>>(d, n);
+    launch_tasks(cgq[0], st, stg, [&](const SpTask<double>* d, int n, int nb) {
+      k_spmv_stream_multi<double, OP_CG_Q, false><<<nb, kBlock, 0, st>>>(d, n);
+    });
+    launch_tasks(cgq[1], st, stg, [&](const SpTask<double>* d, int n, int nb) {
+      k_spmv_stream_multi<double, OP_CG_Q, true><<<nb, kBlock, 0, st>>>(d, n);
     });
     launch_tasks(upd, st, stg, [&](const UpdTask<T>* d, int n, int nb) { k_cg_update_multi<T><<<nb, kBlock, 0, st>>>(d, n); });
     launch_tasks(dir, st, stg, [&](const DirTask<T>* d, int n, int nb) { k_cg_direction_multi<T><<<nb, kBlock, 0, st>>>(d, n); });
@@ -1488,10 +1554,10 @@ void batched_round(std::vector<BInst*>& I, hipStream_t st, Staging& stg) {
     SpArgs<double> a = args<double>(i->h->sv);
     a.x = i->h->p; a.y = i->h->q;
     if (M.blk) {
-      a.rp = M.rp; a.ci = M.ci; a.av = M.v; a.nrows = M.n; a.tpb = M.tpb;
+      bind(a, M);
       SpTask<double> t;
       t.a = a; t.blk = M.blk; t.nb = M.nb; t.off = 0;
-      B.cgq.push_back(t);
+      B.cgq[M.cs ? 1 : 0].push_back(t);
     } else {
       const DCsr<double> Mc = M;
       B.single.push_back([=] { launch_spmv<double, OP_CG_Q>(Mc, a, st); });

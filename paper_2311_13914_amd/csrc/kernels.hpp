@@ -252,7 +252,10 @@ enum VcRed : int { RED_NONE = 0, RED_F64 = 1, RED_F32 = 2 };
 template <typename T>
 struct SpArgs {
   const int* rp;
-  const int* ci;
+  const int* ci;          // 32-bit column indices (null when cs is used)
+  const uint16_t* cs;     // CSR-stream only: column - cbase[tile], or null
+  const int* cbase;       // CSR-stream only: per-tile column base, with cs
+  int ncols;
   const T* av;
   int nrows;
   int tpb;           // row tiles per block
@@ -464,12 +467,14 @@ __device__ __forceinline__ void load4(const float* p, float (&v)[4]) {
 // Rows and entry range of one tile, plus the row-offset pair of this thread's phase-2 row.
 struct Tile {
   int r0, r1, beg, end;
+  int cb;      // column base of the tile's 16-bit column offsets (0 with 32-bit indices)
   int k0;      // beg rounded down to a multiple of 4: LDS slot 0 holds entry k0
   int lo, hi;  // rp[row], rp[row + 1] of this thread's phase-2 row
   int g;       // lanes per row in phase 2: a power of two, at most 64
 };
 
-// Matrix entries of one tile held in registers between phase 1's loads and its gathers.
+// Matrix entries of one tile held in registers between phase 1's loads and its gathers:
+// four 32-bit column indices per chunk, or (16-bit offsets) two words of two offsets each.
 template <typename T>
 struct TileRegs {
   int c[kStreamChunks][4];
@@ -481,12 +486,15 @@ struct TileRegs {
 constexpr int kStageLen = 4 * ((kStreamCap + 2) / 4 + 1);
 static_assert(kStageLen <= kStreamChunks * 4 * kBlock, "every spanned chunk has a thread");
 
-__device__ __forceinline__ Tile tile_open(const int* __restrict__ rp, const int* __restrict__ blk, int b) {
+template <bool CS>
+__device__ __forceinline__ Tile tile_open(const int* __restrict__ rp, const int* __restrict__ blk,
+                                          const int* __restrict__ cbase, int b) {
   Tile t;
   t.r0 = blk[b];
   t.r1 = blk[b + 1];
   t.beg = rp[t.r0];
   t.end = rp[t.r1];
+  t.cb = CS ? cbase[b] : 0;
   t.k0 = t.beg & ~3;
   const int nrow = t.r1 - t.r0;
   int g = kBlock / (nrow > 0 ? nrow : 1);
@@ -501,26 +509,47 @@ __device__ __forceinline__ Tile tile_open(const int* __restrict__ rp, const int*
 // Phase 1, loads: the 4-entry chunks (aligned to 4) spanning the tile's entries [beg, end).
 // Branch-free so that every chunk load is in flight at once: chunk positions past the tile are
 // clamped to its last chunk.  Entries outside [beg, end) are neighbouring rows' or the zero
-// padding of the arrays (kStreamPad entries past nnz), so every loaded column index is valid.
-template <typename T>
+// padding of the arrays (kStreamPad entries past nnz), so every 32-bit column index is valid;
+// CS (16-bit offsets): offsets of a neighbouring tile decode against this tile's base and are
+// clamped into [0, ncols) at the gather.  The index form is a template parameter: a run-time
+// branch around the loads made the compiler wait for them at the join.
+template <typename T, bool CS>
 __device__ __forceinline__ void tile_load(const SpArgs<T>& a, const Tile& t, TileRegs<T>& R) {
   const int klast = max(t.k0, (t.end - 1) & ~3);
 #pragma unroll
   for (int c = 0; c < kStreamChunks; ++c) {
     const int k = min(t.k0 + 4 * ((int)threadIdx.x + kBlock * c), klast);
-    const int4 cc = *reinterpret_cast<const int4*>(a.ci + k);
-    R.c[c][0] = cc.x; R.c[c][1] = cc.y; R.c[c][2] = cc.z; R.c[c][3] = cc.w;
+    if constexpr (CS) {
+      const uint2 cc = *reinterpret_cast<const uint2*>(a.cs + k);
+      R.c[c][0] = (int)cc.x; R.c[c][1] = (int)cc.y;
+    } else {
+      const int4 cc = *reinterpret_cast<const int4*>(a.ci + k);
+      R.c[c][0] = cc.x; R.c[c][1] = cc.y; R.c[c][2] = cc.z; R.c[c][3] = cc.w;
+    }
     load4(a.av + k, R.v[c]);
   }
 }
 
 // Phase 1, gathers of x at the loaded columns (issued together).
-template <typename T>
-__device__ __forceinline__ void tile_gather(const SpArgs<T>& a, const TileRegs<T>& R, T (&xv)[kStreamChunks][4]) {
+template <typename T, bool CS>
+__device__ __forceinline__ void tile_gather(const SpArgs<T>& a, const Tile& t, const TileRegs<T>& R,
+                                            T (&xv)[kStreamChunks][4]) {
+  if constexpr (CS) {
+    const int cmax = a.ncols - 1;
 #pragma unroll
-  for (int c = 0; c < kStreamChunks; ++c)
+    for (int c = 0; c < kStreamChunks; ++c) {
+      const unsigned w0 = (unsigned)R.c[c][0], w1 = (unsigned)R.c[c][1];
+      xv[c][0] = a.x[min(t.cb + (int)(w0 & 0xffffu), cmax)];
+      xv[c][1] = a.x[min(t.cb + (int)(w0 >> 16), cmax)];
+      xv[c][2] = a.x[min(t.cb + (int)(w1 & 0xffffu), cmax)];
+      xv[c][3] = a.x[min(t.cb + (int)(w1 >> 16), cmax)];
+    }
+  } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) xv[c][j] = a.x[R.c[c][j]];
+    for (int c = 0; c < kStreamChunks; ++c)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) xv[c][j] = a.x[R.c[c][j]];
+  }
 }
 
 // Phase 1, products a_k x_{c_k} into LDS slot k - k0.  Every chunk is stored whole: entries of
@@ -562,30 +591,34 @@ __device__ __forceinline__ void tile_reduce(const SpArgs<T>& a, const Tile& t, c
   block_tail<T, OP>(a, acc, vc, bi, nb, lds, lds32);
 }
 
-// Body of the CSR-stream product for row tile b of nb (b also indexes the block partials).
-// (Testing the solve's done flag only after the tile's reads are issued, to overlap its
-// latency, measured slower: the branch keeps every loaded register live across it.)
-template <typename T, int OP>
+// Body of the CSR-stream product for row tile b of nb (b also indexes the block partials);
+// CS: the matrix stores 16-bit column offsets (a.cs, a.cbase) instead of 32-bit indices.
+// (Testing the solve's done flag only after the tile's vector reads are issued measured
+// slower: the branch keeps every loaded register live across it.)
+template <typename T, int OP, bool CS>
 __device__ __forceinline__ void stream_body(const SpArgs<T>& a, const int* __restrict__ blk, int b, int nb, T* prod,
                                             double* lds, float* lds32) {
-  if (solve_done(a.sv)) return;
-  const Tile t = tile_open(a.rp, blk, b);
+  // The done flag (written by an earlier kernel, so a plain load sees it) is read together
+  // with the tile bounds and tested before any vector load: one scalar round trip fewer.
+  const int done = a.sv.fl[F_DONE];
+  const Tile t = tile_open<CS>(a.rp, blk, a.cbase, b);
+  if (done) return;
   TileRegs<T> R;
   T xv[kStreamChunks][4];
-  tile_load(a, t, R);
-  tile_gather(a, R, xv);
+  tile_load<T, CS>(a, t, R);
+  tile_gather<T, CS>(a, t, R, xv);
   const RowIn<T> in = tile_fetch<T, OP>(a, t);
   tile_stage(t, R, xv, prod);
   __syncthreads();
   tile_reduce<T, OP>(a, t, in, b, nb, prod, lds, lds32);
 }
 
-template <typename T, int OP>
+template <typename T, int OP, bool CS>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* __restrict__ blk) {
   __shared__ double lds[16];
   __shared__ float lds32[24];
   __shared__ T prod[kStageLen];
-  stream_body<T, OP>(a, blk, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, prod, lds, lds32);
+  stream_body<T, OP, CS>(a, blk, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, prod, lds, lds32);
 }
 
 
@@ -956,14 +989,14 @@ struct SpTask {
   int nb, off;
 };
 
-template <typename T, int OP>
+template <typename T, int OP, bool CS>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream_multi(const SpTask<T>* __restrict__ tasks, int ntasks) {
   __shared__ double lds[16];
   __shared__ float lds32[24];
   __shared__ T prod[kStageLen];
   const SpTask<T>& tk = tasks[task_of(tasks, ntasks)];
   const SpArgs<T> a = tk.a;
-  stream_body<T, OP>(a, tk.blk, xcd_tile((int)blockIdx.x - tk.off, tk.nb), tk.nb, prod, lds, lds32);
+  stream_body<T, OP, CS>(a, tk.blk, xcd_tile((int)blockIdx.x - tk.off, tk.nb), tk.nb, prod, lds, lds32);
 }
 
 template <typename T>
