@@ -46,18 +46,21 @@ Csr transpose(const Csr& A) {
   return T;
 }
 
-Csr spgemm(const Csr& A, const Csr& B) {
+// C = A B with products accumulated in the order of A's row, then B's rows, into a dense
+// accumulator with a row-stamped marker.  Sparse products (a few partial products per entry
+// of A) take a symbolic pass for the row sizes and write C in place.  Dense ones (the coarse
+// levels of smoothed aggregation, where rows of A P fill most of the coarse columns) take one
+// numeric pass into per-thread buffers, since a symbolic pass would repeat the whole product;
+// their rows accumulate without a branch and are emitted by a scan of the marker.
+namespace {
+Csr spgemm_sparse(const Csr& A, const Csr& B) {
   Csr C;
   C.nrows = A.nrows;
   C.ncols = B.ncols;
   C.rp.assign((size_t)C.nrows + 1, 0);
-  const int nt = omp_get_max_threads();
-  std::vector<std::vector<int32_t>> mark(nt, std::vector<int32_t>());
-  // symbolic pass: row sizes
 #pragma omp parallel
   {
-    std::vector<int32_t>& mk = mark[omp_get_thread_num()];
-    mk.assign(B.ncols, -1);
+    std::vector<int32_t> mk(B.ncols, -1);
 #pragma omp for schedule(dynamic, 16)
     for (int32_t i = 0; i < A.nrows; ++i) {
       int32_t cnt = 0;
@@ -75,11 +78,9 @@ Csr spgemm(const Csr& A, const Csr& B) {
   for (int32_t i = 0; i < C.nrows; ++i) C.rp[i + 1] += C.rp[i];
   C.ci.resize(C.rp[C.nrows]);
   C.v.resize(C.rp[C.nrows]);
-  // numeric pass: accumulate in the order of A's row then B's rows, then sort the columns
 #pragma omp parallel
   {
-    std::vector<int32_t>& mk = mark[omp_get_thread_num()];
-    std::fill(mk.begin(), mk.end(), -1);
+    std::vector<int32_t> mk(B.ncols, -1);
     std::vector<double> acc(B.ncols, 0.0);
     std::vector<int32_t> cols;
 #pragma omp for schedule(dynamic, 16)
@@ -109,6 +110,68 @@ Csr spgemm(const Csr& A, const Csr& B) {
     }
   }
   return C;
+}
+
+Csr spgemm_dense(const Csr& A, const Csr& B) {
+  Csr C;
+  C.nrows = A.nrows;
+  C.ncols = B.ncols;
+  C.rp.assign((size_t)C.nrows + 1, 0);
+  const int nt = omp_get_max_threads();
+  std::vector<std::vector<int32_t>> bci(nt);
+  std::vector<std::vector<double>> bv(nt);
+  std::vector<int64_t> row_off(C.nrows);  // row start in its thread's buffer
+  std::vector<int32_t> row_thr(C.nrows);
+#pragma omp parallel
+  {
+    const int tid = omp_get_thread_num();
+    std::vector<int32_t> mk(B.ncols, -1);
+    std::vector<double> acc(B.ncols, 0.0);  // zero outside the row being accumulated
+    std::vector<int32_t>& oc = bci[tid];
+    std::vector<double>& ov = bv[tid];
+#pragma omp for schedule(dynamic, 4)
+    for (int32_t i = 0; i < A.nrows; ++i) {
+      for (int32_t ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
+        const int32_t k = A.ci[ka];
+        const double a = A.v[ka];
+        for (int32_t kb = B.rp[k]; kb < B.rp[k + 1]; ++kb) {
+          const int32_t j = B.ci[kb];
+          acc[j] += a * B.v[kb];
+          mk[j] = i;
+        }
+      }
+      row_off[i] = (int64_t)oc.size();
+      row_thr[i] = tid;
+      for (int32_t j = 0; j < B.ncols; ++j)
+        if (mk[j] == i) {
+          oc.push_back(j);
+          ov.push_back(acc[j]);
+          acc[j] = 0.0;
+        }
+      C.rp[i + 1] = (int32_t)((int64_t)oc.size() - row_off[i]);
+    }
+  }
+  for (int32_t i = 0; i < C.nrows; ++i) C.rp[i + 1] += C.rp[i];
+  C.ci.resize(C.rp[C.nrows]);
+  C.v.resize(C.rp[C.nrows]);
+#pragma omp parallel for schedule(static, 256)
+  for (int32_t i = 0; i < C.nrows; ++i) {
+    const int64_t len = C.rp[i + 1] - C.rp[i];
+    std::copy_n(bci[row_thr[i]].data() + row_off[i], len, C.ci.data() + C.rp[i]);
+    std::copy_n(bv[row_thr[i]].data() + row_off[i], len, C.v.data() + C.rp[i]);
+  }
+  return C;
+}
+}  // namespace
+
+Csr spgemm(const Csr& A, const Csr& B) {
+  // partial products per row, on average, against the output width
+  int64_t flops = 0;
+#pragma omp parallel for reduction(+ : flops) schedule(static, 4096)
+  for (int32_t i = 0; i < A.nrows; ++i)
+    for (int32_t ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) flops += B.rp[A.ci[ka] + 1] - B.rp[A.ci[ka]];
+  const bool dense = A.nrows > 0 && (double)flops / A.nrows > 0.25 * (double)B.ncols;
+  return dense ? spgemm_dense(A, B) : spgemm_sparse(A, B);
 }
 
 std::vector<double> diagonal(const Csr& A) {
