@@ -48,6 +48,24 @@ def spmv_bytes(n: int, nnz: int, s: int = 8, col_bytes: int = 4, tiles: int = 0)
     return b
 
 
+def iteration_bytes(info: dict, s: int) -> int:
+    """Algorithmic bytes of one PCG iteration by the cost model of the solve phase: the outer
+    float64 product, then per level k below the coarsest 4 products with A_k (pre-smoothing,
+    residual, two post-smoothing steps), one with R_k and one with P_k, about 6 level vectors
+    streamed by their epilogues, plus about 10 fine float64 vector streams of the CG updates and
+    the dense coarsest GEMV.  s: bytes per V-cycle value (8, or 4 for the float32 V-cycle)."""
+    n, nnz, L = info["n"], info["nnz"], info["nlevels"]
+    b = spmv_bytes(n[0], nnz[0], 8, info["col_bytes"][0], info["tiles"][0])
+    for k in range(L - 1):
+        b += 4 * spmv_bytes(n[k], nnz[k], s, info["col_bytes"][k], info["tiles"][k])
+        pn = info["p_nnz"][k]
+        b += pn * (s + info["col_bytes_r"][k]) + n[k + 1] * (4 + s) + n[k] * s  # R_k: n_{k+1} rows
+        b += pn * (s + info["col_bytes_p"][k]) + n[k] * (4 + 2 * s) + n[k + 1] * s  # P_k: y += P e
+        b += 6 * n[k] * s
+    b += 10 * n[0] * 8 + n[L - 1] * n[L - 1] * 8
+    return b
+
+
 def traffic_from_profile(n, nnz):
     """Measured HBM bytes per launch of the outer product, from the committed rocprofv3 counter
     summary -- only while the kernel sources are the ones that were profiled."""
@@ -297,6 +315,13 @@ def main():
     avg_ms = prof_ms / max(prof_launches, 1)
     bytes_launch = spmv_bytes(n, nnz, 8, info_e["col_bytes"][0], info_e["tiles"][0])
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    it_bytes = iteration_bytes(info_e, 4 if args.mixed else 8)
+    it_ms = info["ms_ell"] / max(info["it_ell"], 1)
+    it_gbs = it_bytes / (it_ms * 1e-3) / 1e9
+    iteration = dict(bytes=it_bytes, ms=round(it_ms, 4), achieved=round(it_gbs, 1),
+                     frac=round(it_gbs / PEAK_HBM_GBS, 4),
+                     note="whole elliptic PCG iteration (outer product, V-cycle, CG updates) by the cost "
+                          "model of iteration_bytes, over elliptic solve time / iterations")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic_from_profile(n, nnz),
                     kernel="k_spmv_stream<double, 8> (OP_CG_Q: outer q = A p on the fine operator, with p^T q)",
@@ -328,6 +353,7 @@ def main():
         "iters_per_step": {"par": info["it_par"] / args.steps, "ell": info["it_ell"] / args.steps},
         "setup_s": round(setup_s, 2),
         "roofline": roofline,
+        "iteration_roofline": iteration,
     }
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -111,6 +111,8 @@ typedef struct {
    * tiles (0 when rows are too long for the staging buffer and a lane-group kernel runs). */
   int32_t col_bytes[BD_MAX_LEVELS];
   int64_t tiles[BD_MAX_LEVELS];
+  int32_t col_bytes_p[BD_MAX_LEVELS];  /* the same for P_k and R_k (0 on the coarsest level) */
+  int32_t col_bytes_r[BD_MAX_LEVELS];
 } bd_amg_stats;
 
 /*

@@ -55,7 +55,8 @@ class bd_amg_stats(C.Structure):
                 ("p_nnz", C.c_int64 * BD_MAX_LEVELS), ("lambda_", C.c_double * BD_MAX_LEVELS),
                 ("coarse_mode", C.c_int32), ("operator_complexity", C.c_double), ("grid_complexity", C.c_double),
                 ("device_bytes", C.c_int64), ("col_bytes", C.c_int32 * BD_MAX_LEVELS),
-                ("tiles", C.c_int64 * BD_MAX_LEVELS)]
+                ("tiles", C.c_int64 * BD_MAX_LEVELS), ("col_bytes_p", C.c_int32 * BD_MAX_LEVELS),
+                ("col_bytes_r", C.c_int32 * BD_MAX_LEVELS)]
 
 
 class bd_slab(C.Structure):
@@ -249,7 +250,7 @@ def bidomain_amg_info(h) -> dict:
     return dict(nlevels=L, n=list(s.n[:L]), nnz=list(s.nnz[:L]), p_nnz=list(s.p_nnz[:L]),
                 lam=list(s.lambda_[:L]), coarse_mode=s.coarse_mode, operator_complexity=s.operator_complexity,
                 grid_complexity=s.grid_complexity, device_bytes=s.device_bytes, col_bytes=list(s.col_bytes[:L]),
-                tiles=list(s.tiles[:L]))
+                tiles=list(s.tiles[:L]), col_bytes_p=list(s.col_bytes_p[:L]), col_bytes_r=list(s.col_bytes_r[:L]))
 
 
 def bidomain_amg_destroy(h):

@@ -1022,6 +1022,12 @@ int bidomain_amg_info(const bd_amg* h, bd_amg_stats* s) {
                                : (h->mixed ? static_cast<const DPat&>(h->L32[k].A) : static_cast<const DPat&>(h->L64[k].A));
         s->col_bytes[k] = M.col_bytes();
         s->tiles[k] = M.blk ? M.nb : 0;
+        if (k + 1 < L.size()) {
+          const DPat& P = h->mixed ? static_cast<const DPat&>(h->L32[k].P) : static_cast<const DPat&>(h->L64[k].P);
+          const DPat& R = h->mixed ? static_cast<const DPat&>(h->L32[k].R) : static_cast<const DPat&>(h->L64[k].R);
+          s->col_bytes_p[k] = P.col_bytes();
+          s->col_bytes_r[k] = R.col_bytes();
+        }
       }
     }
     s->coarse_mode = h->H.coarse_mode;
