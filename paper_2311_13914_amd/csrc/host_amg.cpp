@@ -10,7 +10,10 @@
 // singular).  Tie and threshold rules are spelled out where they are applied; they make the
 // hierarchy independent of the rounding of the matrix entries.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <queue>
 #include <string>
@@ -665,7 +668,12 @@ int coarse_operator(const HostLevel& L, bool nullspace, std::vector<double>& G, 
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
+// With BIDOMAIN_SETUP_LOG set in the environment, one line per level goes to stderr as the
+// setup proceeds (large hierarchies take minutes on the host).
 int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::string& err) {
+  const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
+  const auto t_start = std::chrono::steady_clock::now();
+  auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
   H.lv.clear();
   HostLevel cur;
   cur.A = A0;
@@ -720,7 +728,13 @@ int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::
       break;
     }
     Csr R = transpose(P);
-    Csr Ac = symmetrize(spgemm(R, spgemm(cur.A, P)));
+    Csr AP = spgemm(cur.A, P);
+    if (log) std::fprintf(stderr, "[setup] level %d: A P has %zu nonzeros (%.1f s)\n", k, AP.v.size(), elapsed());
+    Csr Ac = symmetrize(spgemm(R, AP));
+    AP = Csr();
+    if (log)
+      std::fprintf(stderr, "[setup] level %d: %d rows, %zu nonzeros -> %d rows, %zu nonzeros (%.1f s)\n", k, n,
+                   cur.A.v.size(), Ac.nrows, Ac.v.size(), elapsed());
     cur.P = std::move(P);
     cur.R = std::move(R);
     HostLevel next;
