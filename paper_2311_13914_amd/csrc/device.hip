@@ -117,16 +117,15 @@ std::vector<int> pack_tiles(const Csr& H, int max_rows, int64_t max_nnz) {
 // Row tiles of the CSR-stream kernel (nb + 1 row boundaries).  Matrices whose every row fits
 // the staging buffer use it (measured faster than the lane-group kernel on every level of the
 // slab hierarchies, short and long rows alike); longer rows fall back to the lane-group kernel
-// (empty result).  Tiles hold at most kStreamCap entries and kStreamRows / 2 rows, or
-// kStreamRows rows for short rows, so that a tile of a prolongator still streams a few thousand
-// entries.  (Shrinking tiles so that their count fills whole rounds of resident blocks measured
-// slower on every level.)
+// (empty result).  Tiles hold at most kStreamCap entries and kStreamRows rows (149 rows of a
+// 27-point operator, 256 of a prolongator), so that every tile streams a few thousand entries.
+// (Capping long-row tiles at 128 rows, for two lanes per row in phase 2, measured slower; so
+// did shrinking tiles until their count fills whole rounds of resident blocks.)
 std::vector<int> stream_blocks(const Csr& H) {
   if (H.nrows == 0) return {};
   for (int32_t i = 0; i < H.nrows; ++i)
     if (H.rp[i + 1] - H.rp[i] > kStreamCap) return {};
-  const int max_rows = (double)H.nnz() / H.nrows <= 12.0 ? kStreamRows : kStreamRows / 2;
-  return pack_tiles(H, max_rows, kStreamCap);
+  return pack_tiles(H, kStreamRows, kStreamCap);
 }
 
 void configure(DPat& M, int max_blocks) {

@@ -585,7 +585,18 @@ __device__ __forceinline__ void tile_reduce(const SpArgs<T>& a, const Tile& t, c
   const bool own = grp < t.r1 - t.r0;
   T s = T(0);
   const int hi = own ? t.hi - t.k0 : 0;
-  for (int k = t.lo - t.k0 + lane; k < hi; k += t.g) s += prod[k];
+  {  // four independent partial sums: a row of 27 entries on one lane is 7 LDS round trips, not 27
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    int k = t.lo - t.k0 + lane;
+    for (; k + 3 * t.g < hi; k += 4 * t.g) {
+      s0 += prod[k];
+      s1 += prod[k + t.g];
+      s2 += prod[k + 2 * t.g];
+      s3 += prod[k + 3 * t.g];
+    }
+    for (; k < hi; k += t.g) s0 += prod[k];
+    s = (s0 + s1) + (s2 + s3);
+  }
   for (int off = t.g / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, t.g);
   if (own && lane == 0) row_apply<T, OP>(a, row, s, in, acc, vc);
   block_tail<T, OP>(a, acc, vc, bi, nb, lds, lds32);
