@@ -72,6 +72,13 @@ typedef struct {
   int32_t nullspace;           /* BD_NULL_NONE | BD_NULL_CONSTANT                        */
   double stagnation_ratio;     /* stop coarsening when n_c > ratio * n_k (0.9)           */
   int32_t coarse_dense_max;    /* largest coarsest level solved directly (2048)          */
+  /* Galerkin products R (A P) of the setup as dense GEMMs on the device (rocBLAS, float64,
+   * structural pattern from 0/1 GEMMs, so the result equals the sparse product up to
+   * rounding order): 0 never, 1 for levels where the dense work is within a few thousand
+   * times the sparse work and fits in half the free device memory (default), 2 for every
+   * level of at most 65,536 rows and columns that fits.  bidomain_amg_build_host never uses
+   * the device. */
+  int32_t galerkin_device;
 } bd_amg_opts;
 
 void bidomain_default_opts(bd_amg_opts* opts);

@@ -37,7 +37,7 @@ class bd_amg_opts(C.Structure):
                 ("smoother", C.c_int32), ("smoother_degree", C.c_int32), ("cheb_lo", C.c_double),
                 ("cheb_hi", C.c_double), ("esteig_iters", C.c_int32), ("seed", C.c_uint64),
                 ("vcycle_precision", C.c_int32), ("nullspace", C.c_int32), ("stagnation_ratio", C.c_double),
-                ("coarse_dense_max", C.c_int32)]
+                ("coarse_dense_max", C.c_int32), ("galerkin_device", C.c_int32)]
 
 
 class bd_csr(C.Structure):

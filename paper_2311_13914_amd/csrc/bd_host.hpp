@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <limits>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -42,8 +43,14 @@ struct HostHierarchy {
   std::vector<double> G;        // n_M x n_M row-major: A_M^{-1}, or the pseudo-inverse on b-perp
 };
 
+// Galerkin product on another engine: given A_k, P_k and the number of partial products of
+// the sparse A_k P_k, either fills A_c = symmetrized R_k (A_k P_k) (R_k = P_k^T) and returns
+// true, or returns false and the host computes it.
+using GalerkinOffload = std::function<bool(const Csr& A, const Csr& P, int64_t sparse_flops, Csr& Ac)>;
+
 // Setup phase: returns BD_OK or a BD_E_* code with a message in err.
-int build_hierarchy(const Csr& A, const bd_amg_opts& o, HostHierarchy& H, std::string& err);
+int build_hierarchy(const Csr& A, const bd_amg_opts& o, HostHierarchy& H, std::string& err,
+                    const GalerkinOffload* offload = nullptr);
 
 // Largest Ritz value of D^{-1} A after `iters` Jacobi-CG steps from a SplitMix64 vector.
 double lambda_estimate(const Csr& A, const std::vector<double>& Dinv, int iters, uint64_t seed);

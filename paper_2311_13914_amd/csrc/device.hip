@@ -2,9 +2,12 @@
 // of fused kernels, PCG / flexible CG with all scalars kept on the device, the Bidomain
 // time step (eqs. (4)-(7)) and the C ABI declared in bidomain.h.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -842,8 +845,163 @@ void device_upload(bd_amg* h, const double* weights, bool need_ci, hipStream_t s
   h->host_only = false;
 }
 
+// ------------------------------------------------------------------------------------------
+// Dense Galerkin products on the device (setup phase).  The filled coarse levels of smoothed
+// aggregation make R (A P) a dense-matrix product in all but name; as float64 GEMMs (rocBLAS)
+// they take milliseconds instead of the host's minutes.  The structural pattern of the result
+// (which the sparse product keeps, explicit zeros included) comes from the same two products
+// on 0/1 matrices in float32: the counts are integers below 2^24, so they are exact.
+
+// Row-major dense copy of a CSR matrix (row i at i * ld) and its 0/1 pattern; one block per row.
+__global__ void k_densify(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                          int nrows, int64_t ld, double* __restrict__ dval, float* __restrict__ dpat) {
+  for (int i = blockIdx.x; i < nrows; i += gridDim.x)
+    for (int k = rp[i] + (int)threadIdx.x; k < rp[i + 1]; k += blockDim.x) {
+      const int64_t o = (int64_t)i * ld + ci[k];
+      dval[o] = v[k];
+      dpat[o] = 1.0f;
+    }
+}
+
+__global__ void k_binarize(float* __restrict__ a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = a[i] > 0.5f ? 1.0f : 0.0f;
+}
+
+std::mutex g_galerkin_mu;  // one device Galerkin product at a time (its buffers are large)
+
+bool dense_galerkin(const Csr& A, const Csr& P, int64_t sparse_flops, int mode, bool log, Csr& Ac) {
+  const int64_t n = A.nrows, nc = P.ncols;
+  if (mode == 0 || n == 0 || nc == 0 || n > 65536 || nc > 65536) return false;
+  const double dense_flops = 2.0 * (double)n * (double)n * (double)nc + 2.0 * (double)n * (double)nc * (double)nc;
+  if (mode == 1 && (sparse_flops < 500000000LL || dense_flops > 4000.0 * (double)sparse_flops || dense_flops > 2e14))
+    return false;
+  std::lock_guard<std::mutex> lock(g_galerkin_mu);
+  const size_t dense_bytes = (size_t)(12 * n * n + 24 * n * nc + 12 * nc * nc);
+  const size_t csr_bytes = (size_t)(A.nnz() + P.nnz()) * 12 + (size_t)(n + 1) * 8;
+  size_t freeb = 0, total = 0;
+  if (hipMemGetInfo(&freeb, &total) != hipSuccess || dense_bytes + csr_bytes > freeb / 2) return false;
+
+  std::vector<void*> bufs;
+  hipStream_t st = nullptr;
+  rocblas_handle hb = nullptr;
+  bool ok = true;
+  auto alloc = [&](size_t bytes) -> void* {
+    void* p = nullptr;
+    if (!ok || hipMalloc(&p, bytes) != hipSuccess) {
+      ok = false;
+      return nullptr;
+    }
+    bufs.push_back(p);
+    return p;
+  };
+  auto hip_ok = [&](hipError_t e) { ok = ok && e == hipSuccess; };
+  auto blas_ok = [&](rocblas_status e) { ok = ok && e == rocblas_status_success; };
+  double *dA = (double*)alloc(8 * n * n), *dPt = (double*)alloc(8 * n * nc), *dAP = (double*)alloc(8 * n * nc),
+         *dRAP = (double*)alloc(8 * nc * nc);
+  float *sA = (float*)alloc(4 * n * n), *sPt = (float*)alloc(4 * n * nc), *sAP = (float*)alloc(4 * n * nc),
+        *sRAP = (float*)alloc(4 * nc * nc);
+  int *arp = (int*)alloc(4 * (n + 1)), *aci = (int*)alloc(4 * std::max<int64_t>(1, A.nnz())),
+      *prp = (int*)alloc(4 * (n + 1)), *pci = (int*)alloc(4 * std::max<int64_t>(1, P.nnz()));
+  double *av = (double*)alloc(8 * std::max<int64_t>(1, A.nnz())), *pv = (double*)alloc(8 * std::max<int64_t>(1, P.nnz()));
+  std::vector<double> rap;
+  std::vector<float> pat;
+  if (ok) hip_ok(hipStreamCreate(&st));
+  if (ok) blas_ok(rocblas_create_handle(&hb));
+  if (ok) blas_ok(rocblas_set_stream(hb, st));
+  if (ok) {
+    hip_ok(hipMemcpyAsync(arp, A.rp.data(), 4 * (n + 1), hipMemcpyHostToDevice, st));
+    hip_ok(hipMemcpyAsync(aci, A.ci.data(), 4 * A.nnz(), hipMemcpyHostToDevice, st));
+    hip_ok(hipMemcpyAsync(av, A.v.data(), 8 * A.nnz(), hipMemcpyHostToDevice, st));
+    hip_ok(hipMemcpyAsync(prp, P.rp.data(), 4 * (n + 1), hipMemcpyHostToDevice, st));
+    hip_ok(hipMemcpyAsync(pci, P.ci.data(), 4 * P.nnz(), hipMemcpyHostToDevice, st));
+    hip_ok(hipMemcpyAsync(pv, P.v.data(), 8 * P.nnz(), hipMemcpyHostToDevice, st));
+    hip_ok(hipMemsetAsync(dA, 0, 8 * n * n, st));
+    hip_ok(hipMemsetAsync(sA, 0, 4 * n * n, st));
+    hip_ok(hipMemsetAsync(dPt, 0, 8 * n * nc, st));
+    hip_ok(hipMemsetAsync(sPt, 0, 4 * n * nc, st));
+  }
+  if (ok) {
+    const int g = (int)std::min<int64_t>(n, 65535);
+    // row-major A read column-major is A^T; row-major P (ld nc) read column-major is P^T (nc x n)
+    k_densify<<<g, kBlock, 0, st>>>(arp, aci, av, (int)n, n, dA, sA);
+    k_densify<<<g, kBlock, 0, st>>>(prp, pci, pv, (int)n, nc, dPt, sPt);
+    hip_ok(hipGetLastError());
+  }
+  const double one = 1.0, zero = 0.0;
+  const float onef = 1.0f, zerof = 0.0f;
+  const rocblas_int N = (rocblas_int)n, NC = (rocblas_int)nc;
+  if (ok) {
+    // A P = (A^T)^T (P^T)^T: n x nc
+    blas_ok(rocblas_dgemm(hb, rocblas_operation_transpose, rocblas_operation_transpose, N, NC, N, &one, dA, N, dPt, NC,
+                          &zero, dAP, N));
+    blas_ok(rocblas_sgemm(hb, rocblas_operation_transpose, rocblas_operation_transpose, N, NC, N, &onef, sA, N, sPt, NC,
+                          &zerof, sAP, N));
+  }
+  if (ok) {
+    k_binarize<<<2048, kBlock, 0, st>>>(sAP, n * nc);
+    hip_ok(hipGetLastError());
+    // R (A P) = P^T (A P): nc x nc
+    blas_ok(rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, NC, NC, N, &one, dPt, NC, dAP, N, &zero,
+                          dRAP, NC));
+    blas_ok(rocblas_sgemm(hb, rocblas_operation_none, rocblas_operation_none, NC, NC, N, &onef, sPt, NC, sAP, N, &zerof,
+                          sRAP, NC));
+  }
+  if (ok) {
+    // C = (R A P + (R A P)^T) / 2 (a structurally absent mirror is an exact zero, as the host's
+    // symmetrisation assumes) into the A P buffer; the pattern transposed into sAP, so that row
+    // a of the pattern is contiguous.  0.5 a + 0.5 b rounds exactly as 0.5 (a + b).
+    const double half = 0.5;
+    blas_ok(rocblas_dgeam(hb, rocblas_operation_none, rocblas_operation_transpose, NC, NC, &half, dRAP, NC, &half, dRAP,
+                          NC, dAP, NC));
+    blas_ok(rocblas_sgeam(hb, rocblas_operation_transpose, rocblas_operation_none, NC, NC, &onef, sRAP, NC, &zerof, sRAP,
+                          NC, sAP, NC));
+  }
+  if (ok) {
+    rap.resize((size_t)nc * nc);
+    pat.resize((size_t)nc * nc);
+    hip_ok(hipMemcpyAsync(rap.data(), dAP, 8 * nc * nc, hipMemcpyDeviceToHost, st));
+    hip_ok(hipMemcpyAsync(pat.data(), sAP, 4 * nc * nc, hipMemcpyDeviceToHost, st));
+    hip_ok(hipStreamSynchronize(st));
+  }
+  if (hb) (void)rocblas_destroy_handle(hb);
+  if (st) (void)hipStreamDestroy(st);
+  for (void* p : bufs) (void)hipFree(p);
+  if (!ok) {
+    (void)hipGetLastError();
+    if (log) std::fprintf(stderr, "[setup] device Galerkin product unavailable, using the host\n");
+    return false;
+  }
+  // CSR on R A P's pattern: pattern(a, b) at pat[b + a nc], C(a, b) = C(b, a) at rap[b + a nc]
+  Ac = Csr();
+  Ac.nrows = Ac.ncols = (int32_t)nc;
+  Ac.rp.assign(nc + 1, 0);
+#pragma omp parallel for schedule(static, 64)
+  for (int64_t a = 0; a < nc; ++a) {
+    int32_t cnt = 0;
+    for (int64_t b = 0; b < nc; ++b) cnt += pat[b + a * nc] > 0.5f;
+    Ac.rp[a + 1] = cnt;
+  }
+  for (int64_t a = 0; a < nc; ++a) Ac.rp[a + 1] += Ac.rp[a];
+  Ac.ci.resize(Ac.rp[nc]);
+  Ac.v.resize(Ac.rp[nc]);
+#pragma omp parallel for schedule(static, 64)
+  for (int64_t a = 0; a < nc; ++a) {
+    int32_t pos = Ac.rp[a];
+    for (int64_t b = 0; b < nc; ++b)
+      if (pat[b + a * nc] > 0.5f) {
+        Ac.ci[pos] = (int32_t)b;
+        Ac.v[pos] = rap[b + a * nc];
+        ++pos;
+      }
+  }
+  return true;
+}
+
+// host_only: build the hierarchy but do not upload it; use_device: the setup may run its
+// Galerkin products on the device (option galerkin_device).
 int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, hipStream_t st, bd_amg** out,
-               bool host_only = false) {
+               bool host_only = false, bool use_device = true) {
   if (!A || !out) throw Failure{BD_E_INVALID, "null argument"};
   bd_amg_opts o;
   bidomain_default_opts(&o);
@@ -851,6 +1009,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   if (o.smoother_degree < 1 || o.coarse_eq_limit < 1 || o.max_levels < 1 || !(o.cheb_hi > o.cheb_lo) ||
       !(o.cheb_lo >= 0.0) || o.esteig_iters < 1 || !(o.threshold >= 0.0) || !(o.stagnation_ratio > 0.0) ||
       o.coarse_dense_max < 1 || (o.coarsening != BD_SA && o.coarsening != BD_RS) ||
+      o.galerkin_device < 0 || o.galerkin_device > 2 ||
       (o.smoother != BD_CHEBYSHEV && o.smoother != BD_JACOBI) ||
       (o.vcycle_precision != BD_F64 && o.vcycle_precision != BD_F32))
     throw Failure{BD_E_INVALID, "invalid AMG options"};
@@ -870,7 +1029,11 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   h->n = A->n;
   h->mixed = o.vcycle_precision == BD_F32;
   std::string err;
-  const int rc = build_hierarchy(H, o, h->H, err);
+  const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
+  const GalerkinOffload offload = [&](const Csr& Ak, const Csr& Pk, int64_t flops, Csr& Ac) {
+    return dense_galerkin(Ak, Pk, flops, o.galerkin_device, log, Ac);
+  };
+  const int rc = build_hierarchy(H, o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr);
   if (rc != BD_OK) throw Failure{rc, err};
   h->M = (int)h->H.lv.size() - 1;
   h->host_only = true;
@@ -976,6 +1139,7 @@ void bidomain_default_opts(bd_amg_opts* o) {
   o->nullspace = BD_NULL_NONE;
   o->stagnation_ratio = 0.9;
   o->coarse_dense_max = 2048;
+  o->galerkin_device = 1;
 }
 
 const char* bidomain_last_error(void) { return g_last_error.c_str(); }
@@ -986,7 +1150,7 @@ int bidomain_amg_setup(const bd_csr* A, const bd_amg_opts* opts, const double* n
 }
 
 int bidomain_amg_build_host(const bd_csr* A, const bd_amg_opts* opts, bd_amg** out) {
-  return guarded([&] { return setup_impl(A, opts, nullptr, nullptr, out, true); });
+  return guarded([&] { return setup_impl(A, opts, nullptr, nullptr, out, true, false); });
 }
 
 int bidomain_pcg_solve(bd_amg* h, const double* b_dev, double* x_dev, int x_is_guess, double rtol, int maxit,

@@ -670,7 +670,8 @@ int coarse_operator(const HostLevel& L, bool nullspace, std::vector<double>& G, 
 // ------------------------------------------------------------------------------------------
 // With BIDOMAIN_SETUP_LOG set in the environment, one line per level goes to stderr as the
 // setup proceeds (large hierarchies take minutes on the host).
-int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::string& err) {
+int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::string& err,
+                    const GalerkinOffload* offload) {
   const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
   const auto t_start = std::chrono::steady_clock::now();
   auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
@@ -728,10 +729,21 @@ int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::
       break;
     }
     Csr R = transpose(P);
-    Csr AP = spgemm(cur.A, P);
-    if (log) std::fprintf(stderr, "[setup] level %d: A P has %zu nonzeros (%.1f s)\n", k, AP.v.size(), elapsed());
-    Csr Ac = symmetrize(spgemm(R, AP));
-    AP = Csr();
+    Csr Ac;
+    bool done = false;
+    if (offload) {
+      int64_t flops = 0;
+#pragma omp parallel for reduction(+ : flops) schedule(static, 4096)
+      for (int32_t i = 0; i < n; ++i)
+        for (int32_t ka = cur.A.rp[i]; ka < cur.A.rp[i + 1]; ++ka) flops += P.rp[cur.A.ci[ka] + 1] - P.rp[cur.A.ci[ka]];
+      done = (*offload)(cur.A, P, flops, Ac);
+      if (done && log) std::fprintf(stderr, "[setup] level %d: Galerkin product on the device (%.1f s)\n", k, elapsed());
+    }
+    if (!done) {
+      Csr AP = spgemm(cur.A, P);
+      if (log) std::fprintf(stderr, "[setup] level %d: A P has %zu nonzeros (%.1f s)\n", k, AP.v.size(), elapsed());
+      Ac = symmetrize(spgemm(R, AP));
+    }
     if (log)
       std::fprintf(stderr, "[setup] level %d: %d rows, %zu nonzeros -> %d rows, %zu nonzeros (%.1f s)\n", k, n,
                    cur.A.v.size(), Ac.nrows, Ac.v.size(), elapsed());

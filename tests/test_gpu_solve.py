@@ -281,3 +281,27 @@ def test_product_index_forms(torch, far, col_bytes):
         assert _relerr(host(out), ref) <= 1e-13
     finally:
         lib.bidomain_amg_destroy(h)
+
+
+@pytest.mark.parametrize("dims", [(16, 16, 8), (37, 29, 13), (32, 32, 16)])
+def test_device_galerkin_equals_host(torch, dims):
+    """Galerkin products as dense device GEMMs (forced on every level) give the host's sparse
+    hierarchy: the same levels, patterns and nonzero counts, and values equal up to rounding order."""
+    c = bc.make_case(*dims, seed=9)
+    ops = fem.assemble_operators(c)
+    A = ops["Aell"]
+    hd = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, galerkin_device=2), ops["m"])
+    hh = lib.bidomain_amg_build_host(A, lib.bidomain_default_opts(nullspace=1))
+    try:
+        idd, ih = lib.bidomain_amg_info(hd), lib.bidomain_amg_info(hh)
+        print(f"[gpu] device Galerkin dims={dims} levels={idd['n']}", flush=True)
+        assert idd["n"] == ih["n"] and idd["nnz"] == ih["nnz"] and idd["p_nnz"] == ih["p_nnz"]
+        for k in range(idd["nlevels"]):
+            for which in ([0, 1] if k + 1 < idd["nlevels"] else [0]):
+                rd, cd, vd, _ = lib.bidomain_amg_export(hd, k, which)
+                rh, ch, vh, _ = lib.bidomain_amg_export(hh, k, which)
+                assert np.array_equal(rd, rh) and np.array_equal(cd, ch), (k, which)
+                assert np.max(np.abs(vd - vh)) <= 1e-12 * np.max(np.abs(vh)), (k, which)
+    finally:
+        lib.bidomain_amg_destroy(hd)
+        lib.bidomain_amg_destroy(hh)
