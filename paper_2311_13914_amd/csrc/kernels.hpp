@@ -6,8 +6,10 @@
 // contraction (the coarsest-level matrix-vector product has at most a few thousand rows).
 //
 // Conventions:
-//  * a block has 256 threads (4 waves); a CSR row is handled by a group of G lanes (G a power
-//    of two, chosen per matrix from its mean row length), rows_per_block = 256 / G * TPB;
+//  * a block has 256 threads (4 waves); products run as the CSR-stream kernel (a block owns a
+//    tile of consecutive rows whose entries it streams through LDS), or, for rows longer than
+//    the staging buffer, as the lane-group kernel (a row per group of G lanes, G a power of two
+//    chosen from the mean row length, rows_per_block = 256 / G * TPB);
 //  * the block -> row-tile map is XCD-aware: the hardware deals blocks round-robin over the
 //    8 XCDs, so consecutive block ids are remapped to one contiguous row range per XCD, which
 //    keeps each XCD's L2 working on neighbouring rows (and their shared x entries);
@@ -418,7 +420,7 @@ __device__ __forceinline__ void block_tail(const SpArgs<T>& a, double (&acc)[3],
 }
 
 // Row-group kernel: G lanes per row, TPB consecutive 256/G-row tiles per block.  Used for
-// matrices with long rows (coarse Galerkin operators, restrictions).
+// matrices with a row longer than the CSR-stream staging buffer (kStreamCap entries).
 template <typename T, int G, int OP>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
   if (solve_done(a.sv)) return;
