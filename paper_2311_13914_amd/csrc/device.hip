@@ -5,6 +5,7 @@
 #include <rocblas/rocblas.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -82,11 +83,15 @@ struct DPat {
   const int* ci = nullptr;        // 32-bit column indices, or null when only cs is kept
   const uint16_t* cs = nullptr;   // CSR-stream: column - cbase[tile] (16 bits), or null
   const int* cbase = nullptr;     // CSR-stream: per-tile column base, with cs
+  const uint8_t* cd = nullptr;    // CSR-stream: index into dict of column - row, or null
+  const int* dict = nullptr;      // the distinct column - row offsets, with cd
+  int ndict = 0;
   int G = 8;    // lanes per row (row-group kernel)
   int tpb = 1;  // row tiles per block (row-group kernel)
   int nb = 0;   // blocks of a product launch
   const int* blk = nullptr;  // CSR-stream row tiles (nb + 1 row boundaries), or null
-  int col_bytes() const { return cs ? 2 : 4; }
+  int col_bytes() const { return cd ? 1 : (cs ? 2 : 4); }
+  int form() const { return cd ? IXD8 : (cs ? IX16 : IX32); }
 };
 
 template <typename T>
@@ -124,11 +129,49 @@ std::vector<int> pack_tiles(const Csr& H, int max_rows, int64_t max_nnz) {
 // 27-point operator, 256 of a prolongator), so that every tile streams a few thousand entries.
 // (Capping long-row tiles at 128 rows, for two lanes per row in phase 2, measured slower; so
 // did shrinking tiles until their count fills whole rounds of resident blocks.)
-std::vector<int> stream_blocks(const Csr& H) {
+std::vector<int> stream_blocks(const Csr& H, int cap) {
   if (H.nrows == 0) return {};
   for (int32_t i = 0; i < H.nrows; ++i)
-    if (H.rp[i + 1] - H.rp[i] > kStreamCap) return {};
-  return pack_tiles(H, kStreamRows, kStreamCap);
+    if (H.rp[i + 1] - H.rp[i] > cap) return {};
+  return pack_tiles(H, kStreamRows, cap);
+}
+
+// Offset dictionary: if the matrix's column - row offsets take at most kDictMax distinct values
+// (27 for the slab's 27-point operators), each entry stores its offset's index in one byte.
+bool dict_columns(const Csr& H, std::vector<uint8_t>& cd, std::vector<int>& dict) {
+  std::vector<int64_t> offs;
+  std::atomic<bool> fits{true};
+#pragma omp parallel
+  {
+    std::vector<int64_t> mine;
+#pragma omp for schedule(static, 4096)
+    for (int32_t i = 0; i < H.nrows; ++i) {
+      if (!fits.load(std::memory_order_relaxed)) continue;
+      for (int32_t k = H.rp[i]; k < H.rp[i + 1]; ++k) {
+        const int64_t o = (int64_t)H.ci[k] - i;
+        if (std::find(mine.begin(), mine.end(), o) == mine.end()) {
+          mine.push_back(o);
+          if ((int)mine.size() > kDictMax) {
+            fits.store(false, std::memory_order_relaxed);
+            break;
+          }
+        }
+      }
+    }
+#pragma omp critical
+    offs.insert(offs.end(), mine.begin(), mine.end());
+  }
+  if (!fits) return false;
+  std::sort(offs.begin(), offs.end());
+  offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+  if ((int)offs.size() > kDictMax) return false;
+  dict.assign(offs.begin(), offs.end());
+  cd.assign(H.ci.size(), 0);
+#pragma omp parallel for schedule(static, 4096)
+  for (int32_t i = 0; i < H.nrows; ++i)
+    for (int32_t k = H.rp[i]; k < H.rp[i + 1]; ++k)
+      cd[k] = (uint8_t)(std::lower_bound(offs.begin(), offs.end(), (int64_t)H.ci[k] - i) - offs.begin());
+  return true;
 }
 
 void configure(DPat& M, int max_blocks) {
@@ -188,16 +231,29 @@ DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, bool need_ci, hipStre
     HIPCHK(hipStreamSynchronize(st));
     M.rp = rp;
     configure(M, max_blocks);
-    const std::vector<int> blk = stream_blocks(H);
+    // index form: offset dictionary, else 16-bit per-tile offsets, else 32-bit indices
+    std::vector<uint8_t> cd;
+    std::vector<int> dict;
+    std::vector<int> blk = stream_blocks(H, kStreamCapD);
+    const bool dictf = !blk.empty() && dict_columns(H, cd, dict);
+    if (!dictf) blk = stream_blocks(H, kStreamCap);
     std::vector<uint16_t> cs;
     std::vector<int> cbase;
-    const bool compact = !blk.empty() && compact_columns(H, blk, cs, cbase);
+    const bool compact = !dictf && !blk.empty() && compact_columns(H, blk, cs, cbase);
     if (!blk.empty()) {
       int* d = ar.alloc<int>(blk.size());
       HIPCHK(hipMemcpyAsync(d, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice, st));
       HIPCHK(hipStreamSynchronize(st));
       M.blk = d;
       M.nb = (int)blk.size() - 1;
+    }
+    if (dictf) {
+      M.cd = upload_padded<uint8_t>(ar, cd.data(), cd.size(), st);
+      int* d = ar.alloc<int>(dict.size());
+      HIPCHK(hipMemcpyAsync(d, dict.data(), dict.size() * sizeof(int), hipMemcpyHostToDevice, st));
+      HIPCHK(hipStreamSynchronize(st));
+      M.dict = d;
+      M.ndict = (int)dict.size();
     }
     if (compact) {
       M.cs = upload_padded<uint16_t>(ar, cs.data(), cs.size(), st);
@@ -206,7 +262,7 @@ DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, bool need_ci, hipStre
       HIPCHK(hipStreamSynchronize(st));
       M.cbase = d;
     }
-    if (!compact || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
+    if ((!compact && !dictf) || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
   }
   M.v = upload_padded<T>(ar, std::vector<T>(H.v.begin(), H.v.end()).data(), H.v.size(), st);
   return M;
@@ -292,6 +348,9 @@ void bind(SpArgs<T>& a, const DCsr<T>& M) {
   a.ci = M.ci;
   a.cs = M.cs;
   a.cbase = M.cbase;
+  a.cd = M.cd;
+  a.dict = M.dict;
+  a.ndict = M.ndict;
   a.ncols = M.ncols;
   a.av = M.v;
   a.nrows = M.n;
@@ -303,8 +362,11 @@ void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
   bind(a, M);
   if (M.n == 0) return;
   if (M.blk) {
-    if (M.cs) k_spmv_stream<T, OP, true><<<M.nb, kBlock, 0, st>>>(a, M.blk);
-    else k_spmv_stream<T, OP, false><<<M.nb, kBlock, 0, st>>>(a, M.blk);
+    switch (M.form()) {
+      case IXD8: k_spmv_stream<T, OP, IXD8><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
+      case IX16: k_spmv_stream<T, OP, IX16><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
+      default: k_spmv_stream<T, OP, IX32><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
+    }
     HIPCHK(hipGetLastError());
     return;
   }
@@ -1496,9 +1558,9 @@ void launch_tasks(std::vector<Task>& v, hipStream_t st, Staging& stg, Launch lau
 // One sub-step of a round across all solves: the ops it collects are independent.
 template <typename T>
 struct Batch {
-  // products by index form (0: 32-bit columns, 1: 16-bit offsets) and op
-  std::vector<SpTask<T>> sp[2][OP_TRUE_RESID + 1];
-  std::vector<SpTask<double>> cgq[2];  // outer products (always float64)
+  // products by index form (IdxForm) and op
+  std::vector<SpTask<T>> sp[3][OP_TRUE_RESID + 1];
+  std::vector<SpTask<double>> cgq[3];  // outer products (always float64)
   std::vector<UpdTask<T>> upd;
   std::vector<DirTask<T>> dir;
   std::vector<GemvTask<T>> gemv;
@@ -1518,18 +1580,21 @@ struct Batch {
     t.blk = M.blk;
     t.nb = M.nb;
     t.off = 0;
-    sp[M.cs ? 1 : 0][OP].push_back(t);
+    sp[M.form()][OP].push_back(t);
   }
 
   void flush(hipStream_t st, Staging& stg) {
     for (auto& f : single) f();
     single.clear();
 #define BD_SPL(OPV)                                                                                      \
-  launch_tasks(sp[0][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                             \
-    k_spmv_stream_multi<T, OPV, false><<<nb, kBlock, 0, st>>>(d, n);                                     \
+  launch_tasks(sp[IX32][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                          \
+    k_spmv_stream_multi<T, OPV, IX32><<<nb, kBlock, 0, st>>>(d, n);                                      \
   });                                                                                                    \
-  launch_tasks(sp[1][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                             \
-    k_spmv_stream_multi<T, OPV, true><<<nb, kBlock, 0, st>>>(d, n);                                      \
+  launch_tasks(sp[IX16][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                          \
+    k_spmv_stream_multi<T, OPV, IX16><<<nb, kBlock, 0, st>>>(d, n);                                      \
+  });                                                                                                    \
+  launch_tasks(sp[IXD8][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                          \
+    k_spmv_stream_multi<T, OPV, IXD8><<<nb, kBlock, 0, st>>>(d, n);                                      \
   });
     BD_SPL(OP_Y)
     BD_SPL(OP_ADDY)
@@ -1539,11 +1604,14 @@ struct Batch {
     BD_SPL(OP_CHEB_POST0)
     BD_SPL(OP_CHEB_STEP)
 #undef BD_SPL
-    launch_tasks(cgq[0], st, stg, [&](const SpTask<double>* d, int n, int nb) {
-      k_spmv_stream_multi<double, OP_CG_Q, false><<<nb, kBlock, 0, st>>>(d, n);
+    launch_tasks(cgq[IX32], st, stg, [&](const SpTask<double>* d, int n, int nb) {
+      k_spmv_stream_multi<double, OP_CG_Q, IX32><<<nb, kBlock, 0, st>>>(d, n);
     });
-    launch_tasks(cgq[1], st, stg, [&](const SpTask<double>* d, int n, int nb) {
-      k_spmv_stream_multi<double, OP_CG_Q, true><<<nb, kBlock, 0, st>>>(d, n);
+    launch_tasks(cgq[IX16], st, stg, [&](const SpTask<double>* d, int n, int nb) {
+      k_spmv_stream_multi<double, OP_CG_Q, IX16><<<nb, kBlock, 0, st>>>(d, n);
+    });
+    launch_tasks(cgq[IXD8], st, stg, [&](const SpTask<double>* d, int n, int nb) {
+      k_spmv_stream_multi<double, OP_CG_Q, IXD8><<<nb, kBlock, 0, st>>>(d, n);
     });
     launch_tasks(upd, st, stg, [&](const UpdTask<T>* d, int n, int nb) { k_cg_update_multi<T><<<nb, kBlock, 0, st>>>(d, n); });
     launch_tasks(dir, st, stg, [&](const DirTask<T>* d, int n, int nb) { k_cg_direction_multi<T><<<nb, kBlock, 0, st>>>(d, n); });
@@ -1726,7 +1794,7 @@ void batched_round(std::vector<BInst*>& I, hipStream_t st, Staging& stg) {
       bind(a, M);
       SpTask<double> t;
       t.a = a; t.blk = M.blk; t.nb = M.nb; t.off = 0;
-      B.cgq[M.cs ? 1 : 0].push_back(t);
+      B.cgq[M.form()].push_back(t);
     } else {
       const DCsr<double> Mc = M;
       B.single.push_back([=] { launch_spmv<double, OP_CG_Q>(Mc, a, st); });

@@ -257,6 +257,9 @@ struct SpArgs {
   const int* ci;          // 32-bit column indices (null when cs is used)
   const uint16_t* cs;     // CSR-stream only: column - cbase[tile], or null
   const int* cbase;       // CSR-stream only: per-tile column base, with cs
+  const uint8_t* cd;      // CSR-stream only: index into dict of column - row, or null
+  const int* dict;        // the distinct column - row offsets (at most 256), with cd
+  int ndict;
   int ncols;
   const T* av;
   int nrows;
@@ -488,7 +491,25 @@ struct TileRegs {
 constexpr int kStageLen = 4 * ((kStreamCap + 2) / 4 + 1);
 static_assert(kStageLen <= kStreamChunks * 4 * kBlock, "every spanned chunk has a thread");
 
-template <bool CS>
+// Column index forms of a CSR-stream matrix: 32-bit indices; 16-bit offsets from a per-tile
+// base; or, for matrices whose column - row offsets take at most 256 distinct values (the
+// stencil operators of a structured mesh), an 8-bit index into that offset dictionary.
+enum IdxForm : int { IX32 = 0, IX16 = 1, IXD8 = 2 };
+// Dictionary tiles stage values, index bytes and the dictionary in LDS: a smaller cap keeps
+// the float64 total within the other forms' staging buffer.
+constexpr int kStreamCapD = 3450;
+constexpr int kStageLenD = 4 * ((kStreamCapD + 2) / 4 + 1);
+constexpr int kDictMax = 256;
+static_assert(kStageLenD <= kStreamChunks * 4 * kBlock, "every spanned chunk has a thread");
+static_assert(kDictMax <= kBlock, "one thread per dictionary entry");
+template <typename T>
+constexpr int smem_bytes() {
+  const int a = kStageLen * (int)sizeof(T);
+  const int b = kStageLenD * ((int)sizeof(T) + 1) + kDictMax * 4;
+  return a > b ? a : b;
+}
+
+template <int IX>
 __device__ __forceinline__ Tile tile_open(const int* __restrict__ rp, const int* __restrict__ blk,
                                           const int* __restrict__ cbase, int b) {
   Tile t;
@@ -496,7 +517,7 @@ __device__ __forceinline__ Tile tile_open(const int* __restrict__ rp, const int*
   t.r1 = blk[b + 1];
   t.beg = rp[t.r0];
   t.end = rp[t.r1];
-  t.cb = CS ? cbase[b] : 0;
+  t.cb = IX == IX16 ? cbase[b] : 0;
   t.k0 = t.beg & ~3;
   const int nrow = t.r1 - t.r0;
   int g = kBlock / (nrow > 0 ? nrow : 1);
@@ -512,16 +533,16 @@ __device__ __forceinline__ Tile tile_open(const int* __restrict__ rp, const int*
 // Branch-free so that every chunk load is in flight at once: chunk positions past the tile are
 // clamped to its last chunk.  Entries outside [beg, end) are neighbouring rows' or the zero
 // padding of the arrays (kStreamPad entries past nnz), so every 32-bit column index is valid;
-// CS (16-bit offsets): offsets of a neighbouring tile decode against this tile's base and are
+// IX16 (16-bit offsets): offsets of a neighbouring tile decode against this tile's base and are
 // clamped into [0, ncols) at the gather.  The index form is a template parameter: a run-time
 // branch around the loads made the compiler wait for them at the join.
-template <typename T, bool CS>
+template <typename T, int IX>
 __device__ __forceinline__ void tile_load(const SpArgs<T>& a, const Tile& t, TileRegs<T>& R) {
   const int klast = max(t.k0, (t.end - 1) & ~3);
 #pragma unroll
   for (int c = 0; c < kStreamChunks; ++c) {
     const int k = min(t.k0 + 4 * ((int)threadIdx.x + kBlock * c), klast);
-    if constexpr (CS) {
+    if constexpr (IX == IX16) {
       const uint2 cc = *reinterpret_cast<const uint2*>(a.cs + k);
       R.c[c][0] = (int)cc.x; R.c[c][1] = (int)cc.y;
     } else {
@@ -533,10 +554,10 @@ __device__ __forceinline__ void tile_load(const SpArgs<T>& a, const Tile& t, Til
 }
 
 // Phase 1, gathers of x at the loaded columns (issued together).
-template <typename T, bool CS>
+template <typename T, int IX>
 __device__ __forceinline__ void tile_gather(const SpArgs<T>& a, const Tile& t, const TileRegs<T>& R,
                                             T (&xv)[kStreamChunks][4]) {
-  if constexpr (CS) {
+  if constexpr (IX == IX16) {
     const int cmax = a.ncols - 1;
 #pragma unroll
     for (int c = 0; c < kStreamChunks; ++c) {
@@ -575,63 +596,140 @@ __device__ __forceinline__ RowIn<T> tile_fetch(const SpArgs<T>& a, const Tile& t
   return row_fetch<T, OP>(a, min(t.r0 + (int)threadIdx.x / t.g, t.r1 - 1));
 }
 
-// Phase 2: row sums from LDS, the fused epilogue, and the tile's reduction partials (slot bi
-// of nb).  Called by every thread after a barrier that follows tile_stage.
+// Phase 2 tail: the lane group's row sum s (every lane holds it after the shuffles), the fused
+// epilogue, and the tile's reduction partials (slot bi of nb).  Called by every thread.
+template <typename T, int OP>
+__device__ __forceinline__ void tile_finish(const SpArgs<T>& a, const Tile& t, const RowIn<T>& in, T s, int bi,
+                                            int nb, double* lds, float* lds32) {
+  const int grp = threadIdx.x / t.g, lane = threadIdx.x % t.g;
+  double acc[3] = {0.0, 0.0, 0.0};
+  VcAcc<T> vc;
+  for (int off = t.g / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, t.g);
+  if (grp < t.r1 - t.r0 && lane == 0) row_apply<T, OP>(a, t.r0 + grp, s, in, acc, vc);
+  block_tail<T, OP>(a, acc, vc, bi, nb, lds, lds32);
+}
+
+// Phase 2: row sums of the staged products, then tile_finish.  Called by every thread after a
+// barrier that follows tile_stage.
 template <typename T, int OP>
 __device__ __forceinline__ void tile_reduce(const SpArgs<T>& a, const Tile& t, const RowIn<T>& in, int bi, int nb,
                                             const T* prod, double* lds, float* lds32) {
   const int grp = threadIdx.x / t.g, lane = threadIdx.x % t.g;
-  double acc[3] = {0.0, 0.0, 0.0};
-  VcAcc<T> vc;
-  const int row = t.r0 + grp;
-  const bool own = grp < t.r1 - t.r0;
-  T s = T(0);
-  const int hi = own ? t.hi - t.k0 : 0;
-  {  // four independent partial sums: a row of 27 entries on one lane is 7 LDS round trips, not 27
-    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-    int k = t.lo - t.k0 + lane;
-    for (; k + 3 * t.g < hi; k += 4 * t.g) {
-      s0 += prod[k];
-      s1 += prod[k + t.g];
-      s2 += prod[k + 2 * t.g];
-      s3 += prod[k + 3 * t.g];
-    }
-    for (; k < hi; k += t.g) s0 += prod[k];
-    s = (s0 + s1) + (s2 + s3);
+  const int hi = grp < t.r1 - t.r0 ? t.hi - t.k0 : 0;
+  // four independent partial sums: a row of 27 entries on one lane is 7 LDS round trips, not 27
+  T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+  int k = t.lo - t.k0 + lane;
+  for (; k + 3 * t.g < hi; k += 4 * t.g) {
+    s0 += prod[k];
+    s1 += prod[k + t.g];
+    s2 += prod[k + 2 * t.g];
+    s3 += prod[k + 3 * t.g];
   }
-  for (int off = t.g / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, t.g);
-  if (own && lane == 0) row_apply<T, OP>(a, row, s, in, acc, vc);
-  block_tail<T, OP>(a, acc, vc, bi, nb, lds, lds32);
+  for (; k < hi; k += t.g) s0 += prod[k];
+  tile_finish<T, OP>(a, t, in, (s0 + s1) + (s2 + s3), bi, nb, lds, lds32);
 }
 
-// Body of the CSR-stream product for row tile b of nb (b also indexes the block partials);
-// CS: the matrix stores 16-bit column offsets (a.cs, a.cbase) instead of 32-bit indices.
+// Dictionary form.  Phase 1 streams the tile's values and index bytes into LDS (no gathers:
+// an entry's row is not known there); phase 2 runs a lane group per row, so lanes on
+// consecutive rows gather x at the same offset from their rows -- consecutive addresses.
+// Only the rows' own entries are read, so every gather is in bounds.
+template <typename T>
+__device__ __forceinline__ void dict_stage(const SpArgs<T>& a, const Tile& t, T* vals, uint8_t* idxs, int* dict) {
+  const int klast = max(t.k0, (t.end - 1) & ~3);
+  // the dictionary entry is read first and stored last, so no wait for it holds the chunk
+  // loads back
+  const int dv = a.dict[min((int)threadIdx.x, a.ndict - 1)];
+  T v[kStreamChunks][4];
+  uint32_t ix[kStreamChunks];
+#pragma unroll
+  for (int c = 0; c < kStreamChunks; ++c) {
+    const int k = min(t.k0 + 4 * ((int)threadIdx.x + kBlock * c), klast);
+    ix[c] = *reinterpret_cast<const uint32_t*>(a.cd + k);
+    load4(a.av + k, v[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < kStreamChunks; ++c) {
+    const int k = min(t.k0 + 4 * ((int)threadIdx.x + kBlock * c), klast) - t.k0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) vals[k + j] = v[c][j];
+    *reinterpret_cast<uint32_t*>(idxs + k) = ix[c];
+  }
+  if ((int)threadIdx.x < a.ndict) dict[threadIdx.x] = dv;
+}
+
+// Entries per lane whose index, offset and x reads are issued together in phase 2.
+constexpr int kDictBatch = 16;
+
+template <typename T, int OP>
+__device__ __forceinline__ void dict_reduce(const SpArgs<T>& a, const Tile& t, const RowIn<T>& in, int bi, int nb,
+                                            const T* vals, const uint8_t* idxs, const int* dict, double* lds,
+                                            float* lds32) {
+  const int grp = threadIdx.x / t.g, lane = threadIdx.x % t.g;
+  const int row = t.r0 + grp;
+  const int hi = grp < t.r1 - t.r0 ? t.hi - t.k0 : 0;
+  const T* __restrict__ x = a.x;
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  for (int kb = t.lo - t.k0 + lane; kb < hi; kb += kDictBatch * t.g) {
+    // positions past the row's end are clamped to its last entry (a valid column) and weighted 0
+    T v[kDictBatch];
+    int off[kDictBatch];
+#pragma unroll
+    for (int u = 0; u < kDictBatch; ++u) {
+      const int k = kb + u * t.g;
+      const int kc = min(k, hi - 1);
+      v[u] = k < hi ? vals[kc] : T(0);
+      off[u] = idxs[kc];
+    }
+#pragma unroll
+    for (int u = 0; u < kDictBatch; ++u) off[u] = dict[off[u]];
+    T xv[kDictBatch];
+#pragma unroll
+    for (int u = 0; u < kDictBatch; ++u) xv[u] = x[row + off[u]];
+#pragma unroll
+    for (int u = 0; u < kDictBatch; ++u) acc[u & 3] += v[u] * xv[u];
+  }
+  tile_finish<T, OP>(a, t, in, (acc[0] + acc[1]) + (acc[2] + acc[3]), bi, nb, lds, lds32);
+}
+
+// Body of the CSR-stream product for row tile b of nb (b also indexes the block partials), in
+// index form IX; smem holds smem_bytes<T>() bytes of staging.
 // (Testing the solve's done flag only after the tile's vector reads are issued measured
 // slower: the branch keeps every loaded register live across it.)
-template <typename T, int OP, bool CS>
-__device__ __forceinline__ void stream_body(const SpArgs<T>& a, const int* __restrict__ blk, int b, int nb, T* prod,
-                                            double* lds, float* lds32) {
+template <typename T, int OP, int IX>
+__device__ __forceinline__ void stream_body(const SpArgs<T>& a, const int* __restrict__ blk, int b, int nb,
+                                            unsigned char* smem, double* lds, float* lds32) {
   // The done flag (written by an earlier kernel, so a plain load sees it) is read together
   // with the tile bounds and tested before any vector load: one scalar round trip fewer.
   const int done = a.sv.fl[F_DONE];
-  const Tile t = tile_open<CS>(a.rp, blk, a.cbase, b);
+  const Tile t = tile_open<IX>(a.rp, blk, a.cbase, b);
   if (done) return;
-  TileRegs<T> R;
-  T xv[kStreamChunks][4];
-  tile_load<T, CS>(a, t, R);
-  tile_gather<T, CS>(a, t, R, xv);
-  const RowIn<T> in = tile_fetch<T, OP>(a, t);
-  tile_stage(t, R, xv, prod);
-  __syncthreads();
-  tile_reduce<T, OP>(a, t, in, b, nb, prod, lds, lds32);
+  if constexpr (IX == IXD8) {
+    T* vals = reinterpret_cast<T*>(smem);
+    uint8_t* idxs = reinterpret_cast<uint8_t*>(vals + kStageLenD);
+    int* dict = reinterpret_cast<int*>(idxs + kStageLenD);
+    const RowIn<T> in = tile_fetch<T, OP>(a, t);  // first: phase 1 has no gathers to hide it behind
+    dict_stage(a, t, vals, idxs, dict);
+    __syncthreads();
+    dict_reduce<T, OP>(a, t, in, b, nb, vals, idxs, dict, lds, lds32);
+  } else {
+    T* prod = reinterpret_cast<T*>(smem);
+    TileRegs<T> R;
+    T xv[kStreamChunks][4];
+    tile_load<T, IX>(a, t, R);
+    tile_gather<T, IX>(a, t, R, xv);
+    const RowIn<T> in = tile_fetch<T, OP>(a, t);
+    tile_stage(t, R, xv, prod);
+    __syncthreads();
+    tile_reduce<T, OP>(a, t, in, b, nb, prod, lds, lds32);
+  }
 }
 
-template <typename T, int OP, bool CS>
+template <typename T, int OP, int IX>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* __restrict__ blk) {
   __shared__ double lds[16];
   __shared__ float lds32[24];
-  __shared__ T prod[kStageLen];
-  stream_body<T, OP, CS>(a, blk, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, prod, lds, lds32);
+  __shared__ __align__(16) unsigned char smem[smem_bytes<T>()];
+  stream_body<T, OP, IX>(a, blk, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, smem, lds, lds32);
 }
 
 
@@ -1002,14 +1100,14 @@ struct SpTask {
   int nb, off;
 };
 
-template <typename T, int OP, bool CS>
+template <typename T, int OP, int IX>
 __global__ __launch_bounds__(kBlock) void k_spmv_stream_multi(const SpTask<T>* __restrict__ tasks, int ntasks) {
   __shared__ double lds[16];
   __shared__ float lds32[24];
-  __shared__ T prod[kStageLen];
+  __shared__ __align__(16) unsigned char smem[smem_bytes<T>()];
   const SpTask<T>& tk = tasks[task_of(tasks, ntasks)];
   const SpArgs<T> a = tk.a;
-  stream_body<T, OP, CS>(a, tk.blk, xcd_tile((int)blockIdx.x - tk.off, tk.nb), tk.nb, prod, lds, lds32);
+  stream_body<T, OP, IX>(a, tk.blk, xcd_tile((int)blockIdx.x - tk.off, tk.nb), tk.nb, smem, lds, lds32);
 }
 
 template <typename T>

@@ -244,35 +244,39 @@ def test_time_steps_match_oracle(torch, mixed):
         lib.bidomain_sim_destroy(sim)
 
 
-def _far_matrix(n, far):
-    """Rows i >= f (f in far) of every other block of 256 rows also couple to column i - f; every
-    third row is diagonal only, so tile boundaries fall at arbitrary entry alignments."""
+def _far_matrix(n, far, jitter):
+    """Rows i of every other block of 256 rows also couple to column i - f - (i % jitter) for f in
+    far (jitter 1: a single offset per f); every third row is diagonal only, so tile boundaries
+    fall at arbitrary entry alignments."""
     import scipy.sparse as sp
     rng = np.random.default_rng(17)
     rows, cols = [np.arange(n)], [np.arange(n)]
     for f in far:
-        i = np.arange(f, n)
+        i = np.arange(f + jitter, n)
         i = i[(i % 3 != 0) & ((i // 256) % 2 == 0)]
         rows.append(i)
-        cols.append(i - f)
+        cols.append(i - f - (i % jitter))
     r, c = np.concatenate(rows), np.concatenate(cols)
     v = np.where(r == c, 4.0, rng.uniform(-1.0, 1.0, r.size))
     return sp.csr_matrix((v, (r, c)), shape=(n, n))
 
 
-@pytest.mark.parametrize("far,col_bytes", [((60000,), 2), ((60000, 120000), 4)])
-def test_product_index_forms(torch, far, col_bytes):
-    """The product with 16-bit per-tile column offsets (tiles spanning < 65,536 columns) and with
-    32-bit indices.  In the 16-bit case the 256-row tiles alternate between column bases ~60,000
-    apart, so near the end of the matrix the previous tile's entries that an aligned chunk picks
-    up decode past the last column unless they are clamped; the result must still be exact."""
+@pytest.mark.parametrize("far,jitter,col_bytes", [((60000,), 1, 1), ((60000,), 600, 2), ((60000, 120000), 600, 4)])
+def test_product_index_forms(torch, far, jitter, col_bytes):
+    """The product in each column-index form: an offset dictionary (two distinct column - row
+    offsets), 16-bit per-tile offsets (~400 distinct offsets, tiles spanning < 65,536 columns)
+    and 32-bit indices.  In the 16-bit case the 256-row tiles alternate between column bases
+    ~60,000 apart, so near the end of the matrix the previous tile's entries that an aligned
+    chunk picks up decode past the last column unless they are clamped; every result must
+    still be exact."""
     n = 131072
-    A = _far_matrix(n, far)
+    A = _far_matrix(n, far, jitter)
     A.sort_indices()
     h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(max_levels=1, nullspace=0))
     try:
         info = lib.bidomain_amg_info(h)
-        print(f"[gpu] product index forms far={far} col_bytes={info['col_bytes'][0]} tiles={info['tiles'][0]}", flush=True)
+        print(f"[gpu] product index forms far={far} jitter={jitter} col_bytes={info['col_bytes'][0]} "
+              f"tiles={info['tiles'][0]}", flush=True)
         assert info["col_bytes"][0] == col_bytes and info["tiles"][0] > 0
         x = np.random.default_rng(5).standard_normal(n)
         out = torch.empty(n, dtype=torch.float64, device="cuda")
