@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <limits>
+#include <memory>
 #include <functional>
 #include <string>
 #include <vector>
@@ -29,9 +30,14 @@ std::vector<double> diagonal(const Csr& A);
 // Checks the boundary's CSR contract; returns an empty string when valid.
 std::string validate(const Csr& A);
 
+}  // namespace bd
+struct StreamPlan;  // device launch plan of a matrix (filled by the device library)
+namespace bd {
+
 struct HostLevel {
   Csr A;                        // level operator
   Csr P, R;                     // prolongator to this level from the next, and its transpose
+  std::shared_ptr<StreamPlan> plan_a, plan_p, plan_r;  // launch plans, once planned
   std::vector<double> B;        // near-null vector on this level
   std::vector<double> Dinv;     // 1 / diag(A)
   double lam = std::numeric_limits<double>::quiet_NaN();  // lambda_max(D^{-1} A) estimate

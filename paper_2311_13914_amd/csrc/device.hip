@@ -214,55 +214,90 @@ U* upload_padded(Arena& ar, const U* src, size_t count, hipStream_t st) {
   return d;
 }
 
+}  // namespace bd
+
+// Host half of a CSR-stream launch plan: row tiles and the column index encoding.  Built on
+// whichever thread runs the setup (a serving worker, not the serving thread), so that the
+// upload itself is copies only.
+struct StreamPlan {
+  std::vector<int> blk;         // row tiles, or empty (lane-group kernel)
+  std::vector<uint8_t> cd;      // offset-dictionary indices, or empty
+  std::vector<int> dict;
+  std::vector<uint16_t> cs;     // 16-bit per-tile offsets, or empty
+  std::vector<int> cbase;
+};
+
+namespace bd {
+
+StreamPlan plan_stream(const Csr& H) {
+  StreamPlan P;
+  // index form: offset dictionary, else 16-bit per-tile offsets, else 32-bit indices
+  P.blk = stream_blocks(H, kStreamCapD);
+  const bool dictf = !P.blk.empty() && dict_columns(H, P.cd, P.dict);
+  if (!dictf) {
+    P.cd.clear();
+    P.dict.clear();
+    P.blk = stream_blocks(H, kStreamCap);
+    if (!P.blk.empty() && !compact_columns(H, P.blk, P.cs, P.cbase)) {
+      P.cs.clear();
+      P.cbase.clear();
+    }
+  }
+  return P;
+}
+
+// Launch plans of every matrix of a host hierarchy (levels' A, P, R).
+void plan_hierarchy(HostHierarchy& H) {
+  for (HostLevel& L : H.lv) {
+    L.plan_a = std::make_shared<StreamPlan>(plan_stream(L.A));
+    if (L.P.nrows) L.plan_p = std::make_shared<StreamPlan>(plan_stream(L.P));
+    if (L.R.nrows) L.plan_r = std::make_shared<StreamPlan>(plan_stream(L.R));
+  }
+}
+
+template <typename U>
+const U* upload_small(Arena& ar, const std::vector<U>& h, hipStream_t st) {
+  U* d = ar.alloc<U>(h.size());
+  HIPCHK(hipMemcpyAsync(d, h.data(), h.size() * sizeof(U), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return d;
+}
+
 // Device copy of H with values of type T.  share: a pattern uploaded before for the same H
-// (reused as is), or null.  need_ci: keep the 32-bit column indices even where the product
-// reads 16-bit offsets (for kernels outside the product that read them).
+// (reused as is), or null.  plan: H's launch plan (built here if null).  need_ci: keep the
+// 32-bit column indices even where the product reads a compressed form (for kernels outside
+// the product that read them).
 template <typename T>
-DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, bool need_ci, hipStream_t st, int max_blocks) {
+DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, const StreamPlan* plan, bool need_ci, hipStream_t st,
+               int max_blocks) {
   DCsr<T> M;
   if (share) {
     static_cast<DPat&>(M) = *share;
   } else {
+    StreamPlan local;
+    if (!plan) {
+      local = plan_stream(H);
+      plan = &local;
+    }
     M.n = H.nrows;
     M.ncols = H.ncols;
     M.nnz = H.nnz();
-    int* rp = ar.alloc<int>(H.rp.size());
-    HIPCHK(hipMemcpyAsync(rp, H.rp.data(), H.rp.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPCHK(hipStreamSynchronize(st));
-    M.rp = rp;
+    M.rp = upload_small<int>(ar, H.rp, st);
     configure(M, max_blocks);
-    // index form: offset dictionary, else 16-bit per-tile offsets, else 32-bit indices
-    std::vector<uint8_t> cd;
-    std::vector<int> dict;
-    std::vector<int> blk = stream_blocks(H, kStreamCapD);
-    const bool dictf = !blk.empty() && dict_columns(H, cd, dict);
-    if (!dictf) blk = stream_blocks(H, kStreamCap);
-    std::vector<uint16_t> cs;
-    std::vector<int> cbase;
-    const bool compact = !dictf && !blk.empty() && compact_columns(H, blk, cs, cbase);
-    if (!blk.empty()) {
-      int* d = ar.alloc<int>(blk.size());
-      HIPCHK(hipMemcpyAsync(d, blk.data(), blk.size() * sizeof(int), hipMemcpyHostToDevice, st));
-      HIPCHK(hipStreamSynchronize(st));
-      M.blk = d;
-      M.nb = (int)blk.size() - 1;
+    if (!plan->blk.empty()) {
+      M.blk = upload_small<int>(ar, plan->blk, st);
+      M.nb = (int)plan->blk.size() - 1;
     }
-    if (dictf) {
-      M.cd = upload_padded<uint8_t>(ar, cd.data(), cd.size(), st);
-      int* d = ar.alloc<int>(dict.size());
-      HIPCHK(hipMemcpyAsync(d, dict.data(), dict.size() * sizeof(int), hipMemcpyHostToDevice, st));
-      HIPCHK(hipStreamSynchronize(st));
-      M.dict = d;
-      M.ndict = (int)dict.size();
+    if (!plan->cd.empty()) {
+      M.cd = upload_padded<uint8_t>(ar, plan->cd.data(), plan->cd.size(), st);
+      M.dict = upload_small<int>(ar, plan->dict, st);
+      M.ndict = (int)plan->dict.size();
     }
-    if (compact) {
-      M.cs = upload_padded<uint16_t>(ar, cs.data(), cs.size(), st);
-      int* d = ar.alloc<int>(cbase.size());
-      HIPCHK(hipMemcpyAsync(d, cbase.data(), cbase.size() * sizeof(int), hipMemcpyHostToDevice, st));
-      HIPCHK(hipStreamSynchronize(st));
-      M.cbase = d;
+    if (!plan->cs.empty()) {
+      M.cs = upload_padded<uint16_t>(ar, plan->cs.data(), plan->cs.size(), st);
+      M.cbase = upload_small<int>(ar, plan->cbase, st);
     }
-    if ((!compact && !dictf) || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
+    if ((!M.cd && !M.cs) || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
   }
   M.v = upload_padded<T>(ar, std::vector<T>(H.v.begin(), H.v.end()).data(), H.v.size(), st);
   return M;
@@ -579,10 +614,10 @@ void build_levels(bd_amg* h, hipStream_t st) {
       if (k == 0) D.A = h->A0;  // level 0 of the float64 V-cycle is the outer operator itself
     }
     if (D.A.n == 0)
-      D.A = upload<T>(h->ar, HL[k].A, k == 0 ? &h->A0 : nullptr, false, st, kMaxBlocksSpmv);
+      D.A = upload<T>(h->ar, HL[k].A, k == 0 ? &h->A0 : nullptr, HL[k].plan_a.get(), false, st, kMaxBlocksSpmv);
     if (k < nl - 1) {
-      D.P = upload<T>(h->ar, HL[k].P, nullptr, false, st, kMaxBlocksSpmv);
-      D.R = upload<T>(h->ar, HL[k].R, nullptr, false, st, kMaxBlocksSpmv);
+      D.P = upload<T>(h->ar, HL[k].P, nullptr, HL[k].plan_p.get(), false, st, kMaxBlocksSpmv);
+      D.R = upload<T>(h->ar, HL[k].R, nullptr, HL[k].plan_r.get(), false, st, kMaxBlocksSpmv);
     }
     D.dinv = upload_vec<T>(h->ar, HL[k].Dinv, st);
     if (k > 0) D.f = h->ar.alloc<T>(D.n);
@@ -892,7 +927,7 @@ __global__ __launch_bounds__(kBlock) void k_neg_spmv(const int* __restrict__ rp,
 // need_ci: keep the fine operator's 32-bit column indices (a simulation's A_i shares its
 // pattern and the step kernels read them).
 void device_upload(bd_amg* h, const double* weights, bool need_ci, hipStream_t st) {
-  h->A0 = upload<double>(h->ar, h->H.lv[0].A, nullptr, need_ci, st, kMaxBlocksSpmv);
+  h->A0 = upload<double>(h->ar, h->H.lv[0].A, nullptr, h->H.lv[0].plan_a.get(), need_ci, st, kMaxBlocksSpmv);
   if (h->mixed) build_levels<float>(h, st);
   else build_levels<double>(h, st);
   if (h->H.coarse_mode == 0) {
@@ -1097,6 +1132,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   };
   const int rc = build_hierarchy(H, o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr);
   if (rc != BD_OK) throw Failure{rc, err};
+  if (use_device) plan_hierarchy(h->H);  // launch plans, on this (possibly worker) thread
   h->M = (int)h->H.lv.size() - 1;
   h->host_only = true;
   if (!host_only) device_upload(h.get(), weights, false, st);
@@ -1159,7 +1195,7 @@ std::unique_ptr<bd_sim> upload_sim(SimHost& H, const double* v0, bool v0_dev, co
   H.hell = H.hpar = nullptr;
   device_upload(S->hell, H.m.data(), true, st);
   device_upload(S->hpar, nullptr, false, st);
-  S->Ai = upload<double>(S->ar, H.Ai, &S->hell->A0, false, st, kMaxBlocksSpmv);
+  S->Ai = upload<double>(S->ar, H.Ai, &S->hell->A0, nullptr, false, st, kMaxBlocksSpmv);
   S->v = S->ar.alloc<double>(n);
   S->ue = S->ar.alloc<double>(n);
   S->w = S->ar.alloc<double>(n);
