@@ -114,8 +114,9 @@ typedef struct {
   double grid_complexity;
   int64_t device_bytes;           /* device memory owned by the handle                    */
   /* The level operator's product on the device (0 on a host-only handle): bytes per column
-   * index it reads (4, or 2 for 16-bit offsets from a per-tile column base) and its row
-   * tiles (0 when rows are too long for the staging buffer and a lane-group kernel runs). */
+   * index it reads (4; 2 for 16-bit offsets from a per-tile column base; 1 for an index into
+   * the matrix's dictionary of at most 256 distinct column - row offsets) and its row tiles
+   * (0 when rows are too long for the staging buffer and a lane-group kernel runs). */
   int32_t col_bytes[BD_MAX_LEVELS];
   int64_t tiles[BD_MAX_LEVELS];
   int32_t col_bytes_p[BD_MAX_LEVELS];  /* the same for P_k and R_k (0 on the coarsest level) */
