@@ -38,10 +38,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def spmv_bytes(n: int, nnz: int, s: int = 8, col_bytes: int = 4, tiles: int = 0) -> int:
-    """Algorithmic bytes of y = A x in CSR: values + column indices (4 bytes, or 2-byte offsets
-    from a per-tile base) + row offsets, x read once, y written once, the tile table (and the
-    per-tile column bases with 2-byte offsets); the p^T q partials are negligible."""
+def spmv_bytes(n: int, nnz: int, s: int = 8, col_bytes: int = 4, tiles: int = 0, diags: int = 0) -> int:
+    """Algorithmic bytes of y = A x in CSR: values + column indices (4 bytes, 2-byte offsets
+    from a per-tile base, or 1-byte offset-dictionary indices) + row offsets, x read once, y
+    written once, the tile table (and the per-tile column bases with 2-byte offsets); in the
+    symmetric diagonal form the `diags` stored diagonals of n values, x once and y once.  The
+    p^T q partials are negligible."""
+    if diags:
+        return diags * n * s + 2 * n * s
     b = nnz * (s + col_bytes) + n * (4 + 2 * s)
     if tiles:
         b += 4 * (tiles + 1) + (4 * tiles if col_bytes == 2 else 0)
@@ -55,9 +59,10 @@ def iteration_bytes(info: dict, s: int) -> int:
     streamed by their epilogues, plus about 10 fine float64 vector streams of the CG updates and
     the dense coarsest GEMV.  s: bytes per V-cycle value (8, or 4 for the float32 V-cycle)."""
     n, nnz, L = info["n"], info["nnz"], info["nlevels"]
-    b = spmv_bytes(n[0], nnz[0], 8, info["col_bytes"][0], info["tiles"][0])
+    d = info.get("diags", [0] * L)
+    b = spmv_bytes(n[0], nnz[0], 8, info["col_bytes"][0], info["tiles"][0], d[0])
     for k in range(L - 1):
-        b += 4 * spmv_bytes(n[k], nnz[k], s, info["col_bytes"][k], info["tiles"][k])
+        b += 4 * spmv_bytes(n[k], nnz[k], s, info["col_bytes"][k], info["tiles"][k], d[k])
         pn = info["p_nnz"][k]
         b += pn * (s + info["col_bytes_r"][k]) + n[k + 1] * (4 + s) + n[k] * s  # R_k: n_{k+1} rows
         b += pn * (s + info["col_bytes_p"][k]) + n[k] * (4 + 2 * s) + n[k + 1] * s  # P_k: y += P e
@@ -313,7 +318,8 @@ def main():
     ell_s = info["ms_ell"] * 1e-3
     value = n * info["it_ell"] / ell_s
     avg_ms = prof_ms / max(prof_launches, 1)
-    bytes_launch = spmv_bytes(n, nnz, 8, info_e["col_bytes"][0], info_e["tiles"][0])
+    diags = info_e["diags"][0]
+    bytes_launch = spmv_bytes(n, nnz, 8, info_e["col_bytes"][0], info_e["tiles"][0], diags)
     achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
     it_bytes = iteration_bytes(info_e, 4 if args.mixed else 8)
     it_ms = info["ms_ell"] / max(info["it_ell"], 1)
@@ -324,8 +330,10 @@ def main():
                           "model of iteration_bytes, over elliptic solve time / iterations")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic_from_profile(n, nnz),
-                    kernel="k_spmv_stream<double, 8> (OP_CG_Q: outer q = A p on the fine operator, with p^T q)",
+                    kernel=(("k_spmv_sdia<double, 8>" if diags else "k_spmv_stream<double, 8>")
+                            + " (OP_CG_Q: outer q = A p on the fine operator, with p^T q)"),
                     bytes_per_launch=bytes_launch, column_index_bytes=info_e["col_bytes"][0],
+                    stored_diagonals=diags,
                     avg_launch_ms=round(avg_ms, 5), launches=prof_launches)
 
     out = {

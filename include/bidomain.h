@@ -79,6 +79,10 @@ typedef struct {
    * level of at most 65,536 rows and columns that fits.  bidomain_amg_build_host never uses
    * the device. */
   int32_t galerkin_device;
+  /* 1: keep a level operator that equals its transpose and has at most 14 column - row
+   * offsets >= 0 (the 27-point fine operators) in the symmetric diagonal form (default);
+   * 0: CSR forms only. */
+  int32_t diag_form;
 } bd_amg_opts;
 
 void bidomain_default_opts(bd_amg_opts* opts);
@@ -115,12 +119,21 @@ typedef struct {
   int64_t device_bytes;           /* device memory owned by the handle                    */
   /* The level operator's product on the device (0 on a host-only handle): bytes per column
    * index it reads (4; 2 for 16-bit offsets from a per-tile column base; 1 for an index into
-   * the matrix's dictionary of at most 256 distinct column - row offsets) and its row tiles
-   * (0 when rows are too long for the staging buffer and a lane-group kernel runs). */
+   * the matrix's dictionary of at most 256 distinct column - row offsets; 0 in the symmetric
+   * diagonal form below) and its row tiles (0 when rows are too long for the staging buffer
+   * and a lane-group kernel runs, or in the diagonal form). */
   int32_t col_bytes[BD_MAX_LEVELS];
   int64_t tiles[BD_MAX_LEVELS];
   int32_t col_bytes_p[BD_MAX_LEVELS];  /* the same for P_k and R_k (0 on the coarsest level) */
   int32_t col_bytes_r[BD_MAX_LEVELS];
+  /* Stored diagonals (14) where the level operator is kept in the symmetric diagonal form,
+   * else 0.  That form is taken for a square matrix equal to its transpose (values compared
+   * exactly) whose column - row offsets >= 0 number at most 14 (a 27-point stencil): only the
+   * diagonals of offset >= 0 are stored, n values each, and row i reads a(i, i - d) as
+   * a(i - d, i).  It holds no column indices or CSR values (bd_amg_export still returns the
+   * host CSR).  A structurally missing entry reads as zero times x, so a non-finite x value
+   * next to a boundary row can turn that row's result into NaN. */
+  int32_t diags[BD_MAX_LEVELS];
 } bd_amg_stats;
 
 /*

@@ -37,7 +37,8 @@ class bd_amg_opts(C.Structure):
                 ("smoother", C.c_int32), ("smoother_degree", C.c_int32), ("cheb_lo", C.c_double),
                 ("cheb_hi", C.c_double), ("esteig_iters", C.c_int32), ("seed", C.c_uint64),
                 ("vcycle_precision", C.c_int32), ("nullspace", C.c_int32), ("stagnation_ratio", C.c_double),
-                ("coarse_dense_max", C.c_int32), ("galerkin_device", C.c_int32)]
+                ("coarse_dense_max", C.c_int32), ("galerkin_device", C.c_int32),
+                ("diag_form", C.c_int32)]
 
 
 class bd_csr(C.Structure):
@@ -56,7 +57,7 @@ class bd_amg_stats(C.Structure):
                 ("coarse_mode", C.c_int32), ("operator_complexity", C.c_double), ("grid_complexity", C.c_double),
                 ("device_bytes", C.c_int64), ("col_bytes", C.c_int32 * BD_MAX_LEVELS),
                 ("tiles", C.c_int64 * BD_MAX_LEVELS), ("col_bytes_p", C.c_int32 * BD_MAX_LEVELS),
-                ("col_bytes_r", C.c_int32 * BD_MAX_LEVELS)]
+                ("col_bytes_r", C.c_int32 * BD_MAX_LEVELS), ("diags", C.c_int32 * BD_MAX_LEVELS)]
 
 
 class bd_slab(C.Structure):
@@ -250,7 +251,8 @@ def bidomain_amg_info(h) -> dict:
     return dict(nlevels=L, n=list(s.n[:L]), nnz=list(s.nnz[:L]), p_nnz=list(s.p_nnz[:L]),
                 lam=list(s.lambda_[:L]), coarse_mode=s.coarse_mode, operator_complexity=s.operator_complexity,
                 grid_complexity=s.grid_complexity, device_bytes=s.device_bytes, col_bytes=list(s.col_bytes[:L]),
-                tiles=list(s.tiles[:L]), col_bytes_p=list(s.col_bytes_p[:L]), col_bytes_r=list(s.col_bytes_r[:L]))
+                tiles=list(s.tiles[:L]), col_bytes_p=list(s.col_bytes_p[:L]), col_bytes_r=list(s.col_bytes_r[:L]),
+                diags=list(s.diags[:L]))
 
 
 def bidomain_amg_destroy(h):

@@ -90,13 +90,17 @@ struct DPat {
   int tpb = 1;  // row tiles per block (row-group kernel)
   int nb = 0;   // blocks of a product launch
   const int* blk = nullptr;  // CSR-stream row tiles (nb + 1 row boundaries), or null
-  int col_bytes() const { return cd ? 1 : (cs ? 2 : 4); }
-  int form() const { return cd ? IXD8 : (cs ? IX16 : IX32); }
+  int nd = 0;                // symmetric diagonal form: stored diagonals (kDiagK), or 0
+  int64_t ds = 0;            // with nd: stride between the diagonals
+  int doff[kDiagK] = {};     // with nd: their column - row offsets (>= 0)
+  int col_bytes() const { return nd ? 0 : (cd ? 1 : (cs ? 2 : 4)); }
+  int form() const { return nd ? SDIA : (cd ? IXD8 : (cs ? IX16 : IX32)); }
 };
 
 template <typename T>
 struct DCsr : DPat {
-  T* v = nullptr;
+  T* v = nullptr;   // CSR values (null in the symmetric diagonal form)
+  T* dv = nullptr;  // with nd: the nd diagonals, ds apart
 };
 
 int lanes_for(double mean_row) {
@@ -216,10 +220,14 @@ U* upload_padded(Arena& ar, const U* src, size_t count, hipStream_t st) {
 
 }  // namespace bd
 
-// Host half of a CSR-stream launch plan: row tiles and the column index encoding.  Built on
-// whichever thread runs the setup (a serving worker, not the serving thread), so that the
-// upload itself is copies only.
+// Host half of a product's launch plan: the symmetric diagonal form, or the CSR-stream row
+// tiles and column index encoding.  Built on whichever thread runs the setup (a serving
+// worker, not the serving thread), so that the upload itself is copies only.
 struct StreamPlan {
+  int nd = 0;                   // symmetric diagonal form: stored diagonals, or 0
+  int64_t ds = 0;               // stride between the diagonals
+  int doff[bd::kDiagK] = {};    // their column - row offsets (>= 0; 0 pads unused ones)
+  std::vector<double> dval;     // nd * ds values, zero where an entry does not exist
   std::vector<int> blk;         // row tiles, or empty (lane-group kernel)
   std::vector<uint8_t> cd;      // offset-dictionary indices, or empty
   std::vector<int> dict;
@@ -229,8 +237,89 @@ struct StreamPlan {
 
 namespace bd {
 
-StreamPlan plan_stream(const Csr& H) {
+// Symmetric diagonal form: taken where the matrix is square and equal to its transpose (every
+// entry a(i, j) has an entry a(j, i) of the same value, no duplicates), its column - row
+// offsets d >= 0 number at most kDiagK, and the kDiagK diagonals (8 bytes a slot) move fewer
+// bytes than the offset-dictionary form's values and index bytes (9 bytes an entry).  Square
+// matrices with too many offsets (coarse levels) are rejected after a few rows.
+bool sym_diagonals(const Csr& H, StreamPlan& P) {
+  const int32_t n = H.nrows;
+  if (n == 0 || H.ncols != n) return false;
+  if ((int64_t)kDiagK * n * 8 >= H.nnz() * 9 + 4 * (int64_t)n) return false;
+  std::vector<int> offs{0};
+  std::atomic<bool> ok{true};
+#pragma omp parallel
+  {
+    std::vector<int> mine;
+#pragma omp for schedule(static, 4096)
+    for (int32_t i = 0; i < n; ++i) {
+      if (!ok.load(std::memory_order_relaxed)) continue;
+      for (int32_t k = H.rp[i]; k < H.rp[i + 1]; ++k) {
+        const int d = H.ci[k] - i;
+        if (d < 0 || std::find(mine.begin(), mine.end(), d) != mine.end()) continue;
+        mine.push_back(d);
+        if ((int)mine.size() > kDiagK) {
+          ok.store(false, std::memory_order_relaxed);
+          break;
+        }
+      }
+    }
+#pragma omp critical
+    offs.insert(offs.end(), mine.begin(), mine.end());
+  }
+  if (!ok) return false;
+  std::sort(offs.begin(), offs.end());
+  offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+  const int nu = (int)offs.size();
+  if (nu > kDiagK) return false;
+  for (int o = 0; o < kDiagK; ++o) P.doff[o] = o < nu ? offs[o] : 0;
+  auto slot = [&](int d) {
+    for (int o = 0; o < nu; ++o)
+      if (P.doff[o] == d) return o;
+    return -1;
+  };
+  P.ds = ((int64_t)n + 63) / 64 * 64;
+  P.dval.assign((size_t)kDiagK * P.ds, 0.0);
+  std::vector<uint16_t> up(n, 0), lo(n, 0);  // slots filled by row i's own and mirrored entries
+  int64_t nup = 0, nlo = 0;
+  // entries on and above the diagonal: row i's own slots (no duplicates)
+#pragma omp parallel for schedule(static, 4096) reduction(+ : nup)
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = H.rp[i]; k < H.rp[i + 1]; ++k) {
+      const int d = H.ci[k] - i;
+      if (d < 0) continue;
+      const int o = slot(d);
+      if (up[i] >> o & 1) ok.store(false, std::memory_order_relaxed);
+      up[i] |= (uint16_t)(1u << o);
+      P.dval[(size_t)o * P.ds + i] = H.v[k];
+      if (d > 0) ++nup;
+    }
+  // entries below: each the mirror of a distinct stored entry, with the same value
+#pragma omp parallel for schedule(static, 4096) reduction(+ : nlo)
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = H.rp[i]; k < H.rp[i + 1]; ++k) {
+      const int32_t c = H.ci[k];
+      const int o = c < i ? slot(i - c) : -1;
+      if (c >= i) continue;
+      if (o < 0 || !(up[c] >> o & 1) || (lo[i] >> o & 1) || !(P.dval[(size_t)o * P.ds + c] == H.v[k])) {
+        ok.store(false, std::memory_order_relaxed);
+        continue;
+      }
+      lo[i] |= (uint16_t)(1u << o);
+      ++nlo;
+    }
+  if (!ok || nlo != nup) {
+    P.dval.clear();
+    P.dval.shrink_to_fit();
+    return false;
+  }
+  P.nd = kDiagK;
+  return true;
+}
+
+StreamPlan plan_stream(const Csr& H, bool diag_form) {
   StreamPlan P;
+  if (diag_form && sym_diagonals(H, P)) return P;
   // index form: offset dictionary, else 16-bit per-tile offsets, else 32-bit indices
   P.blk = stream_blocks(H, kStreamCapD);
   const bool dictf = !P.blk.empty() && dict_columns(H, P.cd, P.dict);
@@ -247,11 +336,11 @@ StreamPlan plan_stream(const Csr& H) {
 }
 
 // Launch plans of every matrix of a host hierarchy (levels' A, P, R).
-void plan_hierarchy(HostHierarchy& H) {
+void plan_hierarchy(HostHierarchy& H, bool diag_form) {
   for (HostLevel& L : H.lv) {
-    L.plan_a = std::make_shared<StreamPlan>(plan_stream(L.A));
-    if (L.P.nrows) L.plan_p = std::make_shared<StreamPlan>(plan_stream(L.P));
-    if (L.R.nrows) L.plan_r = std::make_shared<StreamPlan>(plan_stream(L.R));
+    L.plan_a = std::make_shared<StreamPlan>(plan_stream(L.A, diag_form));
+    if (L.P.nrows) L.plan_p = std::make_shared<StreamPlan>(plan_stream(L.P, false));
+    if (L.R.nrows) L.plan_r = std::make_shared<StreamPlan>(plan_stream(L.R, false));
   }
 }
 
@@ -276,7 +365,7 @@ DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, const StreamPlan* pla
   } else {
     StreamPlan local;
     if (!plan) {
-      local = plan_stream(H);
+      local = plan_stream(H, false);
       plan = &local;
     }
     M.n = H.nrows;
@@ -284,6 +373,12 @@ DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, const StreamPlan* pla
     M.nnz = H.nnz();
     M.rp = upload_small<int>(ar, H.rp, st);
     configure(M, max_blocks);
+    if (plan->nd) {
+      M.nd = plan->nd;
+      M.ds = plan->ds;
+      std::copy(plan->doff, plan->doff + kDiagK, M.doff);
+      M.nb = (M.n + kBlock - 1) / kBlock;
+    }
     if (!plan->blk.empty()) {
       M.blk = upload_small<int>(ar, plan->blk, st);
       M.nb = (int)plan->blk.size() - 1;
@@ -297,9 +392,23 @@ DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, const StreamPlan* pla
       M.cs = upload_padded<uint16_t>(ar, plan->cs.data(), plan->cs.size(), st);
       M.cbase = upload_small<int>(ar, plan->cbase, st);
     }
-    if ((!M.cd && !M.cs) || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
+    if ((!M.nd && !M.cd && !M.cs) || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
   }
-  M.v = upload_padded<T>(ar, std::vector<T>(H.v.begin(), H.v.end()).data(), H.v.size(), st);
+  if (M.nd && !(plan && plan->nd == M.nd)) {
+    // a matrix sharing a diagonal-form pattern without diagonals of its own (a simulation's
+    // A_i): CSR only, read by kernels outside the product (which keep the column indices)
+    M.nd = 0;
+    configure(M, max_blocks);
+    if (!M.ci) throw std::runtime_error("device matrix without a usable form");
+  }
+  if (M.nd) {
+    M.dv = ar.alloc<T>(plan->dval.size());
+    const std::vector<T> dv(plan->dval.begin(), plan->dval.end());
+    HIPCHK(hipMemcpyAsync(M.dv, dv.data(), dv.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  } else {
+    M.v = upload_padded<T>(ar, std::vector<T>(H.v.begin(), H.v.end()).data(), H.v.size(), st);
+  }
   return M;
 }
 
@@ -390,12 +499,20 @@ void bind(SpArgs<T>& a, const DCsr<T>& M) {
   a.av = M.v;
   a.nrows = M.n;
   a.tpb = M.tpb;
+  a.dv = M.dv;
+  a.ds = M.ds;
+  for (int o = 0; o < kDiagK; ++o) a.doff[o] = M.doff[o];
 }
 
 template <typename T, int OP>
 void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
   bind(a, M);
   if (M.n == 0) return;
+  if (M.nd) {
+    k_spmv_sdia<T, OP><<<M.nb, kBlock, 0, st>>>(a);
+    HIPCHK(hipGetLastError());
+    return;
+  }
   if (M.blk) {
     switch (M.form()) {
       case IXD8: k_spmv_stream<T, OP, IXD8><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
@@ -1106,7 +1223,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   if (o.smoother_degree < 1 || o.coarse_eq_limit < 1 || o.max_levels < 1 || !(o.cheb_hi > o.cheb_lo) ||
       !(o.cheb_lo >= 0.0) || o.esteig_iters < 1 || !(o.threshold >= 0.0) || !(o.stagnation_ratio > 0.0) ||
       o.coarse_dense_max < 1 || (o.coarsening != BD_SA && o.coarsening != BD_RS) ||
-      o.galerkin_device < 0 || o.galerkin_device > 2 ||
+      o.galerkin_device < 0 || o.galerkin_device > 2 || o.diag_form < 0 || o.diag_form > 1 ||
       (o.smoother != BD_CHEBYSHEV && o.smoother != BD_JACOBI) ||
       (o.vcycle_precision != BD_F64 && o.vcycle_precision != BD_F32))
     throw Failure{BD_E_INVALID, "invalid AMG options"};
@@ -1132,7 +1249,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   };
   const int rc = build_hierarchy(H, o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr);
   if (rc != BD_OK) throw Failure{rc, err};
-  if (use_device) plan_hierarchy(h->H);  // launch plans, on this (possibly worker) thread
+  if (use_device) plan_hierarchy(h->H, o.diag_form != 0);  // launch plans, on this (possibly worker) thread
   h->M = (int)h->H.lv.size() - 1;
   h->host_only = true;
   if (!host_only) device_upload(h.get(), weights, false, st);
@@ -1238,6 +1355,7 @@ void bidomain_default_opts(bd_amg_opts* o) {
   o->stagnation_ratio = 0.9;
   o->coarse_dense_max = 2048;
   o->galerkin_device = 1;
+  o->diag_form = 1;
 }
 
 const char* bidomain_last_error(void) { return g_last_error.c_str(); }
@@ -1283,6 +1401,7 @@ int bidomain_amg_info(const bd_amg* h, bd_amg_stats* s) {
                                : (h->mixed ? static_cast<const DPat&>(h->L32[k].A) : static_cast<const DPat&>(h->L64[k].A));
         s->col_bytes[k] = M.col_bytes();
         s->tiles[k] = M.blk ? M.nb : 0;
+        s->diags[k] = M.nd;
         if (k + 1 < L.size()) {
           const DPat& P = h->mixed ? static_cast<const DPat&>(h->L32[k].P) : static_cast<const DPat&>(h->L64[k].P);
           const DPat& R = h->mixed ? static_cast<const DPat&>(h->L32[k].R) : static_cast<const DPat&>(h->L64[k].R);
@@ -1595,8 +1714,8 @@ void launch_tasks(std::vector<Task>& v, hipStream_t st, Staging& stg, Launch lau
 template <typename T>
 struct Batch {
   // products by index form (IdxForm) and op
-  std::vector<SpTask<T>> sp[3][OP_TRUE_RESID + 1];
-  std::vector<SpTask<double>> cgq[3];  // outer products (always float64)
+  std::vector<SpTask<T>> sp[kForms][OP_TRUE_RESID + 1];
+  std::vector<SpTask<double>> cgq[kForms];  // outer products (always float64)
   std::vector<UpdTask<T>> upd;
   std::vector<DirTask<T>> dir;
   std::vector<GemvTask<T>> gemv;
@@ -1606,7 +1725,7 @@ struct Batch {
   template <int OP>
   void add(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
     if (M.n == 0) return;
-    if (!M.blk) {  // rows longer than the staging buffer: lane-group kernel, one launch
+    if (!M.blk && !M.nd) {  // rows longer than the staging buffer: lane-group kernel, one launch
       single.push_back([=] { launch_spmv<T, OP>(M, a, st); });
       return;
     }
@@ -1631,6 +1750,9 @@ struct Batch {
   });                                                                                                    \
   launch_tasks(sp[IXD8][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                          \
     k_spmv_stream_multi<T, OPV, IXD8><<<nb, kBlock, 0, st>>>(d, n);                                      \
+  });                                                                                                    \
+  launch_tasks(sp[SDIA][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                          \
+    k_spmv_sdia_multi<T, OPV><<<nb, kBlock, 0, st>>>(d, n);                                              \
   });
     BD_SPL(OP_Y)
     BD_SPL(OP_ADDY)
@@ -1648,6 +1770,9 @@ struct Batch {
     });
     launch_tasks(cgq[IXD8], st, stg, [&](const SpTask<double>* d, int n, int nb) {
       k_spmv_stream_multi<double, OP_CG_Q, IXD8><<<nb, kBlock, 0, st>>>(d, n);
+    });
+    launch_tasks(cgq[SDIA], st, stg, [&](const SpTask<double>* d, int n, int nb) {
+      k_spmv_sdia_multi<double, OP_CG_Q><<<nb, kBlock, 0, st>>>(d, n);
     });
     launch_tasks(upd, st, stg, [&](const UpdTask<T>* d, int n, int nb) { k_cg_update_multi<T><<<nb, kBlock, 0, st>>>(d, n); });
     launch_tasks(dir, st, stg, [&](const DirTask<T>* d, int n, int nb) { k_cg_direction_multi<T><<<nb, kBlock, 0, st>>>(d, n); });
@@ -1826,7 +1951,7 @@ void batched_round(std::vector<BInst*>& I, hipStream_t st, Staging& stg) {
     const DCsr<double>& M = i->h->A0;
     SpArgs<double> a = args<double>(i->h->sv);
     a.x = i->h->p; a.y = i->h->q;
-    if (M.blk) {
+    if (M.blk || M.nd) {
       bind(a, M);
       SpTask<double> t;
       t.a = a; t.blk = M.blk; t.nb = M.nb; t.off = 0;

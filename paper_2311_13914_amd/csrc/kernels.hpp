@@ -251,6 +251,10 @@ enum SpOp : int {
 // Level-0 reductions fused into the last V-cycle kernel (OP_CHEB_STEP) or run alone.
 enum VcRed : int { RED_NONE = 0, RED_F64 = 1, RED_F32 = 2 };
 
+// Stored diagonals of the symmetric diagonal form: offset 0 and the 13 positive column - row
+// offsets of a 27-point stencil.
+constexpr int kDiagK = 14;
+
 template <typename T>
 struct SpArgs {
   const int* rp;
@@ -281,6 +285,10 @@ struct SpArgs {
   const double* r64;     // RED_F64: the CG residual (level-0 right-hand side)
   const float* r32;      // RED_F32: current level-0 right-hand side
   const float* r32_old;  // RED_F32: previous level-0 right-hand side
+  // symmetric diagonal form only: diagonal o (offset doff[o] >= 0) at dv + o * ds
+  const T* dv;
+  int64_t ds;
+  int doff[kDiagK];
 };
 
 template <typename T>
@@ -494,7 +502,8 @@ static_assert(kStageLen <= kStreamChunks * 4 * kBlock, "every spanned chunk has 
 // Column index forms of a CSR-stream matrix: 32-bit indices; 16-bit offsets from a per-tile
 // base; or, for matrices whose column - row offsets take at most 256 distinct values (the
 // stencil operators of a structured mesh), an 8-bit index into that offset dictionary.
-enum IdxForm : int { IX32 = 0, IX16 = 1, IXD8 = 2 };
+// SDIA: the symmetric diagonal form (k_spmv_sdia), no column indices at all.
+enum IdxForm : int { IX32 = 0, IX16 = 1, IXD8 = 2, SDIA = 3, kForms = 4 };
 // Dictionary tiles stage values, index bytes and the dictionary in LDS: a smaller cap keeps
 // the float64 total within the other forms' staging buffer.
 constexpr int kStreamCapD = 3450;
@@ -732,6 +741,58 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* 
   stream_body<T, OP, IX>(a, blk, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, smem, lds, lds32);
 }
 
+// ---------------------------------------------------------------------------------------
+// Symmetric diagonal product.  A matrix equal to its transpose whose column - row offsets
+// take at most 2 kDiagK - 1 values, symmetric about zero (27 for the 27-point stencil of a
+// structured hexahedral mesh), is stored as its diagonals of offset d_o >= 0 only:
+// dv[o * ds + i] = a(i, i + d_o), zero where that entry does not exist.  Row i takes
+// a(i, i + d_o) from dv[o][i] and a(i, i - d_o) = a(i - d_o, i) from dv[o][i - d_o].  One row
+// per lane: both value streams and both gathers x[i + d_o], x[i - d_o] are contiguous across
+// a wave's consecutive rows, so the product reads no column indices or row pointers, stages
+// nothing in LDS, and moves 14 values per row from HBM instead of 27; the shifted second
+// read of each diagonal comes from cache (a lane's own rows or those of recent blocks of the
+// same XCD).  Indices past either end are clamped and their terms weighted by zero (the
+// stored value there is zero, or the row test below drops it).
+template <typename T, int OP>
+__device__ __forceinline__ void sdia_body(const SpArgs<T>& a, int b, int nb, double* lds, float* lds32) {
+  if (a.sv.fl[F_DONE]) return;  // written by an earlier kernel: a plain load sees it
+  const int n = a.nrows;
+  const int row = b * kBlock + (int)threadIdx.x;
+  double acc[3] = {0.0, 0.0, 0.0};
+  VcAcc<T> vc;
+  if (row < n) {
+    const T* __restrict__ dv = a.dv;
+    const T* __restrict__ x = a.x;
+    T vu[kDiagK], xu[kDiagK], vl[kDiagK], xl[kDiagK];
+#pragma unroll
+    for (int o = 0; o < kDiagK; ++o) {
+      vu[o] = dv[o * a.ds + row];
+      xu[o] = x[min(row + a.doff[o], n - 1)];
+    }
+#pragma unroll
+    for (int o = 1; o < kDiagK; ++o) {
+      const int j = max(row - a.doff[o], 0);
+      vl[o] = dv[o * a.ds + j];
+      xl[o] = x[j];
+    }
+    const RowIn<T> in = row_fetch<T, OP>(a, row);
+    T s[4] = {vu[0] * xu[0], T(0), T(0), T(0)};
+#pragma unroll
+    for (int o = 1; o < kDiagK; ++o) {
+      s[o & 3] += vu[o] * xu[o];
+      s[(o + 2) & 3] += (row >= a.doff[o]) ? vl[o] * xl[o] : T(0);
+    }
+    row_apply<T, OP>(a, row, (s[0] + s[1]) + (s[2] + s[3]), in, acc, vc);
+  }
+  block_tail<T, OP>(a, acc, vc, b, nb, lds, lds32);
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_spmv_sdia(SpArgs<T> a) {
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  sdia_body<T, OP>(a, xcd_tile(blockIdx.x, gridDim.x), gridDim.x, lds, lds32);
+}
 
 // Block partials of the level-0 reductions: 1^T z, r^T z, 1^T r (RED_F64) or the two Dot2
 // pairs z32.r32, z32.r32_old and 1^T z (RED_F32).
@@ -1108,6 +1169,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream_multi(const SpTask<T>* _
   const SpTask<T>& tk = tasks[task_of(tasks, ntasks)];
   const SpArgs<T> a = tk.a;
   stream_body<T, OP, IX>(a, tk.blk, xcd_tile((int)blockIdx.x - tk.off, tk.nb), tk.nb, smem, lds, lds32);
+}
+
+template <typename T, int OP>
+__global__ __launch_bounds__(kBlock) void k_spmv_sdia_multi(const SpTask<T>* __restrict__ tasks, int ntasks) {
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  const SpTask<T>& tk = tasks[task_of(tasks, ntasks)];
+  const SpArgs<T> a = tk.a;
+  sdia_body<T, OP>(a, xcd_tile((int)blockIdx.x - tk.off, tk.nb), tk.nb, lds, lds32);
 }
 
 template <typename T>

@@ -50,16 +50,23 @@ def _relerr(a, b):
     return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
 
 
+# the fine operator in the symmetric diagonal form (the default for a 27-point operator) or in
+# the CSR-stream offset-dictionary form
+FORMS = {"diag": (1, 14, 0), "csr": (0, 0, 1)}  # diag_form option, stored diagonals, index bytes
+
+
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("name", list(CASES))
-def test_vcycle_operations_match_oracle(torch, name):
+def test_vcycle_operations_match_oracle(torch, name, form):
     c, ops, f = _problem(name)
     A = ops["Aell"]
     h_or = amg.setup(A, amg.AMGOptions(nullspace=True))
-    print(f"[gpu] case={name} n={c.n} levels={h_or.nlevels}", flush=True)
-    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1), ops["m"])
+    print(f"[gpu] case={name} form={form} n={c.n} levels={h_or.nlevels}", flush=True)
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, diag_form=FORMS[form][0]), ops["m"])
     try:
         info = lib.bidomain_amg_info(h)
         assert info["n"] == [lv.A.shape[0] for lv in h_or.levels]
+        assert (info["diags"][0], info["col_bytes"][0]) == FORMS[form][1:]
         rng = np.random.default_rng(11)
         for k, lv in enumerate(h_or.levels):
             n = lv.A.shape[0]
@@ -101,18 +108,21 @@ def _check_solution(A, f, x, m, x_ref, rtol=1e-8, err=1e-6, nullspace=True):
     assert np.linalg.norm(x - x_ref) <= err * np.linalg.norm(x_ref)
 
 
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("name", list(CASES))
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_elliptic_solve_matches_oracle(torch, name, precision):
+def test_elliptic_solve_matches_oracle(torch, name, precision, form):
     c, ops, f = _problem(name)
     A, m = ops["Aell"], ops["m"]
     h_or = amg.setup(A, amg.AMGOptions(nullspace=True))
     ref = krylov.amg_pcg(A, f, h_or, rtol=1e-12, m=m)
     or8 = (krylov.amg_pcg if precision == "f64" else krylov.amg_fcg_mixed)(A, f, h_or, rtol=1e-8, m=m)
-    print(f"[gpu] case={name} precision={precision} oracle_its={or8.iterations}", flush=True)
-    opts = lib.bidomain_default_opts(nullspace=1, vcycle_precision=lib.BD_F64 if precision == "f64" else lib.BD_F32)
+    print(f"[gpu] case={name} precision={precision} form={form} oracle_its={or8.iterations}", flush=True)
+    opts = lib.bidomain_default_opts(nullspace=1, vcycle_precision=lib.BD_F64 if precision == "f64" else lib.BD_F32,
+                                     diag_form=FORMS[form][0])
     h = lib.bidomain_amg_setup(A, opts, m)
     try:
+        assert lib.bidomain_amg_info(h)["diags"][0] == FORMS[form][1]
         x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
         rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-8, 200)
         assert rc == lib.BD_OK, info
@@ -283,6 +293,91 @@ def test_product_index_forms(torch, far, jitter, col_bytes):
         lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, dev(torch, x), out)
         ref = A @ x
         assert _relerr(host(out), ref) <= 1e-13
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+def _long_row_matrix(n, base, long_rows, seed):
+    """Rows of 0..base-1 entries plus `long_rows` rows of 4,029..12,000 entries (longer than a
+    stream tile holds, so the lane-group kernel takes the matrix), row lengths ragged around
+    the kernel's 1,024-entry trips; columns (7 i + k s_i) mod n with odd s_i, distinct within a
+    row since n is a power of two; a diagonal added to every row."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    L = rng.integers(0, base, n)
+    pick = rng.choice(n, long_rows, replace=False)
+    L[pick] = rng.integers(4029, 12001, long_rows)
+    L[pick[:4]] = [4029, 4096, 5121, 8191][: min(4, long_rows)]
+    step = rng.integers(0, n // 2, n) * 2 + 1
+    r = np.repeat(np.arange(n), L)
+    k = np.arange(r.size) - np.repeat(np.cumsum(L) - L, L)
+    c = (7 * r + k * step[r]) % n
+    v = rng.uniform(-1.0, 1.0, r.size)
+    d = np.arange(n)
+    return sp.csr_matrix((np.concatenate([v, np.full(n, 4.0)]),
+                          (np.concatenate([r, d]), np.concatenate([c, d]))), shape=(n, n))
+
+
+@pytest.mark.parametrize("n,base,long_rows", [(16384, 400, 64), (16384, 100, 3)])
+def test_long_rows_lane_group(torch, n, base, long_rows):
+    """Rows longer than a stream tile (coarse levels of the largest slabs reach ~12,000 entries)
+    go to the lane-group kernel: 64 lanes a row when the mean row is long, fewer otherwise;
+    the product must still be exact to rounding."""
+    A = _long_row_matrix(n, base, long_rows, seed=23)
+    A.sort_indices()
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(max_levels=1, nullspace=0))
+    try:
+        info = lib.bidomain_amg_info(h)
+        print(f"[gpu] long rows n={n} base={base} long={long_rows} nnz={A.nnz} "
+              f"tiles={info['tiles'][0]}", flush=True)
+        assert info["tiles"][0] == 0
+        x = np.random.default_rng(6).standard_normal(n)
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, dev(torch, x), out)
+        ref = A @ x
+        assert _relerr(host(out), ref) <= 1e-13
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+def _diag_cases():
+    """(name, matrix, expected stored diagonals): the symmetric diagonal form is taken only for
+    an exactly symmetric matrix with at most 14 offsets >= 0 that it stores in fewer bytes."""
+    import scipy.sparse as sp
+    c = bc.make_case(21, 19, 11, seed=3)            # n = 22 * 20 * 12 = 5280
+    A = fem.assemble_operators(c)["Aell"].tocsr()
+    A.sort_indices()
+    out = [("27-point", A, 14)]
+    B = A.copy()
+    k = B.indptr[100] + 3                            # one value no longer equals its mirror
+    B.data[k] = np.nextafter(B.data[k], np.inf)
+    out.append(("one value off", B, 0))
+    C = A.tolil()
+    i = 2000
+    j = int(A.indices[A.indptr[i]])                  # drop one mirror entry: pattern asymmetric
+    C[j, i] = 0.0
+    C = C.tocsr()
+    C.eliminate_zeros()
+    out.append(("one mirror missing", C, 0))
+    n = A.shape[0]
+    e = np.ones(n)
+    L = sp.diags([-e[1:], 2 * e, -e[1:]], [-1, 0, 1], format="csr")   # 3 nonzeros a row
+    out.append(("three-point", L, 0))
+    return out
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_diag_form_selection(torch, case):
+    name, A, nd = _diag_cases()[case]
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(max_levels=1, nullspace=0))
+    try:
+        info = lib.bidomain_amg_info(h)
+        print(f"[gpu] diagonal form case={name} diags={info['diags'][0]} col_bytes={info['col_bytes'][0]}", flush=True)
+        assert info["diags"][0] == nd
+        x = np.random.default_rng(8).standard_normal(A.shape[0])
+        out = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+        lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, dev(torch, x), out)
+        assert _relerr(host(out), A @ x) <= 1e-14
     finally:
         lib.bidomain_amg_destroy(h)
 

@@ -34,6 +34,7 @@ def test_default_options_follow_appendix_a():
     assert o.threshold == 0.06 and o.prolong_smooths == 1 and o.coarse_eq_limit == 100
     assert o.square_graph_levels == 1 and o.smoother_degree == 2 and o.esteig_iters == 10
     assert (o.cheb_lo, o.cheb_hi) == (0.05, 1.05)
+    assert o.galerkin_device == 1 and o.diag_form == 1
 
 
 def _csr(rp, ci, v, n):
