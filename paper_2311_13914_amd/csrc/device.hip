@@ -87,7 +87,7 @@ struct DPat {
   const int* dict = nullptr;      // the distinct column - row offsets, with cd
   int ndict = 0;
   int G = 8;    // lanes per row (row-group kernel)
-  int tpb = 1;  // row tiles per block (row-group kernel)
+  int tpb = 1;  // row tiles per block (row-group kernel); chunks per plane (diagonal form)
   int nb = 0;   // blocks of a product launch
   const int* blk = nullptr;  // CSR-stream row tiles (nb + 1 row boundaries), or null
   int nd = 0;                // symmetric diagonal form: stored diagonals (kDiagK), or 0
@@ -278,7 +278,7 @@ bool sym_diagonals(const Csr& H, StreamPlan& P) {
       if (P.doff[o] == d) return o;
     return -1;
   };
-  P.ds = ((int64_t)n + 63) / 64 * 64;
+  P.ds = ((int64_t)n + 1 + 63) / 64 * 64;  // at least one zero slot past the last row
   P.dval.assign((size_t)kDiagK * P.ds, 0.0);
   std::vector<uint16_t> up(n, 0), lo(n, 0);  // slots filled by row i's own and mirrored entries
   int64_t nup = 0, nlo = 0;
@@ -377,7 +377,11 @@ DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, const StreamPlan* pla
       M.nd = plan->nd;
       M.ds = plan->ds;
       std::copy(plan->doff, plan->doff + kDiagK, M.doff);
-      M.nb = (M.n + kBlock - 1) / kBlock;
+      // block grid of the diagonal kernel: Z planes of S 256-row chunks (tpb holds S)
+      const int chunks = (M.n + kBlock - 1) / kBlock;
+      const int dmax = *std::max_element(M.doff, M.doff + kDiagK);
+      M.tpb = std::max(1, std::min(chunks, (dmax + kBlock - 1) / kBlock));
+      M.nb = M.tpb * ((chunks + M.tpb - 1) / M.tpb);
     }
     if (!plan->blk.empty()) {
       M.blk = upload_small<int>(ar, plan->blk, st);

@@ -267,7 +267,7 @@ struct SpArgs {
   int ncols;
   const T* av;
   int nrows;
-  int tpb;           // row tiles per block
+  int tpb;           // row tiles per block (row-group kernel); chunks per plane S (diagonal form)
   const T* x;        // product input (also the pointwise direction d of the Chebyshev steps)
   T* y;              // output
   T* y2;             // second output
@@ -752,38 +752,52 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* 
 // nothing in LDS, and moves 14 values per row from HBM instead of 27; the shifted second
 // read of each diagonal comes from cache (a lane's own rows or those of recent blocks of the
 // same XCD).  Indices past either end are clamped and their terms weighted by zero (the
-// stored value there is zero, or the row test below drops it).
+// stored value there is zero; each diagonal holds at least one zero slot past row n - 1).
+//
+// Block order: 256-row chunks form a grid of Z "planes" of S chunks (S chunks span at least the
+// largest offset), and consecutive blocks of the sequence walk a column (c fixed, z
+// increasing), so that the rows i - d_o of the far diagonals lie near chunks loaded by recent
+// blocks of the same XCD (measured: 6 % less fetched than plain row order; two-dimensional
+// tiles of a grid plane walked along z fetch less still but lose the contiguous wave access
+// and run slower).
+template <typename T, int OP>
+__device__ __forceinline__ void sdia_row(const SpArgs<T>& a, int row, double (&acc)[3], VcAcc<T>& vc) {
+  const int n = a.nrows;
+  const T* __restrict__ dv = a.dv;
+  const T* __restrict__ x = a.x;
+  T vu[kDiagK], xu[kDiagK], vl[kDiagK], xl[kDiagK];
+#pragma unroll
+  for (int o = 0; o < kDiagK; ++o) {
+    vu[o] = dv[o * a.ds + row];
+    xu[o] = x[min(row + a.doff[o], n - 1)];
+  }
+#pragma unroll
+  for (int o = 1; o < kDiagK; ++o) {
+    // before the first row the value index points at the zero slot n of the diagonal, so every
+    // term is a plain product (a select on the product let the compiler sink loads into a branch)
+    const int j = row - a.doff[o];
+    vl[o] = dv[o * a.ds + (j >= 0 ? j : n)];
+    xl[o] = x[max(j, 0)];
+  }
+  const RowIn<T> in = row_fetch<T, OP>(a, row);
+  T s[4] = {vu[0] * xu[0], T(0), T(0), T(0)};
+#pragma unroll
+  for (int o = 1; o < kDiagK; ++o) {
+    s[o & 3] += vu[o] * xu[o];
+    s[(o + 2) & 3] += vl[o] * xl[o];
+  }
+  row_apply<T, OP>(a, row, (s[0] + s[1]) + (s[2] + s[3]), in, acc, vc);
+}
+
 template <typename T, int OP>
 __device__ __forceinline__ void sdia_body(const SpArgs<T>& a, int b, int nb, double* lds, float* lds32) {
   if (a.sv.fl[F_DONE]) return;  // written by an earlier kernel: a plain load sees it
-  const int n = a.nrows;
-  const int row = b * kBlock + (int)threadIdx.x;
+  const int S = a.tpb, Z = nb / S;
+  const int c = b / Z, z = b - c * Z;
+  const int row = (z * S + c) * kBlock + (int)threadIdx.x;
   double acc[3] = {0.0, 0.0, 0.0};
   VcAcc<T> vc;
-  if (row < n) {
-    const T* __restrict__ dv = a.dv;
-    const T* __restrict__ x = a.x;
-    T vu[kDiagK], xu[kDiagK], vl[kDiagK], xl[kDiagK];
-#pragma unroll
-    for (int o = 0; o < kDiagK; ++o) {
-      vu[o] = dv[o * a.ds + row];
-      xu[o] = x[min(row + a.doff[o], n - 1)];
-    }
-#pragma unroll
-    for (int o = 1; o < kDiagK; ++o) {
-      const int j = max(row - a.doff[o], 0);
-      vl[o] = dv[o * a.ds + j];
-      xl[o] = x[j];
-    }
-    const RowIn<T> in = row_fetch<T, OP>(a, row);
-    T s[4] = {vu[0] * xu[0], T(0), T(0), T(0)};
-#pragma unroll
-    for (int o = 1; o < kDiagK; ++o) {
-      s[o & 3] += vu[o] * xu[o];
-      s[(o + 2) & 3] += (row >= a.doff[o]) ? vl[o] * xl[o] : T(0);
-    }
-    row_apply<T, OP>(a, row, (s[0] + s[1]) + (s[2] + s[3]), in, acc, vc);
-  }
+  if (row < a.nrows) sdia_row<T, OP>(a, row, acc, vc);
   block_tail<T, OP>(a, acc, vc, b, nb, lds, lds32);
 }
 
