@@ -257,6 +257,8 @@ def main():
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--no-mixed-serve", action="store_true", help="serve: float64 V-cycles")
     ap.add_argument("--coarsening", default="sa", choices=["sa", "rs"])
+    ap.add_argument("--par-precond", default="amg", choices=["amg", "jacobi", "none"],
+                    help="step: preconditioner of the parabolic CG (none = the paper's GPU runs, Sec. 5)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed region, copy 1 GiB once (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -281,6 +283,7 @@ def main():
     prec = lib.BD_F32 if args.mixed else lib.BD_F64
     opts_e = lib.bidomain_default_opts(vcycle_precision=prec)
     opts_p = lib.bidomain_default_opts(vcycle_precision=prec, threshold=0.0)  # parabolic default
+    opts_p.preconditioner = {"amg": lib.BD_PC_AMG, "jacobi": lib.BD_PC_JACOBI, "none": lib.BD_PC_NONE}[args.par_precond]
     v0 = torch.tensor(bc.nodal_v0(case), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
 
@@ -351,7 +354,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: Bidomain slab {case.nx}x{case.ny}x{case.nz} Q1 elements, n={n}, "
-                        f"nnz={nnz}, Aliev-Panfilov + parabolic + elliptic AMG-PCG per step, rtol {args.rtol:g}",
+                        f"nnz={nnz}, Aliev-Panfilov + parabolic + elliptic AMG-PCG per step, rtol {args.rtol:g}"
+                        + ("" if args.par_precond == "amg" else f"; parabolic CG preconditioner: {args.par_precond}"),
             "elliptic_levels": info_e["n"],
             "parabolic_levels": info_p["n"],
             "operator_complexity_ell": round(info_e["operator_complexity"], 3),

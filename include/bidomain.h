@@ -48,6 +48,7 @@ enum { BD_SA = 0, BD_RS = 1 };                 /* coarsening                    
 enum { BD_CHEBYSHEV = 0, BD_JACOBI = 1 };      /* level smoother                            */
 enum { BD_F64 = 0, BD_F32 = 1 };               /* V-cycle precision                          */
 enum { BD_NULL_NONE = 0, BD_NULL_CONSTANT = 1 };/* kernel of the operator                    */
+enum { BD_PC_AMG = 0, BD_PC_JACOBI = 1, BD_PC_NONE = 2 }; /* preconditioner of the CG solve    */
 
 /*
  * AMG options.  Defaults (bidomain_default_opts) follow App. A of the paper: smoothed
@@ -83,6 +84,12 @@ typedef struct {
    * offsets >= 0 (the 27-point fine operators) in the symmetric diagonal form (default);
    * 0: CSR forms only. */
   int32_t diag_form;
+  /* Preconditioner of bidomain_pcg_solve (and of the simulation's solves): BD_PC_AMG, one
+   * V-cycle (default); BD_PC_JACOBI, z = D^{-1} r; BD_PC_NONE, z = r (plain CG; the paper runs
+   * the parabolic system unpreconditioned on GPUs and with block Jacobi on CPUs, Sec. 5).
+   * With JACOBI or NONE the setup keeps the fine level only and vcycle_precision must be
+   * BD_F64; the serving API takes BD_PC_AMG only. */
+  int32_t preconditioner;
 } bd_amg_opts;
 
 void bidomain_default_opts(bd_amg_opts* opts);
@@ -118,7 +125,9 @@ typedef struct {
   double grid_complexity;
   int64_t device_bytes;           /* device memory owned by the handle                    */
   /* The level operator's product on the device (0 on a host-only handle): bytes per column
-   * index it reads (4; 2 for 16-bit offsets from a per-tile column base; 1 for an index into
+   * index it reads (4; 2 for 16-bit offsets from a per-tile column base, or for 16-bit column
+   * indices where rows are too long for the staging buffer and there are at most 65,536
+   * columns; 1 for an index into
    * the matrix's dictionary of at most 256 distinct column - row offsets; 0 in the symmetric
    * diagonal form below) and its row tiles (0 when rows are too long for the staging buffer
    * and a lane-group kernel runs, or in the diagonal form). */

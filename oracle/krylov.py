@@ -18,6 +18,8 @@ Readings:
     guess and preconditioned residual for the elliptic system; stop on the recursive residual
     ||r|| <= rtol ||Pi f||; the returned elliptic solution is normalised to m^T x = 0
     (integral zero);
+  * diagonal preconditioning (point Jacobi, z = D^{-1} r) or none stand in for the paper's
+    parabolic solvers (block Jacobi on CPUs, unpreconditioned on GPUs, Sec. 5);
   * flexible CG (Notay 2000) with beta = z_{k+1}^T (r_{k+1} - r_k) / (z_k^T r_k);
   * mixed form: the V-cycle runs in float32 on a float32 copy of the hierarchy, the coarse
     solve stays float64; its inner products z.r are taken exactly (correctly rounded) here,
@@ -247,3 +249,18 @@ def amg_fcg_mixed(A, f, h: Hierarchy, x0=None, rtol=1e-8, maxit=500, m=None):
     """FCG(1) in float64 around a float32 V-cycle with a float64 coarse solve."""
     lv32 = float32_levels(h)
     return fcg(A, f, lambda r32: vcycle(h, r32, 0, lv32), x0, rtol, maxit, h.opts.nullspace, m)
+
+
+def diag_pcg(A, f, kind, x0=None, rtol=1e-8, maxit=5000, nullspace=False, m=None):
+    """CG with a diagonal preconditioner or none.  The paper solves the parabolic system with
+    unpreconditioned CG on GPUs and with block-Jacobi-preconditioned CG on CPUs (Sec. 5).
+    kind "jacobi": z = D^{-1} r with D = diag(A) (point Jacobi); kind "none": z = r."""
+    if kind == "jacobi":
+        dinv = 1.0 / A.diagonal()
+        precond = lambda r: dinv * r
+    elif kind == "none":
+        precond = lambda r: r
+    else:
+        raise ValueError(kind)
+    return pcg(A, f, precond, x0, rtol, maxit, nullspace, m)
+

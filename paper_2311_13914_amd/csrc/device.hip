@@ -81,7 +81,7 @@ struct DPat {
   int64_t nnz = 0;
   const int* rp = nullptr;
   const int* ci = nullptr;        // 32-bit column indices, or null when only cs is kept
-  const uint16_t* cs = nullptr;   // CSR-stream: column - cbase[tile] (16 bits), or null
+  const uint16_t* cs = nullptr;   // column - cbase[tile] (stream) or the column (lane group) in 16 bits, or null
   const int* cbase = nullptr;     // CSR-stream: per-tile column base, with cs
   const uint8_t* cd = nullptr;    // CSR-stream: index into dict of column - row, or null
   const int* dict = nullptr;      // the distinct column - row offsets, with cd
@@ -231,7 +231,7 @@ struct StreamPlan {
   std::vector<int> blk;         // row tiles, or empty (lane-group kernel)
   std::vector<uint8_t> cd;      // offset-dictionary indices, or empty
   std::vector<int> dict;
-  std::vector<uint16_t> cs;     // 16-bit per-tile offsets, or empty
+  std::vector<uint16_t> cs;     // 16-bit per-tile offsets (stream) or column indices (lane group), or empty
   std::vector<int> cbase;
 };
 
@@ -331,6 +331,9 @@ StreamPlan plan_stream(const Csr& H, bool diag_form) {
       P.cs.clear();
       P.cbase.clear();
     }
+    // rows too long for a stream tile, 64 lanes a row: 16-bit column indices where they fit
+    if (P.blk.empty() && H.nrows > 0 && H.ncols <= 65536 && lanes_for((double)H.nnz() / H.nrows) == 64)
+      P.cs.assign(H.ci.begin(), H.ci.end());
   }
   return P;
 }
@@ -394,7 +397,7 @@ DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, const StreamPlan* pla
     }
     if (!plan->cs.empty()) {
       M.cs = upload_padded<uint16_t>(ar, plan->cs.data(), plan->cs.size(), st);
-      M.cbase = upload_small<int>(ar, plan->cbase, st);
+      if (!plan->cbase.empty()) M.cbase = upload_small<int>(ar, plan->cbase, st);
     }
     if ((!M.nd && !M.cd && !M.cs) || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
   }
@@ -523,6 +526,11 @@ void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
       case IX16: k_spmv_stream<T, OP, IX16><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
       default: k_spmv_stream<T, OP, IX32><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
     }
+    HIPCHK(hipGetLastError());
+    return;
+  }
+  if (M.cs && M.G == 64) {  // 16-bit column indices (plan_stream takes them only with 64 lanes)
+    k_spmv<T, 64, OP, IX16><<<M.nb, kBlock, 0, st>>>(a);
     HIPCHK(hipGetLastError());
     return;
   }
@@ -706,6 +714,19 @@ bool vcycle(bd_amg* h, int k, const Solve& sv, bool d_ready, const RedSpec& red,
 template <typename T>
 void precondition(bd_amg* h, const Solve& sv, bool d_ready, const RedSpec& red, hipStream_t st) {
   auto& L = levels<T>(h);
+  if constexpr (std::is_same<T, double>::value) {
+    if (h->o.preconditioner != BD_PC_AMG) {  // Jacobi or none: one pointwise kernel
+      SpArgs<double> a = args<double>(sv);
+      a.nrows = L[0].n;
+      a.r64 = red.r64;
+      a.dinv = h->o.preconditioner == BD_PC_JACOBI ? L[0].dinv : nullptr;
+      const int nb = vec_blocks(L[0].n);
+      k_pc_diag<<<nb, kBlock, 0, st>>>(a, L[0].x);
+      HIPCHK(hipGetLastError());
+      finalize(sv, FIN_VC64, nb, st);
+      return;
+    }
+  }
   const bool fused = vcycle<T>(h, 0, sv, d_ready, red, st);
   if (red.red == RED_NONE) return;
   int nb = L[0].A.nb;
@@ -863,7 +884,7 @@ int pcg(bd_amg* h, const double* b, double* x, int guess, double rtol, int maxit
     k_clear_first<<<1, 64, 0, st>>>(sv);
     HIPCHK(hipGetLastError());
 
-    const bool fuse0 = smoothed_level(h, 0);
+    const bool fuse0 = smoothed_level(h, 0) && h->o.preconditioner == BD_PC_AMG;
     const bool x0_too = h->o.smoother == BD_JACOBI || h->o.smoother_degree == 1;
     hipEvent_t ev[2];
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -1228,9 +1249,15 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
       !(o.cheb_lo >= 0.0) || o.esteig_iters < 1 || !(o.threshold >= 0.0) || !(o.stagnation_ratio > 0.0) ||
       o.coarse_dense_max < 1 || (o.coarsening != BD_SA && o.coarsening != BD_RS) ||
       o.galerkin_device < 0 || o.galerkin_device > 2 || o.diag_form < 0 || o.diag_form > 1 ||
+      o.preconditioner < BD_PC_AMG || o.preconditioner > BD_PC_NONE ||
+      (o.preconditioner != BD_PC_AMG && o.vcycle_precision != BD_F64) ||
       (o.smoother != BD_CHEBYSHEV && o.smoother != BD_JACOBI) ||
       (o.vcycle_precision != BD_F64 && o.vcycle_precision != BD_F32))
     throw Failure{BD_E_INVALID, "invalid AMG options"};
+  if (o.preconditioner != BD_PC_AMG) {
+    o.max_levels = 1;        // the fine level only (operator, D^{-1}, work vectors)
+    o.coarse_dense_max = 1;  // no dense coarse inverse of it
+  }
   Csr H;
   H.nrows = H.ncols = A->n;
   if (A->n <= 0 || A->nnz < 0 || A->nnz > INT32_MAX || !A->row_ptr || !A->col_idx || !A->val)
@@ -1360,6 +1387,7 @@ void bidomain_default_opts(bd_amg_opts* o) {
   o->coarse_dense_max = 2048;
   o->galerkin_device = 1;
   o->diag_form = 1;
+  o->preconditioner = BD_PC_AMG;
 }
 
 const char* bidomain_last_error(void) { return g_last_error.c_str(); }
@@ -2278,9 +2306,11 @@ int bidomain_serve_create(int64_t budget_bytes, int32_t max_slots, const bd_amg_
     bidomain_default_opts(&S->op);
     if (ell) S->oe = *ell;
     if (par) S->op = *par;
-    for (const bd_amg_opts* o : {&S->oe, &S->op})
+    for (const bd_amg_opts* o : {&S->oe, &S->op}) {
       if (o->smoother != BD_CHEBYSHEV || o->smoother_degree != 2)
         throw Failure{BD_E_INVALID, "serving needs the Chebyshev smoother of degree 2"};
+      if (o->preconditioner != BD_PC_AMG) throw Failure{BD_E_INVALID, "serving needs the AMG preconditioner"};
+    }
     if (S->oe.vcycle_precision != S->op.vcycle_precision)
       throw Failure{BD_E_INVALID, "both systems must use the same V-cycle precision when served"};
     S->mixed = S->oe.vcycle_precision == BD_F32;

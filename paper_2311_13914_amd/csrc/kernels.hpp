@@ -205,9 +205,10 @@ __device__ __forceinline__ void block_dot2(Dot2 (&v)[NV], float* lds /* NV * 2 *
 // CSR row product by a group of G lanes; every lane of the group returns the row sum.  Four
 // strided entries per lane per trip, with indices clamped into the row so that the four
 // column loads and the four x gathers are issued together (entries past the row end are
-// gathered but multiplied by zero).
-template <typename T, int G>
-__device__ __forceinline__ T row_product(const int* __restrict__ rp, const int* __restrict__ ci,
+// gathered but multiplied by zero).  Column indices of type I: int, or uint16_t for a matrix
+// of at most 65,536 columns.
+template <typename T, int G, typename I = int>
+__device__ __forceinline__ T row_product(const int* __restrict__ rp, const I* __restrict__ ci,
                                          const T* __restrict__ av, const T* __restrict__ x, int row,
                                          int lane) {
   T s = T(0);
@@ -219,7 +220,7 @@ __device__ __forceinline__ T row_product(const int* __restrict__ rp, const int* 
 #pragma unroll
       for (int j = 0; j < 4; ++j) kk[j] = min(k + j * G, end - 1);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) { c[j] = ci[kk[j]]; v[j] = av[kk[j]]; }
+      for (int j = 0; j < 4; ++j) { c[j] = (int)ci[kk[j]]; v[j] = av[kk[j]]; }
 #pragma unroll
       for (int j = 0; j < 4; ++j) xv[j] = x[c[j]];
 #pragma unroll
@@ -431,8 +432,9 @@ __device__ __forceinline__ void block_tail(const SpArgs<T>& a, double (&acc)[3],
 }
 
 // Row-group kernel: G lanes per row, TPB consecutive 256/G-row tiles per block.  Used for
-// matrices with a row longer than the CSR-stream staging buffer (kStreamCap entries).
-template <typename T, int G, int OP>
+// matrices with a row longer than the CSR-stream staging buffer (kStreamCap entries); IX16:
+// 16-bit column indices (cs) for a matrix of at most 65,536 columns.
+template <typename T, int G, int OP, int IX = 0>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
   if (solve_done(a.sv)) return;
   __shared__ double lds[16];
@@ -446,7 +448,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
   for (int t = 0; t < a.tpb; ++t) {
     const int row = (tile0 + t) * RPT + grp;
     if (row >= a.nrows) break;
-    const T s = row_product<T, G>(a.rp, a.ci, a.av, a.x, row, lane);
+    T s;
+    if constexpr (IX == 1) s = row_product<T, G, uint16_t>(a.rp, a.cs, a.av, a.x, row, lane);
+    else s = row_product<T, G, int>(a.rp, a.ci, a.av, a.x, row, lane);
     if (lane == 0) row_epilogue<T, OP>(a, row, s, acc, vc);
   }
   block_tail<T, OP>(a, acc, vc, blockIdx.x, nb, lds, lds32);
@@ -857,6 +861,22 @@ __global__ __launch_bounds__(kBlock) void k_vc_reduce(SpArgs<T> a, const T* __re
     vc.add(a.red, (double)z[i], (float)z[i], rr, r32, r32o);
   }
   vc_partials<T>(vc, a.red, a.sv, blockIdx.x, gridDim.x, lds, lds32);
+}
+
+// Diagonal preconditioners of a solve without a hierarchy: z = D^{-1} r (Jacobi) or z = r
+// (none: plain CG), with the reductions of the preconditioned residual (RED_F64) fused.
+__global__ __launch_bounds__(kBlock) void k_pc_diag(SpArgs<double> a, double* __restrict__ z) {
+  if (solve_done(a.sv)) return;
+  __shared__ double lds[16];
+  __shared__ float lds32[24];
+  VcAcc<double> vc;
+  for (long i = (long)blockIdx.x * kBlock + threadIdx.x; i < a.nrows; i += (long)gridDim.x * kBlock) {
+    const double r = a.r64[i];
+    const double zi = a.dinv ? a.dinv[i] * r : r;
+    z[i] = zi;
+    vc.add(RED_F64, zi, 0.f, r, 0.f, 0.f);
+  }
+  vc_partials<double>(vc, RED_F64, a.sv, blockIdx.x, gridDim.x, lds, lds32);
 }
 
 // One block: sums the partials of the preceding kernel (nb blocks) in a fixed order and

@@ -160,6 +160,57 @@ def test_parabolic_solve_matches_oracle(torch, dims):
         lib.bidomain_amg_destroy(h)
 
 
+@pytest.mark.parametrize("kind", ["none", "jacobi"])
+def test_diag_preconditioned_solves_match_oracle(torch, kind):
+    """The paper's GPU parabolic solver (unpreconditioned CG, Sec. 5) and point-Jacobi CG:
+    the parabolic system at 24 x 24 x 12, and the singular elliptic system at 16 x 16 x 8 with
+    the null-space projection; iteration counts within 1 (parabolic) or 2 % (elliptic, a few
+    hundred iterations) of the oracle's, solutions against a tighter oracle solve."""
+    pc = {"none": lib.BD_PC_NONE, "jacobi": lib.BD_PC_JACOBI}[kind]
+    c = bc.make_case(24, 24, 12, seed=5)
+    ops = fem.assemble_operators(c)
+    A = ops["Apar"]
+    f = A @ np.random.default_rng(12).standard_normal(c.n)
+    ref = krylov.diag_pcg(A, f, kind, rtol=1e-12)
+    or8 = krylov.diag_pcg(A, f, kind, rtol=1e-8)
+    print(f"[gpu] diagonal preconditioner {kind}: parabolic oracle_its={or8.iterations}", flush=True)
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(preconditioner=pc))
+    try:
+        assert lib.bidomain_amg_info(h)["nlevels"] == 1
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-8, 2000)
+        assert rc == lib.BD_OK and info["rel_residual_true"] <= 1e-8 * (1 + 1e-6)
+        _check_solution(A, f, host(x), None, ref.x, nullspace=False)
+        assert abs(info["iterations"] - or8.iterations) <= 1
+    finally:
+        lib.bidomain_amg_destroy(h)
+    c = bc.make_case(16, 16, 8, seed=9)
+    ops = fem.assemble_operators(c)
+    A, m = ops["Aell"], ops["m"]
+    f = -(ops["Ai"] @ bc.nodal_v0(c))
+    ref = krylov.diag_pcg(A, f, kind, rtol=1e-12, nullspace=True, m=m)
+    or8 = krylov.diag_pcg(A, f, kind, rtol=1e-8, nullspace=True, m=m)
+    print(f"[gpu] diagonal preconditioner {kind}: elliptic oracle_its={or8.iterations}", flush=True)
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, preconditioner=pc), m)
+    try:
+        x = torch.zeros(c.n, dtype=torch.float64, device="cuda")
+        rc, info = lib.bidomain_pcg_solve(h, dev(torch, f), x, False, 1e-8, 5000)
+        assert rc == lib.BD_OK
+        _check_solution(A, f, host(x), m, ref.x)
+        assert abs(info["iterations"] - or8.iterations) <= max(2, 0.02 * or8.iterations)
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+def test_diag_preconditioner_rejects_float32_and_serving(torch):
+    A = fem.assemble_operators(bc.make_case(8, 8, 4, seed=1))["Apar"]
+    with pytest.raises(lib.BidomainError):
+        lib.bidomain_amg_setup(A, lib.bidomain_default_opts(preconditioner=lib.BD_PC_NONE,
+                                                            vcycle_precision=lib.BD_F32))
+    with pytest.raises(lib.BidomainError):
+        lib.bidomain_serve_create(1 << 30, 1, None, lib.bidomain_default_opts(preconditioner=lib.BD_PC_NONE))
+
+
 def test_classical_hierarchy_solve(torch):
     c, ops, f = _problem("ragged")
     A, m = ops["Aell"], ops["m"]
@@ -318,10 +369,11 @@ def _long_row_matrix(n, base, long_rows, seed):
                           (np.concatenate([r, d]), np.concatenate([c, d]))), shape=(n, n))
 
 
-@pytest.mark.parametrize("n,base,long_rows", [(16384, 400, 64), (16384, 100, 3)])
-def test_long_rows_lane_group(torch, n, base, long_rows):
+@pytest.mark.parametrize("n,base,long_rows,col_bytes", [(16384, 400, 64, 2), (16384, 100, 3, 4)])
+def test_long_rows_lane_group(torch, n, base, long_rows, col_bytes):
     """Rows longer than a stream tile (coarse levels of the largest slabs reach ~12,000 entries)
-    go to the lane-group kernel: 64 lanes a row when the mean row is long, fewer otherwise;
+    go to the lane-group kernel: 64 lanes a row, with 16-bit column indices, when the mean row
+    is long (and there are at most 65,536 columns), fewer lanes and 32-bit indices otherwise;
     the product must still be exact to rounding."""
     A = _long_row_matrix(n, base, long_rows, seed=23)
     A.sort_indices()
@@ -330,7 +382,7 @@ def test_long_rows_lane_group(torch, n, base, long_rows):
         info = lib.bidomain_amg_info(h)
         print(f"[gpu] long rows n={n} base={base} long={long_rows} nnz={A.nnz} "
               f"tiles={info['tiles'][0]}", flush=True)
-        assert info["tiles"][0] == 0
+        assert info["tiles"][0] == 0 and info["col_bytes"][0] == col_bytes
         x = np.random.default_rng(6).standard_normal(n)
         out = torch.empty(n, dtype=torch.float64, device="cuda")
         lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, dev(torch, x), out)

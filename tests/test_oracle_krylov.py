@@ -187,3 +187,52 @@ def test_mixed_fcg_reaches_tolerance_c1():
     r32 = krylov.amg_fcg_mixed(A, f, h, rtol=1e-8, m=ops["m"])
     assert r32.converged and r32.rel_residual_true <= 1e-8
     assert abs(r32.iterations - r64.iterations) <= 2
+
+
+def _spd(n, seed):
+    rng = np.random.default_rng(seed)
+    Q = rng.standard_normal((n, n))
+    d = rng.uniform(0.5, 50.0, n)                    # a badly scaled diagonal
+    A = Q @ Q.T / n + np.diag(d)
+    return sp.csr_matrix(A)
+
+
+def test_diag_pcg_none_solves_and_terminates():
+    """Unpreconditioned CG reaches the exact solution (dense LU) within n + a few steps."""
+    n = 40
+    A = _spd(n, 3)
+    f = np.random.default_rng(4).standard_normal(n)
+    res = krylov.diag_pcg(A, f, "none", rtol=1e-12, maxit=200)
+    assert res.converged and res.iterations <= n + 5
+    x = sla.solve(A.toarray(), f)
+    assert np.linalg.norm(res.x - x) <= 1e-9 * np.linalg.norm(x)
+
+
+@pytest.mark.parametrize("k", [1, 3, 7, 12])
+def test_jacobi_pcg_is_cg_on_the_scaled_system(k):
+    """k steps of Jacobi-preconditioned CG on A x = f equal k steps of plain CG on
+    (D^-1/2 A D^-1/2) y = D^-1/2 f mapped back by x = D^-1/2 y (an identity of the method)."""
+    n = 30
+    A = _spd(n, 5)
+    f = np.random.default_rng(6).standard_normal(n)
+    s = 1.0 / np.sqrt(A.diagonal())
+    As = sp.diags(s) @ A @ sp.diags(s)
+    xj = krylov.diag_pcg(A, f, "jacobi", rtol=1e-300, maxit=k).x
+    ys = krylov.diag_pcg(As, s * f, "none", rtol=1e-300, maxit=k).x
+    assert np.linalg.norm(xj - s * ys) <= 1e-11 * np.linalg.norm(xj)
+
+
+def test_jacobi_on_a_scaled_identity_diagonal_is_plain_cg():
+    """With diag(A) = c I the Jacobi preconditioner is a scalar: the iterates are plain CG's."""
+    n = 25
+    rng = np.random.default_rng(7)
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T / n + 3.0 * np.eye(n)
+    A[np.diag_indices(n)] = 7.5                       # the same diagonal everywhere (still SPD)
+    A = sp.csr_matrix(A)
+    f = rng.standard_normal(n)
+    for k in (2, 5, 9):
+        a = krylov.diag_pcg(A, f, "jacobi", rtol=1e-300, maxit=k).x
+        b = krylov.diag_pcg(A, f, "none", rtol=1e-300, maxit=k).x
+        assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
+
