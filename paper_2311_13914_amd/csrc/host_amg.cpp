@@ -31,21 +31,48 @@ constexpr double kTie = 1e-12;  // relative width of a tie / threshold band
 
 // ------------------------------------------------------------------------------------------
 Csr transpose(const Csr& A) {
+  // Threads take consecutive row blocks of A (balanced by entries) and scatter them in order
+  // through per-thread column offsets, so every output row is sorted, as in a serial pass.
   Csr T;
   T.nrows = A.ncols;
   T.ncols = A.nrows;
   T.rp.assign((size_t)T.nrows + 1, 0);
-  for (int32_t c : A.ci) T.rp[c + 1]++;
-  for (int32_t i = 0; i < T.nrows; ++i) T.rp[i + 1] += T.rp[i];
   T.ci.resize(A.ci.size());
   T.v.resize(A.v.size());
-  std::vector<int32_t> next(T.rp.begin(), T.rp.end() - 1);
-  for (int32_t i = 0; i < A.nrows; ++i)  // rows in order, so each output row is sorted
-    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      const int32_t pos = next[A.ci[k]]++;
-      T.ci[pos] = i;
-      T.v[pos] = A.v[k];
+  const int64_t nnz = (int64_t)A.ci.size();
+  int nt = std::max(1, std::min(omp_get_max_threads(), (int)(nnz >> 16) + 1));
+  while (nt > 1 && (int64_t)nt * T.nrows > (int64_t(1) << 28)) --nt;  // counts stay within 1 GiB
+  std::vector<int32_t> r0(nt + 1, A.nrows);
+  for (int t = 0; t < nt; ++t)
+    r0[t] = (int32_t)(std::lower_bound(A.rp.begin(), A.rp.end(), (int32_t)(nnz * t / nt)) - A.rp.begin());
+  r0[0] = 0;
+  std::vector<int32_t> off((size_t)nt * T.nrows, 0);  // counts, then each thread's next slot
+#pragma omp parallel num_threads(nt)
+  {
+    const int t = omp_get_thread_num();
+    int32_t* c = off.data() + (size_t)t * T.nrows;
+    for (int32_t k = A.rp[r0[t]]; k < A.rp[r0[t + 1]]; ++k) c[A.ci[k]]++;
+#pragma omp barrier
+#pragma omp for schedule(static)
+    for (int32_t col = 0; col < T.nrows; ++col) {
+      int32_t sum = 0;
+      for (int u = 0; u < nt; ++u) {
+        const int32_t n_u = off[(size_t)u * T.nrows + col];
+        off[(size_t)u * T.nrows + col] = sum;
+        sum += n_u;
+      }
+      T.rp[col + 1] = sum;
     }
+#pragma omp single
+    for (int32_t col = 0; col < T.nrows; ++col) T.rp[col + 1] += T.rp[col];
+    for (int32_t i = r0[t]; i < r0[t + 1]; ++i)
+      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        const int32_t col = A.ci[k];
+        const int32_t pos = T.rp[col] + c[col]++;
+        T.ci[pos] = i;
+        T.v[pos] = A.v[k];
+      }
+  }
   return T;
 }
 
@@ -576,6 +603,14 @@ Csr rs_interpolation(const Csr& A, const Csr& S, const std::vector<uint8_t>& st)
 // every entry's mirror is found by a binary search in the mirror row; rows are independent.
 Csr symmetrize(const Csr& A) {
   Csr C = A;
+  {  // a structurally symmetric matrix (the Galerkin products): a_ji from the transpose
+    const Csr T = transpose(A);
+    if (T.rp == A.rp && T.ci == A.ci) {
+#pragma omp parallel for schedule(static, 4096)
+      for (int64_t k = 0; k < (int64_t)A.v.size(); ++k) C.v[k] = 0.5 * (A.v[k] + T.v[k]);
+      return C;
+    }
+  }
 #pragma omp parallel for schedule(dynamic, 64)
   for (int32_t i = 0; i < A.nrows; ++i)
     for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
@@ -675,6 +710,9 @@ int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::
   const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
   const auto t_start = std::chrono::steady_clock::now();
   auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
+  auto stamp = [&](int k, const char* what) {
+    if (log) std::fprintf(stderr, "[setup] level %d: %s (%.2f s)\n", k, what, elapsed());
+  };
   H.lv.clear();
   HostLevel cur;
   cur.A = A0;
@@ -704,12 +742,15 @@ int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::
       return BD_E_INVALID;
     }
     cur.lam = lambda_estimate(cur.A, cur.Dinv, o.esteig_iters, o.seed + (uint64_t)k);
+    stamp(k, "eigenvalue estimate");
     Csr P;
     std::vector<double> Bc;
     int32_t nc = 0;
     if (o.coarsening == BD_SA) {
       const Graph G = sa_strength(cur.A, d, o.threshold);
+      stamp(k, "strength graph");
       const std::vector<uint8_t> st = greedy_mis(G, n, k < o.square_graph_levels);
+      stamp(k, "independent set");
       std::vector<int32_t> agg;
       nc = sa_aggregate(G, st, agg);
       if (nc < 0) {
@@ -717,6 +758,7 @@ int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::
         return BD_E_INVALID;
       }
       P = sa_prolongator(cur.A, cur.Dinv, cur.B, agg, nc, cur.lam, o.prolong_smooths, Bc);
+      stamp(k, "aggregates and smoothed prolongator");
     } else {
       const Csr S = rs_strength(cur.A, o.threshold);
       const std::vector<uint8_t> st = rs_split(S);
@@ -742,7 +784,9 @@ int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::
     if (!done) {
       Csr AP = spgemm(cur.A, P);
       if (log) std::fprintf(stderr, "[setup] level %d: A P has %zu nonzeros (%.1f s)\n", k, AP.v.size(), elapsed());
-      Ac = symmetrize(spgemm(R, AP));
+      Csr RAP = spgemm(R, AP);
+      stamp(k, "R (A P)");
+      Ac = symmetrize(RAP);
     }
     if (log)
       std::fprintf(stderr, "[setup] level %d: %d rows, %zu nonzeros -> %d rows, %zu nonzeros (%.1f s)\n", k, n,
