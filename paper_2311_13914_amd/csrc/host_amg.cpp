@@ -206,6 +206,7 @@ Csr spgemm(const Csr& A, const Csr& B) {
 
 std::vector<double> diagonal(const Csr& A) {
   std::vector<double> d(A.nrows, 0.0);
+#pragma omp parallel for schedule(static, 4096)
   for (int32_t i = 0; i < A.nrows; ++i)
     for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
       if (A.ci[k] == i) d[i] = A.v[k];
@@ -218,18 +219,34 @@ std::string validate(const Csr& A) {
   for (int32_t i = 0; i < A.nrows; ++i)
     if (A.rp[i + 1] < A.rp[i]) return "row_ptr must be non-decreasing";
   if ((int64_t)A.rp[A.nrows] != A.nnz()) return "row_ptr[n] must equal nnz";
+  // rows checked in parallel; the message names the first bad row and its first problem
+  enum : uint8_t { OK = 0, RANGE, ORDER, NONFINITE, DIAG_SIGN, NO_DIAG };
+  std::vector<uint8_t> bad(A.nrows, OK);
+#pragma omp parallel for schedule(static, 4096)
   for (int32_t i = 0; i < A.nrows; ++i) {
     bool diag = false;
-    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      if (A.ci[k] < 0 || A.ci[k] >= A.ncols) return "column index out of range in row " + std::to_string(i);
-      if (k > A.rp[i] && A.ci[k] <= A.ci[k - 1]) return "columns must be sorted and unique in row " + std::to_string(i);
-      if (!std::isfinite(A.v[k])) return "non-finite value in row " + std::to_string(i);
-      if (A.ci[k] == i) {
+    uint8_t b = OK;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1] && b == OK; ++k) {
+      if (A.ci[k] < 0 || A.ci[k] >= A.ncols) b = RANGE;
+      else if (k > A.rp[i] && A.ci[k] <= A.ci[k - 1]) b = ORDER;
+      else if (!std::isfinite(A.v[k])) b = NONFINITE;
+      else if (A.ci[k] == i) {
         diag = true;
-        if (!(A.v[k] > 0.0)) return "diagonal must be positive in row " + std::to_string(i);
+        if (!(A.v[k] > 0.0)) b = DIAG_SIGN;
       }
     }
-    if (!diag) return "missing diagonal in row " + std::to_string(i);
+    bad[i] = b != OK ? b : (diag ? OK : NO_DIAG);
+  }
+  for (int32_t i = 0; i < A.nrows; ++i) {
+    if (bad[i] == OK) continue;
+    const std::string row = std::to_string(i);
+    switch (bad[i]) {
+      case RANGE: return "column index out of range in row " + row;
+      case ORDER: return "columns must be sorted and unique in row " + row;
+      case NONFINITE: return "non-finite value in row " + row;
+      case DIAG_SIGN: return "diagonal must be positive in row " + row;
+      default: return "missing diagonal in row " + row;
+    }
   }
   return "";
 }
@@ -363,29 +380,32 @@ Graph sa_strength(const Csr& A, const std::vector<double>& d, double theta) {
   const int32_t n = A.nrows;
   G.rp.assign(n + 1, 0);
   const double cut = theta * (1.0 - kTie);
+  auto strong = [&](int32_t i, int32_t k, double& w) {
+    const int32_t j = A.ci[k];
+    if (j == i || A.v[k] == 0.0) return false;
+    w = std::fabs(A.v[k]) / std::sqrt(d[i] * d[j]);
+    return w >= cut;
+  };
+#pragma omp parallel for schedule(static, 4096)
   for (int32_t i = 0; i < n; ++i) {
     int32_t c = 0;
-    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      const int32_t j = A.ci[k];
-      if (j == i || A.v[k] == 0.0) continue;
-      if (std::fabs(A.v[k]) / std::sqrt(d[i] * d[j]) >= cut) ++c;
-    }
-    G.rp[i + 1] = G.rp[i] + c;
+    double w;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) c += strong(i, k, w);
+    G.rp[i + 1] = c;
   }
+  for (int32_t i = 0; i < n; ++i) G.rp[i + 1] += G.rp[i];
   G.ci.resize(G.rp[n]);
   G.w.resize(G.rp[n]);
+#pragma omp parallel for schedule(static, 4096)
   for (int32_t i = 0; i < n; ++i) {
     int32_t pos = G.rp[i];
-    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      const int32_t j = A.ci[k];
-      if (j == i || A.v[k] == 0.0) continue;
-      const double w = std::fabs(A.v[k]) / std::sqrt(d[i] * d[j]);
-      if (w >= cut) {
-        G.ci[pos] = j;
+    double w;
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (strong(i, k, w)) {
+        G.ci[pos] = A.ci[k];
         G.w[pos] = w;
         ++pos;
       }
-    }
   }
   return G;
 }
@@ -491,17 +511,26 @@ Csr rs_strength(const Csr& A, double alpha) {
   const int32_t n = A.nrows;
   S.nrows = S.ncols = n;
   S.rp.assign(n + 1, 0);
+  std::vector<double> cut(n);
+#pragma omp parallel for schedule(static, 4096)
   for (int32_t i = 0; i < n; ++i) {
     double mx = 0.0;
     for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
       if (A.ci[k] != i) mx = std::max(mx, std::fabs(A.v[k]));
-    const double cut = alpha * mx * (1.0 - kTie);
+    cut[i] = alpha * mx * (1.0 - kTie);
+    int32_t c = 0;
     for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-      if (A.ci[k] != i && A.v[k] != 0.0 && std::fabs(A.v[k]) >= cut) {
-        S.ci.push_back(A.ci[k]);
-        S.v.push_back(1.0);
-      }
-    S.rp[i + 1] = (int32_t)S.ci.size();
+      c += A.ci[k] != i && A.v[k] != 0.0 && std::fabs(A.v[k]) >= cut[i];
+    S.rp[i + 1] = c;
+  }
+  for (int32_t i = 0; i < n; ++i) S.rp[i + 1] += S.rp[i];
+  S.ci.resize(S.rp[n]);
+  S.v.assign(S.rp[n], 1.0);
+#pragma omp parallel for schedule(static, 4096)
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t pos = S.rp[i];
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+      if (A.ci[k] != i && A.v[k] != 0.0 && std::fabs(A.v[k]) >= cut[i]) S.ci[pos++] = A.ci[k];
   }
   return S;
 }

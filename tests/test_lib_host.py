@@ -121,3 +121,11 @@ def test_malformed_csr_is_rejected():
         lib.bidomain_amg_build_host(neg)
     with pytest.raises(lib.BidomainError):
         lib.bidomain_amg_build_host(A, lib.bidomain_default_opts(smoother_degree=0))
+    # rows are checked in parallel; the message still names the first bad row
+    two = A.copy()
+    two.data = two.data.copy()
+    two.data[two.indptr[9] + 1] = np.nan                   # row 9: non-finite value
+    two.data[two.indptr[4]:two.indptr[5]][two.indices[two.indptr[4]:two.indptr[5]] == 4] = -2.0  # row 4
+    with pytest.raises(lib.BidomainError) as e:
+        lib.bidomain_amg_build_host(two)
+    assert "diagonal must be positive in row 4" in str(e.value)
