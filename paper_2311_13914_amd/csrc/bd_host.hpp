@@ -55,7 +55,7 @@ struct HostHierarchy {
 using GalerkinOffload = std::function<bool(const Csr& A, const Csr& P, int64_t sparse_flops, Csr& Ac)>;
 
 // Setup phase: returns BD_OK or a BD_E_* code with a message in err.
-int build_hierarchy(const Csr& A, const bd_amg_opts& o, HostHierarchy& H, std::string& err,
+int build_hierarchy(Csr A, const bd_amg_opts& o, HostHierarchy& H, std::string& err,
                     const GalerkinOffload* offload = nullptr);
 
 // Largest Ritz value of D^{-1} A after `iters` Jacobi-CG steps from a SplitMix64 vector.

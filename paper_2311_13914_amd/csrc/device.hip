@@ -209,6 +209,22 @@ bool compact_columns(const Csr& H, const std::vector<int>& blk, std::vector<uint
   return true;
 }
 
+// Host values in the device precision: the vector itself for float64, a copy converted in
+// parallel for float32.
+template <typename T>
+const std::vector<double>& as_type(const std::vector<double>& v,
+                                   typename std::enable_if<std::is_same<T, double>::value>::type* = nullptr) {
+  return v;
+}
+template <typename T>
+std::vector<float> as_type(const std::vector<double>& v,
+                           typename std::enable_if<std::is_same<T, float>::value>::type* = nullptr) {
+  std::vector<float> f(v.size());
+#pragma omp parallel for schedule(static, 65536)
+  for (int64_t i = 0; i < (int64_t)v.size(); ++i) f[i] = (float)v[i];
+  return f;
+}
+
 template <typename U>
 U* upload_padded(Arena& ar, const U* src, size_t count, hipStream_t st) {
   U* d = ar.alloc<U>(count + kStreamPad);  // padded for 4-entry vector loads
@@ -410,11 +426,11 @@ DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, const StreamPlan* pla
   }
   if (M.nd) {
     M.dv = ar.alloc<T>(plan->dval.size());
-    const std::vector<T> dv(plan->dval.begin(), plan->dval.end());
+    const auto& dv = as_type<T>(plan->dval);
     HIPCHK(hipMemcpyAsync(M.dv, dv.data(), dv.size() * sizeof(T), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
   } else {
-    M.v = upload_padded<T>(ar, std::vector<T>(H.v.begin(), H.v.end()).data(), H.v.size(), st);
+    M.v = upload_padded<T>(ar, as_type<T>(H.v).data(), H.v.size(), st);
   }
   return M;
 }
@@ -1278,9 +1294,13 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   const GalerkinOffload offload = [&](const Csr& Ak, const Csr& Pk, int64_t flops, Csr& Ac) {
     return dense_galerkin(Ak, Pk, flops, o.galerkin_device, log, Ac);
   };
-  const int rc = build_hierarchy(H, o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr);
+  const auto t0 = std::chrono::steady_clock::now();
+  const int rc = build_hierarchy(std::move(H), o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr);
   if (rc != BD_OK) throw Failure{rc, err};
   if (use_device) plan_hierarchy(h->H, o.diag_form != 0);  // launch plans, on this (possibly worker) thread
+  if (log)
+    std::fprintf(stderr, "[setup] hierarchy and launch plans: %.2f s\n",
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
   h->M = (int)h->H.lv.size() - 1;
   h->host_only = true;
   if (!host_only) device_upload(h.get(), weights, false, st);
@@ -1306,15 +1326,19 @@ std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell
   std::unique_ptr<SimHost> H(new SimHost());
   H->s = s;
   const int n = (int)slab_nodes(s);
+  const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
   Csr Ae;
   assemble_slab_stiffness(s, s.sig_il, s.sig_it, H->Ai);
   assemble_slab_stiffness(s, s.sig_el, s.sig_et, Ae);
   slab_lumped_mass(s, H->m);
   Csr Aell = H->Ai, Apar = H->Ai;
-  for (size_t k = 0; k < Aell.v.size(); ++k) Aell.v[k] += Ae.v[k];
-  for (int32_t i = 0; i < Apar.nrows; ++i)
-    for (int32_t k = Apar.rp[i]; k < Apar.rp[i + 1]; ++k)
+#pragma omp parallel for schedule(static, 4096)
+  for (int32_t i = 0; i < n; ++i)
+    for (int32_t k = Aell.rp[i]; k < Aell.rp[i + 1]; ++k) {
+      Aell.v[k] += Ae.v[k];
       if (Apar.ci[k] == i) Apar.v[k] += s.cm / s.dt * H->m[i];
+    }
   bd_amg_opts oe, op;
   bidomain_default_opts(&oe);
   bidomain_default_opts(&op);
@@ -1323,6 +1347,9 @@ std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell
   if (par) op = *par;
   oe.nullspace = BD_NULL_CONSTANT;
   op.nullspace = BD_NULL_NONE;
+  if (log)
+    std::fprintf(stderr, "[setup] slab operators assembled: %.2f s\n",
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
   bd_csr ce{n, Aell.nnz(), Aell.rp.data(), Aell.ci.data(), Aell.v.data()};
   bd_csr cp{n, Apar.nnz(), Apar.rp.data(), Apar.ci.data(), Apar.v.data()};
   setup_impl(&ce, &oe, nullptr, nullptr, &H->hell, true);

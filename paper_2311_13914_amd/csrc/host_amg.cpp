@@ -734,7 +734,7 @@ int coarse_operator(const HostLevel& L, bool nullspace, std::vector<double>& G, 
 // ------------------------------------------------------------------------------------------
 // With BIDOMAIN_SETUP_LOG set in the environment, one line per level goes to stderr as the
 // setup proceeds (large hierarchies take minutes on the host).
-int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::string& err,
+int build_hierarchy(Csr A0, const bd_amg_opts& o, HostHierarchy& H, std::string& err,
                     const GalerkinOffload* offload) {
   const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
   const auto t_start = std::chrono::steady_clock::now();
@@ -744,8 +744,8 @@ int build_hierarchy(const Csr& A0, const bd_amg_opts& o, HostHierarchy& H, std::
   };
   H.lv.clear();
   HostLevel cur;
-  cur.A = A0;
   cur.B.assign(A0.nrows, 1.0);
+  cur.A = std::move(A0);
   for (int k = 0;; ++k) {
     const std::vector<double> d = diagonal(cur.A);
     cur.Dinv.resize(d.size());
