@@ -103,3 +103,27 @@ def test_step_is_bitwise_reproducible(c2):
             lib.bidomain_sim_destroy(sim)
     assert outs[0][1:] == outs[1][1:]
     assert np.array_equal(outs[0][0], outs[1][0])
+
+
+def test_c5_fine_product_sampled():
+    """The fine elliptic product at the largest single-GPU size bench.py runs (384 x 384 x 96
+    elements, 14.4 M rows, 384 M nonzeros; the diagonal form, in its launch configuration) on
+    sampled rows -- both ends and 20,000 random ones -- against the library's host assembly, which
+    the host tests check against the oracle's at small sizes."""
+    import torch
+    case = bc.config_case("C5")
+    print(f"[gpu] C5 n={case.n}: host assembly", flush=True)
+    rp, ci, v, _ = lib.bidomain_slab_assemble(case, lib.BD_MAT_AELL)
+    h = lib.bidomain_amg_setup((rp, ci, v), lib.bidomain_default_opts(nullspace=1, max_levels=1))
+    try:
+        assert lib.bidomain_amg_info(h)["diags"][0] == 14
+        rng = np.random.default_rng(5)
+        x = rng.uniform(-1, 1, case.n)
+        y = torch.empty(case.n, dtype=torch.float64, device="cuda")
+        lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, _dev(x), y)
+        ys = y.cpu().numpy()
+        rows = np.concatenate([[0, 1, case.n - 2, case.n - 1], rng.integers(0, case.n, 20000)])
+        ref = np.array([v[rp[i]:rp[i + 1]] @ x[ci[rp[i]:rp[i + 1]]] for i in rows])
+        assert np.max(np.abs(ys[rows] - ref)) <= 1e-13 * np.max(np.abs(ref))
+    finally:
+        lib.bidomain_amg_destroy(h)
