@@ -153,3 +153,101 @@ def test_coarsening_stops_on_weakly_coupled_operator():
     # the mass term dominates on this coarse mesh: no edge reaches theta, no coarsening, and the
     # oversized coarsest level is relaxed by its smoother rather than factorised
     assert h.nlevels == 1 and h.coarse_factor is None and np.isfinite(h.levels[0].lam)
+
+
+def test_smoothed_prolongator_hand_derived_neumann_path():
+    """P = (I - omega D^-1 A) P_t with omega = 4 / (3 lambda), written out by hand.
+
+    Path of four nodes with Neumann ends, A = [[1,-1,0,0],[-1,2,-1,0],[0,-1,2,-1],[0,0,-1,1]],
+    D = diag(1, 2, 2, 1); aggregates {0, 1}, {2, 3}, s = 2^-1/2.  A P_t = s [[0,0],[1,-1],[-1,1],[0,0]],
+    D^-1 A P_t = s [[0,0],[1/2,-1/2],[-1/2,1/2],[0,0]].  D^-1 A has eigenvalues 1 - cos(k pi/3),
+    so lambda = 2 and omega = 2/3: P = s [[1,0],[2/3,1/3],[1/3,2/3],[0,1]].
+    """
+    A = _path_laplacian(4)
+    s = 2.0 ** -0.5
+    Pt = sp.csr_matrix(np.array([[s, 0], [s, 0], [0, s], [0, s]]))
+    P = amg.smooth_prolongator(A, 1.0 / A.diagonal(), Pt, 2.0, 1).toarray()
+    expect = s * np.array([[1, 0], [2 / 3, 1 / 3], [1 / 3, 2 / 3], [0, 1]])
+    np.testing.assert_allclose(P, expect, rtol=0, atol=1e-15)
+
+
+def test_smoothed_prolongator_in_setup_dirichlet_path():
+    """The same product inside setup(), with lambda from the eigenvalue estimate.
+
+    A = tridiag(-1, 2, -1) on four nodes (SPD), D = 2 I.  D^-1 A has eigenvalues 1 - cos(k pi/5),
+    k = 1..4, so after a complete Krylov space lambda = 1 + cos(pi/5) = (5 + 5^1/2)/4 and
+    omega = 4/(3 lambda) = 4 (5 - 5^1/2)/15.  All couplings have weight 1/2; node 1 ties between
+    roots 0 and 2 and joins 0, so the aggregates are {0, 1}, {2, 3}.  D^-1 A P_t =
+    (s/2) [[1,0],[1,-1],[-1,1],[0,1]], hence P = s [[1-w,0],[1-w,w],[w,1-w],[0,1-w]], w = omega/2.
+    """
+    A = sp.csr_matrix(np.array([[2., -1, 0, 0], [-1, 2, -1, 0], [0, -1, 2, -1], [0, 0, -1, 2]]))
+    h = amg.setup(A, amg.AMGOptions(coarse_eq_limit=2, square_graph_levels=0))
+    lv = h.levels[0]
+    assert lv.agg.tolist() == [0, 0, 1, 1]
+    assert lv.lam == pytest.approx((5 + 5 ** 0.5) / 4, rel=1e-14)
+    w = 2 * (5 - 5 ** 0.5) / 15
+    s = 2.0 ** -0.5
+    expect = s * np.array([[1 - w, 0], [1 - w, w], [w, 1 - w], [0, 1 - w]])
+    np.testing.assert_allclose(lv.P.toarray(), expect, rtol=0, atol=1e-14)
+
+
+def _rs_star():
+    """Centre 0 (diagonal 10) coupled to 1 (-4), 2 (+3), 3 (-2), 4 (-1), 5 (+1); each leaf is
+    coupled to the centre only."""
+    off = {1: -4.0, 2: 3.0, 3: -2.0, 4: -1.0, 5: 1.0}
+    A = np.zeros((6, 6))
+    A[0, 0] = 10.0
+    for j, a in off.items():
+        A[0, j] = A[j, 0] = a
+        A[j, j] = 5.0
+    return sp.csr_matrix(A)
+
+
+def test_rs_strength_eq10_cuts_and_keeps_positive_couplings():
+    """Eq. (10) with alpha = 0.5: row 0 has max |a_0k| = 4, so |a| >= 2 is strong: 1 (-4), 2 (+3),
+    3 (-2) strong; 4 (-1) and 5 (+1) weak.  A leaf's only coupling is its own maximum."""
+    S = amg.rs_strength(_rs_star(), 0.5)
+    strong = {i: S.indices[S.indptr[i]:S.indptr[i + 1]].tolist() for i in range(6)}
+    assert strong == {0: [1, 2, 3], 1: [0], 2: [0], 3: [0], 4: [0], 5: [0]}
+    # a smaller alpha keeps the weak couplings too; a larger one cuts 3 and then 2
+    assert amg.rs_strength(_rs_star(), 0.25).indices[:5].tolist() == [1, 2, 3, 4, 5]
+    row0 = lambda al: amg.rs_strength(_rs_star(), al)[0].indices.tolist()
+    assert row0(0.6) == [1, 2] and row0(0.8) == [1]
+
+
+def test_rs_direct_interpolation_both_sign_classes():
+    """F point 0 of the star with C points {1, 2}: P_0 = C cap S_0 = {1, 2}.
+    Sums over all neighbours: negative -4 - 2 - 1 = -7, positive 3 + 1 = 4; over P_0: -4 and 3.
+    alpha_0 = 7/4, beta_0 = 4/3, abar = a_00 = 10 (both classes interpolate).
+    w_01 = -(7/4)(-4)/10 = 0.7, w_02 = -(4/3)(3)/10 = -0.4."""
+    A = _rs_star()
+    S = amg.rs_strength(A, 0.5)
+    cpts = np.array([0, 1, 1, 0, 0, 0], dtype=np.int8)
+    P = amg.rs_direct_interpolation(A, S, cpts).toarray()
+    expect = np.zeros((6, 2))
+    expect[0] = [0.7, -0.4]
+    expect[1, 0] = expect[2, 1] = 1.0           # C points inject; leaves 3-5 have no strong C point
+    np.testing.assert_allclose(P, expect, rtol=0, atol=1e-15)
+
+
+def test_rs_direct_interpolation_lumps_a_class_without_interpolatory_member():
+    """F point 0 with a_00 = 6, a_01 = -3 (C), a_02 = +2 (F, strong).  No positive coupling
+    interpolates, so it is lumped: abar = 6 + 2 = 8; alpha_0 = -3/-3 = 1; w_01 = 3/8."""
+    A = sp.csr_matrix(np.array([[6., -3, 2], [-3, 4, 0], [2, 0, 4]]))
+    S = amg.rs_strength(A, 0.5)
+    assert S[0].indices.tolist() == [1, 2]
+    P = amg.rs_direct_interpolation(A, S, np.array([0, 1, 0], dtype=np.int8)).toarray()
+    np.testing.assert_allclose(P, [[3 / 8], [1.0], [0.0]], rtol=0, atol=1e-15)
+
+
+def test_sa_strength_uses_absolute_scaled_coupling():
+    """w_ij = |a_ij| / sqrt(a_ii a_jj) (Sec. 4, with the absolute value of reading R8):
+    star of _rs_star with diagonals 10 and 5: w = 4/sqrt(50) = 0.566, 3/sqrt(50) = 0.424,
+    0.283, 0.141, 0.141.  theta = 0.2 keeps 1, 2, 3 (positive coupling 2 included) and cuts 4, 5;
+    theta = 0.3 cuts 3 as well."""
+    A = _rs_star()
+    G = amg.sa_strength(A, 0.2)
+    assert G[0].indices.tolist() == [1, 2, 3]
+    np.testing.assert_allclose(G[0].data, np.array([4, 3, 2]) / 50 ** 0.5, rtol=1e-15)
+    assert G[2].indices.tolist() == [0]         # symmetric: the positive edge is kept both ways
+    assert amg.sa_strength(A, 0.3)[0].indices.tolist() == [1, 2]

@@ -236,3 +236,96 @@ def test_jacobi_on_a_scaled_identity_diagonal_is_plain_cg():
         b = krylov.diag_pcg(A, f, "none", rtol=1e-300, maxit=k).x
         assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(b)
 
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3])
+def test_jacobi_error_factor_per_eigenpair(degree):
+    """Damped Jacobi with omega = 4/(3 lambda_hat) from x0 = 0: for an eigenpair (lam, y) of
+    D^-1 A and f = A y, each sweep multiplies the error by (1 - omega lam), so after d sweeps
+    y - x = (1 - omega lam)^d y."""
+    rng = np.random.default_rng(8)
+    Q = rng.standard_normal((10, 10))
+    A = Q @ Q.T + 3 * np.eye(10)
+    lams, Y = sla.eigh(A, np.diag(np.diag(A)))
+    lamhat = lams[-1] * 1.1
+    omega = 4.0 / (3.0 * lamhat)
+    As, Dinv = sp.csr_matrix(A), 1.0 / np.diag(A)
+    for lam, y in zip(lams, Y.T):
+        x = krylov.jacobi(As, Dinv, A @ y, None, lamhat, degree)
+        np.testing.assert_allclose(y - x, (1 - omega * lam) ** degree * y, rtol=0,
+                                   atol=1e-12 * np.abs(y).max())
+
+
+def test_smooth_dispatches_jacobi_with_degree_sweeps():
+    c, ops, A, h = _small_hierarchy(3, 3, 2, smoother="jacobi", degree=3, coarse_eq_limit=4)
+    lv = h.levels[0]
+    f = bc.random_vector(A.shape[0], 2)
+    omega = 4.0 / (3.0 * lv.lam)
+    x = np.zeros_like(f)
+    for _ in range(3):
+        x = x + omega * lv.Dinv * (f - lv.A @ x)
+    np.testing.assert_allclose(krylov.smooth(h, 0, f, None), x, rtol=0, atol=1e-14 * np.abs(x).max())
+
+
+class _Recorder:
+    """Wraps a matrix and records every vector it multiplies (the search directions p_k)."""
+
+    def __init__(self, A):
+        self.A, self.seen = A, []
+
+    def __matmul__(self, v):
+        self.seen.append(np.array(v, dtype=np.float64))
+        return self.A @ v
+
+
+def _varying_preconditioner(n, seed):
+    """z = C_k r with a different random positive diagonal C_k at every call."""
+    rng = np.random.default_rng(seed)
+    return lambda r: rng.uniform(0.2, 5.0, n).astype(r.dtype) * r
+
+
+def test_fcg_local_a_orthogonality_with_varying_preconditioner():
+    """Flexible CG, FCG(1) (Notay 2000): beta_k = z_{k+1}^T (r_{k+1} - r_k) / (z_k^T r_k) makes
+    consecutive directions A-orthogonal, p_{k+1}^T A p_k = 0, for any preconditioner, because
+    A p_k = (r_k - r_{k+1}) / alpha_k and alpha_k = rho_k / p_k^T A p_k.  Plain CG's
+    beta = z_{k+1}^T r_{k+1} / rho_k leaves p_{k+1}^T A p_k = (p_k^T A p_k) z_{k+1}^T r_k / rho_k,
+    which is nonzero once the preconditioner changes between iterations."""
+    n = 30
+    A = _spd(n, 11)
+    f = np.random.default_rng(12).standard_normal(n)
+
+    def directions(solver):
+        rec = _Recorder(A)
+        solver(rec)
+        return rec.seen[1:-1]                # drop the initial and final residual products
+
+    ps = directions(lambda M: krylov.fcg(M, f, _varying_preconditioner(n, 1), rtol=1e-300,
+                                         maxit=8, lowp=np.float64))
+    assert len(ps) == 8
+    Ad = A.toarray()
+    for p0, p1 in zip(ps, ps[1:]):
+        assert abs(p1 @ Ad @ p0) <= 1e-12 * np.linalg.norm(p1) * np.linalg.norm(Ad @ p0)
+    # the same check separates plain CG's beta under the same varying preconditioner
+    qs = directions(lambda M: krylov.pcg(M, f, _varying_preconditioner(n, 1), rtol=1e-300, maxit=8))
+    worst = max(abs(p1 @ Ad @ p0) / (np.linalg.norm(p1) * np.linalg.norm(Ad @ p0))
+                for p0, p1 in zip(qs, qs[1:]))
+    assert worst > 1e-3
+
+
+def test_fcg_two_steps_by_hand():
+    """Two FCG(1) steps on a 3x3 system written out: r0 = f, z0 = C0 r0, p0 = z0,
+    alpha0 = z0.r0 / p0.A p0, r1 = r0 - alpha0 A p0, z1 = C1 r1, beta0 = z1.(r1 - r0) / z0.r0,
+    p1 = z1 + beta0 p0, alpha1 = z1.r1 / p1.A p1, x2 = alpha0 p0 + alpha1 p1."""
+    A = np.array([[4., 1, 0], [1, 3, 1], [0, 1, 2]])
+    f = np.array([1., 2, 3])
+    C = [np.array([1.0, 0.5, 2.0]), np.array([0.3, 1.5, 0.7]), np.ones(3)]
+    calls = iter(C)                          # the third call follows the last step, unused
+    res = krylov.fcg(sp.csr_matrix(A), f, lambda r: next(calls) * r, rtol=1e-300, maxit=2,
+                     lowp=np.float64)
+    r0 = f.copy(); z0 = C[0] * r0; p0 = z0.copy()
+    a0 = (z0 @ r0) / (p0 @ A @ p0)
+    r1 = r0 - a0 * (A @ p0); z1 = C[1] * r1
+    b0 = (z1 @ (r1 - r0)) / (z0 @ r0)
+    p1 = z1 + b0 * p0
+    a1 = (z1 @ r1) / (p1 @ A @ p1)
+    np.testing.assert_allclose(res.x, a0 * p0 + a1 * p1, rtol=1e-14)
