@@ -143,6 +143,9 @@ typedef struct {
    * host CSR).  A structurally missing entry reads as zero times x, so a non-finite x value
    * next to a boundary row can turn that row's result into NaN. */
   int32_t diags[BD_MAX_LEVELS];
+  /* The hierarchy's V-cycle precision (BD_F64 | BD_F32): the element type of the vectors
+   * bidomain_amg_apply reads and writes. */
+  int32_t vcycle_precision;
 } bd_amg_stats;
 
 /*
@@ -290,6 +293,7 @@ typedef struct {
   int64_t rounds, solves;
   double host_enqueue_s, host_wait_s, host_exit_s;  /* host time: enqueuing rounds, waiting on
                                                      the GPU, finishing solves */
+  int64_t max_batched;      /* most running solves advanced together by one round's launches */
 } bd_serve_stats;
 
 /* budget_bytes: HBM the server may hold for cases; max_slots: cases admitted at once. */

@@ -58,7 +58,8 @@ class bd_amg_stats(C.Structure):
                 ("coarse_mode", C.c_int32), ("operator_complexity", C.c_double), ("grid_complexity", C.c_double),
                 ("device_bytes", C.c_int64), ("col_bytes", C.c_int32 * BD_MAX_LEVELS),
                 ("tiles", C.c_int64 * BD_MAX_LEVELS), ("col_bytes_p", C.c_int32 * BD_MAX_LEVELS),
-                ("col_bytes_r", C.c_int32 * BD_MAX_LEVELS), ("diags", C.c_int32 * BD_MAX_LEVELS)]
+                ("col_bytes_r", C.c_int32 * BD_MAX_LEVELS), ("diags", C.c_int32 * BD_MAX_LEVELS),
+                ("vcycle_precision", C.c_int32)]
 
 
 class bd_slab(C.Structure):
@@ -83,7 +84,8 @@ class bd_case_result(C.Structure):
 class bd_serve_stats(C.Structure):
     _fields_ = [("queued", C.c_int32), ("setting_up", C.c_int32), ("running", C.c_int32), ("done", C.c_int32),
                 ("bytes_in_use", C.c_int64), ("budget", C.c_int64), ("rounds", C.c_int64), ("solves", C.c_int64),
-                ("host_enqueue_s", C.c_double), ("host_wait_s", C.c_double), ("host_exit_s", C.c_double)]
+                ("host_enqueue_s", C.c_double), ("host_wait_s", C.c_double), ("host_exit_s", C.c_double),
+                ("max_batched", C.c_int64)]
 
 
 _vp = C.c_void_p
@@ -253,7 +255,7 @@ def bidomain_amg_info(h) -> dict:
                 lam=list(s.lambda_[:L]), coarse_mode=s.coarse_mode, operator_complexity=s.operator_complexity,
                 grid_complexity=s.grid_complexity, device_bytes=s.device_bytes, col_bytes=list(s.col_bytes[:L]),
                 tiles=list(s.tiles[:L]), col_bytes_p=list(s.col_bytes_p[:L]), col_bytes_r=list(s.col_bytes_r[:L]),
-                diags=list(s.diags[:L]))
+                diags=list(s.diags[:L]), vcycle_precision=s.vcycle_precision)
 
 
 def bidomain_amg_destroy(h):
@@ -292,8 +294,11 @@ def bidomain_amg_apply(h, op: int, level: int, inp, out, stream=None):
     li, lo = sizes[op]
     if max(li, lo) >= nl:
         raise ValueError("the coarsest level has no transfer operators")
-    if inp.numel() != info["n"][li] or out.numel() != info["n"][lo] or inp.dtype != out.dtype:
-        raise ValueError("vector sizes or dtypes do not match the level")
+    want = torch.float32 if info["vcycle_precision"] == BD_F32 else torch.float64
+    if inp.dtype != want or out.dtype != want:
+        raise ValueError(f"in and out must be {want} tensors: the hierarchy's V-cycle precision")
+    if inp.numel() != info["n"][li] or out.numel() != info["n"][lo]:
+        raise ValueError("vector sizes do not match the level")
     _check(load().bidomain_amg_apply(_vp(h), op, level, _vp(inp.data_ptr()), _vp(out.data_ptr()), _stream(stream)),
            "bidomain_amg_apply")
 

@@ -956,14 +956,20 @@ int pcg(bd_amg* h, const double* b, double* x, int guess, double rtol, int maxit
     }
     HIPCHK(hipStreamSynchronize(st));
     if (prof) {
-      for (auto& e : pev) {
+      // launch j computes q for iteration j + 1; the launches enqueued after the converging
+      // iteration found the done flag set and returned at once, so only the first
+      // `iterations` launches did the product
+      HIPCHK(hipMemcpyAsync(flags, sv.fl, sizeof(flags), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      const size_t worked = std::min<size_t>(pev.size(), (size_t)std::max(0, flags[F_ITERS]));
+      for (size_t j = 0; j < pev.size(); ++j) {
         float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e.first, e.second));
-        (void)hipEventDestroy(e.first);
-        (void)hipEventDestroy(e.second);
-        g_prof.total_ms += ms;
+        HIPCHK(hipEventElapsedTime(&ms, pev[j].first, pev[j].second));
+        (void)hipEventDestroy(pev[j].first);
+        (void)hipEventDestroy(pev[j].second);
+        if (j < worked) g_prof.total_ms += ms;
       }
-      g_prof.launches += (int64_t)pev.size();
+      g_prof.launches += (int64_t)worked;
     }
   } else if (flags[F_STATUS] == 0) {
     // b^ = 0 gives x = 0; a converged initial guess is kept
@@ -1254,9 +1260,10 @@ bool dense_galerkin(const Csr& A, const Csr& P, int64_t sparse_flops, int mode, 
 }
 
 // host_only: build the hierarchy but do not upload it; use_device: the setup may run its
-// Galerkin products on the device (option galerkin_device).
+// Galerkin products on the device (option galerkin_device); plan: build the launch plans (for a
+// hierarchy that will be uploaded).
 int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, hipStream_t st, bd_amg** out,
-               bool host_only = false, bool use_device = true) {
+               bool host_only = false, bool use_device = true, bool plan = true) {
   if (!A || !out) throw Failure{BD_E_INVALID, "null argument"};
   bd_amg_opts o;
   bidomain_default_opts(&o);
@@ -1297,7 +1304,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   const auto t0 = std::chrono::steady_clock::now();
   const int rc = build_hierarchy(std::move(H), o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr);
   if (rc != BD_OK) throw Failure{rc, err};
-  if (use_device) plan_hierarchy(h->H, o.diag_form != 0);  // launch plans, on this (possibly worker) thread
+  if (plan) plan_hierarchy(h->H, o.diag_form != 0);  // launch plans, on this (possibly worker) thread
   if (log)
     std::fprintf(stderr, "[setup] hierarchy and launch plans: %.2f s\n",
                  std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
@@ -1308,8 +1315,11 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   return BD_OK;
 }
 
-// Host half of a simulation: assembled operators and host-built hierarchies (no device work,
-// so it may run on a worker thread while the GPU serves other cases).
+// Host half of a simulation: assembled operators and host-built hierarchies.  With
+// device_galerkin false the setup does no device work at all, so it may run on a worker thread
+// while the GPU serves other cases without taking device memory outside the serving budget;
+// with it true the filled levels' Galerkin products may run on the device in transient buffers
+// of up to half the free device memory (option galerkin_device).
 struct SimHost {
   bd_slab s{};
   Csr Ai;
@@ -1322,7 +1332,8 @@ struct SimHost {
   }
 };
 
-std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell, const bd_amg_opts* par) {
+std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell, const bd_amg_opts* par,
+                                        bool device_galerkin) {
   std::unique_ptr<SimHost> H(new SimHost());
   H->s = s;
   const int n = (int)slab_nodes(s);
@@ -1352,8 +1363,8 @@ std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell
                  std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
   bd_csr ce{n, Aell.nnz(), Aell.rp.data(), Aell.ci.data(), Aell.v.data()};
   bd_csr cp{n, Apar.nnz(), Apar.rp.data(), Apar.ci.data(), Apar.v.data()};
-  setup_impl(&ce, &oe, nullptr, nullptr, &H->hell, true);
-  setup_impl(&cp, &op, nullptr, nullptr, &H->hpar, true);
+  setup_impl(&ce, &oe, nullptr, nullptr, &H->hell, true, device_galerkin);
+  setup_impl(&cp, &op, nullptr, nullptr, &H->hpar, true, device_galerkin);
   return H;
 }
 
@@ -1425,7 +1436,7 @@ int bidomain_amg_setup(const bd_csr* A, const bd_amg_opts* opts, const double* n
 }
 
 int bidomain_amg_build_host(const bd_csr* A, const bd_amg_opts* opts, bd_amg** out) {
-  return guarded([&] { return setup_impl(A, opts, nullptr, nullptr, out, true, false); });
+  return guarded([&] { return setup_impl(A, opts, nullptr, nullptr, out, true, false, false); });
 }
 
 int bidomain_pcg_solve(bd_amg* h, const double* b_dev, double* x_dev, int x_is_guess, double rtol, int maxit,
@@ -1470,6 +1481,7 @@ int bidomain_amg_info(const bd_amg* h, bd_amg_stats* s) {
       }
     }
     s->coarse_mode = h->H.coarse_mode;
+    s->vcycle_precision = h->o.vcycle_precision;
     s->operator_complexity = nnz / (double)L[0].A.nnz();
     s->grid_complexity = nn / (double)L[0].A.nrows;
     s->device_bytes = h->ar.bytes;
@@ -1627,7 +1639,7 @@ int bidomain_sim_create(const bd_slab* s, const bd_amg_opts* ell, const bd_amg_o
     check_slab(s);
     if (!v0_dev || !out || !(rtol > 0)) throw Failure{BD_E_INVALID, "invalid simulation arguments"};
     hipStream_t st = (hipStream_t)stream;
-    std::unique_ptr<SimHost> H = build_sim_host(*s, ell, par);
+    std::unique_ptr<SimHost> H = build_sim_host(*s, ell, par, true);
     std::unique_ptr<bd_sim> S = upload_sim(*H, v0_dev, true, w0_dev, true, st);
     // u_e^0 from v^0 (eq. (6))
     launch_neg_spmv(S.get(), S->v, S->fell, st);
@@ -2130,8 +2142,11 @@ struct bd_server {
   std::deque<ServedCase*> unreported;
   Staging stg;
   std::vector<double> solve_lat;
-  int64_t rounds = 0, solves = 0;
+  int64_t rounds = 0, solves = 0, max_batched = 0;
   double t_enqueue = 0.0, t_wait = 0.0, t_exit = 0.0;  // host seconds spent per round phase
+  // test hook (environment BIDOMAIN_SERVE_FAIL_UPLOAD=<ticket>): the upload of that case
+  // reports an allocation failure after its device memory was taken, exercising the cleanup
+  uint64_t fail_upload_ticket = 0;
   uint64_t next_ticket = 1;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
@@ -2187,7 +2202,7 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
     const int nthr = setup_threads();
     c->fut = std::async(std::launch::async, [slab, oe, op, nthr] {
       omp_set_num_threads(nthr);
-      return build_sim_host(slab, &oe, &op);
+      return build_sim_host(slab, &oe, &op, false);  // no device memory outside the budget
     });
     S->live.push_back(c);
   }
@@ -2211,14 +2226,30 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
       S->unreported.push_back(c);
       continue;
     }
-    c->sim = upload_sim(*H, c->v0.data(), false, nullptr, false, st);
+    try {
+      c->sim = upload_sim(*H, c->v0.data(), false, nullptr, false, st);
+      if (S->fail_upload_ticket == c->ticket)
+        throw Failure{BD_E_NOMEM, "upload failure injected for ticket " + std::to_string(c->ticket)};
+      launch_neg_spmv(c->sim.get(), c->sim->v, c->sim->fell, st);
+      c->stage = 0;
+      start_solve(S, c, c->sim->hell, c->sim->fell, c->sim->ue, 0);
+    } catch (const Failure& e) {
+      // out of device memory (or a HIP error) while bringing the case onto the device: retire
+      // it with that status and give back its slot and budget, as for a failed host setup
+      c->status = e.code;
+      (void)hipStreamSynchronize(st);
+      c->sim.reset();
+      S->used -= c->est;
+      S->admitted--;
+      c->state = 3;
+      c->t_done = S->now();
+      S->unreported.push_back(c);
+      continue;
+    }
     c->bytes = sim_device_bytes(c->sim.get());
     S->used += c->bytes - c->est;
     c->state = 2;
     c->t_ready = S->now();
-    c->stage = 0;
-    launch_neg_spmv(c->sim.get(), c->sim->v, c->sim->fell, st);
-    start_solve(S, c, c->sim->hell, c->sim->fell, c->sim->ue, 0);
   }
   std::vector<BInst*> act;
   std::vector<ServedCase*> act_cases;
@@ -2228,6 +2259,7 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
       act_cases.push_back(c);
     }
   if (!act.empty()) {
+    S->max_batched = std::max<int64_t>(S->max_batched, (int64_t)act.size());
     S->stg.used = 0;
     const auto ta = std::chrono::steady_clock::now();
     if (S->mixed) batched_round<float>(act, st, S->stg);
@@ -2346,6 +2378,7 @@ int bidomain_serve_create(int64_t budget_bytes, int32_t max_slots, const bd_amg_
     S->rtol = rtol;
     S->st = (hipStream_t)stream;
     S->stg.init(size_t(16) << 20);
+    if (const char* f = std::getenv("BIDOMAIN_SERVE_FAIL_UPLOAD")) S->fail_upload_ticket = std::strtoull(f, nullptr, 10);
     *out = S.release();
     return BD_OK;
   });
@@ -2422,6 +2455,7 @@ int bidomain_serve_stats(const bd_server* S, bd_serve_stats* st) {
     st->host_enqueue_s = S->t_enqueue;
     st->host_wait_s = S->t_wait;
     st->host_exit_s = S->t_exit;
+    st->max_batched = S->max_batched;
     return BD_OK;
   });
 }

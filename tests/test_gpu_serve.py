@@ -20,6 +20,9 @@ def _mix():
             bc.make_case(16, 16, 8, seed=12), bc.make_case(20, 16, 10, seed=13)]
 
 
+_LAST_STATS = {}   # bidomain_serve_stats of the last _serve call, read after all cases finished
+
+
 def _serve(cases, nsteps, budget=1 << 34, slots=8, prec=None, timeout=150, budget_fn=None):
     prec = lib.BD_F32 if prec is None else prec
     oe = lib.bidomain_default_opts(vcycle_precision=prec)
@@ -42,8 +45,11 @@ def _serve(cases, nsteps, budget=1 << 34, slots=8, prec=None, timeout=150, budge
             peak_running = max(peak_running, st["running"] + st["setting_up"])
             peak_bytes = max(peak_bytes, st["bytes_in_use"])
             assert time.time() < t_end, "serving did not finish"
-        states = {t: lib.bidomain_serve_fetch(srv, t, c.n) for t, c in zip(tickets, cases)}
+        states = {t: lib.bidomain_serve_fetch(srv, t, c.n) for t, c in zip(tickets, cases)
+                  if done[t]["status"] == lib.BD_OK}
         lat = lib.bidomain_serve_solve_latencies(srv)
+        _LAST_STATS.clear()
+        _LAST_STATS.update(lib.bidomain_serve_stats(srv))
         return tickets, done, states, peak_running, peak_bytes, lat
     finally:
         lib.bidomain_serve_destroy(srv)
@@ -63,6 +69,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix(torch, prec):
     print(f"[gpu] serve mix of {len(cases)} cases, {prec}", flush=True)
     tk, done, states, peak, _, lat = _serve(cases, 3, prec=p)
     assert peak >= 2, "the mix never ran cases together"
+    assert _LAST_STATS["max_batched"] >= 2, "no round's launches advanced two solves together"
     for t in tk:
         assert done[t]["status"] == lib.BD_OK and done[t]["steps"] == 3
         assert done[t]["max_rel_residual"] <= 1e-8
@@ -135,3 +142,18 @@ def test_case_larger_than_budget_is_refused(torch):
         assert e.value.status == lib.BD_E_BUDGET
     finally:
         lib.bidomain_serve_destroy(srv)
+
+
+def test_failed_upload_retires_the_case_and_frees_its_budget(torch, monkeypatch):
+    """The library's test hook makes the upload of ticket 1 report an allocation failure after
+    its device memory was taken: that case must come back with BD_E_NOMEM, its slot and budget
+    must be released, and the other case must still be served."""
+    monkeypatch.setenv("BIDOMAIN_SERVE_FAIL_UPLOAD", "1")
+    cases = [bc.make_case(12, 12, 6, seed=11), bc.make_case(16, 16, 8, seed=12)]
+    print("[gpu] serve with an injected upload failure", flush=True)
+    tk, done, states, _, _, _ = _serve(cases, 2, slots=1, prec=lib.BD_F64)
+    assert tk[0] == 1
+    assert done[tk[0]]["status"] == lib.BD_E_NOMEM and done[tk[0]]["steps"] == 0
+    assert done[tk[1]]["status"] == lib.BD_OK and done[tk[1]]["steps"] == 2
+    assert tk[1] in states and tk[0] not in states
+    assert _LAST_STATS["bytes_in_use"] == 0 and _LAST_STATS["running"] == 0

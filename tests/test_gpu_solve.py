@@ -264,6 +264,26 @@ def test_edge_cases(torch):
         lib.bidomain_amg_destroy(h)
 
 
+def test_apply_rejects_vectors_of_the_wrong_precision(torch):
+    """bidomain_amg_apply's vectors have the hierarchy's V-cycle precision, reported by
+    bidomain_amg_info; the binding refuses the other type before any launch."""
+    c, ops, f = _problem("C1")
+    A = ops["Aell"]
+    for prec, good, bad in ((lib.BD_F32, torch.float32, torch.float64), (lib.BD_F64, torch.float64, torch.float32)):
+        h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, vcycle_precision=prec), ops["m"])
+        try:
+            assert lib.bidomain_amg_info(h)["vcycle_precision"] == prec
+            with pytest.raises(ValueError):
+                lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, torch.zeros(c.n, dtype=bad, device="cuda"),
+                                       torch.zeros(c.n, dtype=bad, device="cuda"))
+            out = torch.zeros(c.n, dtype=good, device="cuda")
+            lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, dev(torch, f, good), out)
+            ref = A @ f.astype(np.float32 if prec == lib.BD_F32 else np.float64)
+            assert _relerr(host(out).astype(np.float64), ref) <= (1e-4 if prec == lib.BD_F32 else 1e-13)
+        finally:
+            lib.bidomain_amg_destroy(h)
+
+
 @pytest.mark.parametrize("dims", [(2, 2, 1), (3, 3, 2), (4, 4, 2)])
 def test_tiny_meshes(torch, dims):
     c = bc.make_case(*dims, seed=3)
