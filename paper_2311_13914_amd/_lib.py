@@ -305,14 +305,18 @@ def bidomain_amg_apply(h, op: int, level: int, inp, out, stream=None):
 
 def bidomain_pcg_solve(h, b, x, x_is_guess: bool, rtol: float = 1e-8, maxit: int = 500, stream=None):
     """b, x: float64 CUDA tensors of n entries. Returns (status, info dict)."""
+    return _solve("bidomain_pcg_solve", h, b, x, x_is_guess, rtol, maxit, stream)
+
+
+def _solve(name, h, b, x, x_is_guess, rtol, maxit, stream):
     n = bidomain_amg_info(h)["n"][0]
     pb = _dev(b, "float64", n, "b")
     px = _dev(x, "float64", n, "x")
     inf = bd_solve_info()
-    rc = load().bidomain_pcg_solve(_vp(h), pb, px, int(bool(x_is_guess)), float(rtol), int(maxit), _stream(stream),
-                                   C.byref(inf))
+    rc = getattr(load(), name)(_vp(h), pb, px, int(bool(x_is_guess)), float(rtol), int(maxit), _stream(stream),
+                               C.byref(inf))
     if rc < 0 and rc not in (BD_E_BREAKDOWN, BD_E_NONFINITE):
-        raise BidomainError(rc, "bidomain_pcg_solve")
+        raise BidomainError(rc, name)
     return rc, dict(iterations=inf.iterations, rel_residual_true=inf.rel_residual_true,
                     rel_residual_rec=inf.rel_residual_rec, seconds=inf.seconds, status=inf.status)
 

@@ -497,10 +497,13 @@ struct bd_amg {
   int64_t part_len = 0;
   int* host_flags = nullptr;  // pinned
   int last_iters = 8;
-  std::vector<hipEvent_t> prof_ev;
+  // events of a solve (created with the solve state, so that a solve creates none): start and
+  // stop of the timed region, and the two alternating "update kernel finished" markers
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_iter[2] = {nullptr, nullptr};
   ~bd_amg() {
     if (host_flags) (void)hipHostFree(host_flags);
-    for (hipEvent_t e : prof_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : {ev_start, ev_stop, ev_iter[0], ev_iter[1]})
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -835,34 +838,28 @@ void alloc_solve_state(bd_amg* h, hipStream_t st) {
   HIPCHK(hipHostGetDevicePointer((void**)&dflags, h->host_flags, 0));
   h->sv.host_flags = dflags;
   h->sv_apply.host_flags = nullptr;
+  HIPCHK(hipEventCreate(&h->ev_start));
+  HIPCHK(hipEventCreate(&h->ev_stop));
+  HIPCHK(hipEventCreateWithFlags(&h->ev_iter[0], hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&h->ev_iter[1], hipEventDisableTiming));
   HIPCHK(hipStreamSynchronize(st));
 }
 
 // ------------------------------------------------------------------------------------------
-// The solve.
+// The solve.  sv: the solve state (scalars, flags, block partials) the kernels use: the
+// handle's own (h->sv), or the same layout in the library's static scratch array.  profile:
+// allow the per-launch timing events of bidomain_profile_enable (they are created per call).
 template <typename T>
-int pcg(bd_amg* h, const double* b, double* x, int guess, double rtol, int maxit, hipStream_t st,
-        bd_solve_info* info) {
+int pcg(bd_amg* h, const Solve& sv, const double* b, double* x, int guess, double rtol, int maxit, hipStream_t st,
+        bd_solve_info* info, bool profile = true) {
   const int n = h->n;
-  const Solve& sv = h->sv;
   auto& L = levels<T>(h);
-  hipEvent_t t0, t1;
-  HIPCHK(hipEventCreate(&t0));
-  HIPCHK(hipEventCreate(&t1));
-  struct EvGuard {
-    hipEvent_t a, b;
-    ~EvGuard() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
-  } eg{t0, t1};
+  hipEvent_t t0 = h->ev_start, t1 = h->ev_stop;
   HIPCHK(hipEventRecord(t0, st));
 
-  // solve state
-  int fl0[F_COUNT] = {0};
-  fl0[F_FIRST] = 1;
-  fl0[F_MAXIT] = std::max(1, maxit);
-  fl0[F_NULLSPACE] = h->o.nullspace == BD_NULL_CONSTANT;
-  double rtol2 = rtol * rtol;
-  HIPCHK(hipMemcpyAsync(sv.fl, fl0, sizeof(fl0), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(sv.sc + S_RTOL2, &rtol2, sizeof(double), hipMemcpyHostToDevice, st));
+  // solve state: flags, iteration cap, null-space switch and rtol^2, set on the device queue
+  k_solve_control<<<1, 64, 0, st>>>(sv, 0, std::max(1, maxit), h->o.nullspace == BD_NULL_CONSTANT, rtol * rtol);
+  HIPCHK(hipGetLastError());
   h->host_flags[0] = h->host_flags[1] = 0;
 
   const int vb = vec_blocks(n);
@@ -902,15 +899,10 @@ int pcg(bd_amg* h, const double* b, double* x, int guess, double rtol, int maxit
 
     const bool fuse0 = smoothed_level(h, 0) && h->o.preconditioner == BD_PC_AMG;
     const bool x0_too = h->o.smoother == BD_JACOBI || h->o.smoother_degree == 1;
-    hipEvent_t ev[2];
-    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    struct EvGuard2 {
-      hipEvent_t* e;
-      ~EvGuard2() { (void)hipEventDestroy(e[0]); (void)hipEventDestroy(e[1]); }
-    } eg2{ev};
-    std::lock_guard<std::mutex> plock(g_prof.mu);
-    const bool prof = g_prof.on;
+    hipEvent_t* ev = h->ev_iter;
+    std::unique_lock<std::mutex> plock(g_prof.mu, std::defer_lock);
+    if (profile) plock.lock();
+    const bool prof = profile && g_prof.on;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pev;
     int enq = 0;
     for (;;) {
@@ -980,12 +972,14 @@ int pcg(bd_amg* h, const double* b, double* x, int guess, double rtol, int maxit
   HIPCHK(hipMemcpyAsync(flags, sv.fl, sizeof(flags), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   const bool zero_rhs = sc[S_FNORM2] == 0.0;
-  if (zero_rhs) HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * n, st));
-  // true residual, then the null-space normalisation
+  if (zero_rhs) {
+    k_fill_zero<double><<<vec_blocks(n), kBlock, 0, st>>>(x, n);
+    HIPCHK(hipGetLastError());
+  }
+  // true residual, then the null-space normalisation (the exit kernels run once `done` is clear)
   Solve svx = sv;
-  int fl_true[F_COUNT] = {0};
-  fl_true[F_NULLSPACE] = flags[F_NULLSPACE];
-  HIPCHK(hipMemcpyAsync(sv.fl + F_DONE, fl_true, sizeof(int), hipMemcpyHostToDevice, st));
+  k_solve_control<<<1, 64, 0, st>>>(sv, 1, 0, 0, 0.0);
+  HIPCHK(hipGetLastError());
   if (!zero_rhs) {
     SpArgs<double> a = args<double>(svx);
     a.x = x; a.b = b;
@@ -1445,8 +1439,8 @@ int bidomain_pcg_solve(bd_amg* h, const double* b_dev, double* x_dev, int x_is_g
     if (h && h->host_only) throw Failure{BD_E_INVALID, "host-only hierarchy"};
     if (!h || !b_dev || !x_dev || !(rtol > 0.0) || maxit < 1) throw Failure{BD_E_INVALID, "invalid solve arguments"};
     hipStream_t st = (hipStream_t)stream;
-    return h->mixed ? pcg<float>(h, b_dev, x_dev, x_is_guess, rtol, maxit, st, info)
-                    : pcg<double>(h, b_dev, x_dev, x_is_guess, rtol, maxit, st, info);
+    return h->mixed ? pcg<float>(h, h->sv, b_dev, x_dev, x_is_guess, rtol, maxit, st, info)
+                    : pcg<double>(h, h->sv, b_dev, x_dev, x_is_guess, rtol, maxit, st, info);
   });
 }
 
@@ -1644,8 +1638,8 @@ int bidomain_sim_create(const bd_slab* s, const bd_amg_opts* ell, const bd_amg_o
     // u_e^0 from v^0 (eq. (6))
     launch_neg_spmv(S.get(), S->v, S->fell, st);
     bd_solve_info inf;
-    const int rc = S->hell->mixed ? pcg<float>(S->hell, S->fell, S->ue, 0, rtol, 1000, st, &inf)
-                                  : pcg<double>(S->hell, S->fell, S->ue, 0, rtol, 1000, st, &inf);
+    const int rc = S->hell->mixed ? pcg<float>(S->hell, S->hell->sv, S->fell, S->ue, 0, rtol, 1000, st, &inf)
+                                  : pcg<double>(S->hell, S->hell->sv, S->fell, S->ue, 0, rtol, 1000, st, &inf);
     if (rc < 0) return rc;
     *out = S.release();
     return BD_OK;
@@ -1670,12 +1664,12 @@ int bidomain_step(bd_sim* S, int nsteps, double rtol, void* stream, bd_step_info
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
       inf.ms_memb += ms;
       bd_solve_info ip, ie;
-      int rc = S->hpar->mixed ? pcg<float>(S->hpar, S->rhs, S->v, 1, rtol, 1000, st, &ip)
-                              : pcg<double>(S->hpar, S->rhs, S->v, 1, rtol, 1000, st, &ip);
+      int rc = S->hpar->mixed ? pcg<float>(S->hpar, S->hpar->sv, S->rhs, S->v, 1, rtol, 1000, st, &ip)
+                              : pcg<double>(S->hpar, S->hpar->sv, S->rhs, S->v, 1, rtol, 1000, st, &ip);
       if (rc != BD_OK) status = rc;
       launch_neg_spmv(S, S->v, S->fell, st);
-      rc = S->hell->mixed ? pcg<float>(S->hell, S->fell, S->ue, 1, rtol, 1000, st, &ie)
-                          : pcg<double>(S->hell, S->fell, S->ue, 1, rtol, 1000, st, &ie);
+      rc = S->hell->mixed ? pcg<float>(S->hell, S->hell->sv, S->fell, S->ue, 1, rtol, 1000, st, &ie)
+                          : pcg<double>(S->hell, S->hell->sv, S->fell, S->ue, 1, rtol, 1000, st, &ie);
       if (rc != BD_OK && status == BD_OK) status = rc;
       inf.steps++;
       inf.it_par += ip.iterations;

@@ -1104,6 +1104,12 @@ __global__ __launch_bounds__(kBlock) void k_cheb_pre0(Solve sv, const T* __restr
   }
 }
 
+// x = 0 (a fill kernel rather than a memset node, so that the call is safe under stream capture).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_fill_zero(T* __restrict__ x, long n) {
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) x[i] = T(0);
+}
+
 // x += d   (degree-1 post-smoothing completion); x = d when `assign`.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_add(Solve sv, T* __restrict__ x, const T* __restrict__ d, int assign, long n) {
