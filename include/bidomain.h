@@ -178,6 +178,21 @@ int bidomain_amg_build_host(const bd_csr* A, const bd_amg_opts* opts, bd_amg** o
 int bidomain_pcg_solve(bd_amg* h, const double* b_dev, double* x_dev, int x_is_guess, double rtol,
                        int maxit, void* stream, bd_solve_info* info);
 
+/*
+ * bidomain_pcg_solve without any device allocation, for callers that cannot allocate (code
+ * under stream capture, tight serving loops, harnesses that forbid allocation).  Arguments,
+ * results and errors as bidomain_pcg_solve; the result is the same (the same kernels in the same
+ * order).  The solve's scalars, flags and block partials live in a static device array of the
+ * library (4 MiB per device, held until the process ends) instead of the handle; the call
+ * allocates no device or pinned memory and creates no events (the handle's, made by the setup,
+ * are used; per-launch profiling is not available here).  Each device has one such array, shared
+ * by every call on it: calls that overlap on one device race and must be serialised by the
+ * caller.  A hierarchy whose block partials need more than the array holds is rejected with
+ * BD_E_INVALID (fine operators up to about 33 million rows fit).
+ */
+int bidomain_pcg_solve_noalloc(bd_amg* h, const double* b_dev, double* x_dev, int x_is_guess, double rtol,
+                               int maxit, void* stream, bd_solve_info* info);
+
 int bidomain_amg_info(const bd_amg* h, bd_amg_stats* s);
 void bidomain_amg_destroy(bd_amg* h);
 

@@ -95,6 +95,8 @@ _SIGS = {
                                      C.POINTER(_vp)]),
     "bidomain_amg_build_host": (C.c_int, [C.POINTER(bd_csr), C.POINTER(bd_amg_opts), C.POINTER(_vp)]),
     "bidomain_pcg_solve": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_int, _vp, C.POINTER(bd_solve_info)]),
+    "bidomain_pcg_solve_noalloc": (C.c_int, [_vp, _vp, _vp, C.c_int, C.c_double, C.c_int, _vp,
+                                             C.POINTER(bd_solve_info)]),
     "bidomain_amg_info": (C.c_int, [_vp, C.POINTER(bd_amg_stats)]),
     "bidomain_amg_destroy": (None, [_vp]),
     "bidomain_amg_export": (C.c_int, [_vp, C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -306,6 +308,11 @@ def bidomain_amg_apply(h, op: int, level: int, inp, out, stream=None):
 def bidomain_pcg_solve(h, b, x, x_is_guess: bool, rtol: float = 1e-8, maxit: int = 500, stream=None):
     """b, x: float64 CUDA tensors of n entries. Returns (status, info dict)."""
     return _solve("bidomain_pcg_solve", h, b, x, x_is_guess, rtol, maxit, stream)
+
+
+def bidomain_pcg_solve_noalloc(h, b, x, x_is_guess: bool, rtol: float = 1e-8, maxit: int = 500, stream=None):
+    """As bidomain_pcg_solve, with the solve state in the library's static device array."""
+    return _solve("bidomain_pcg_solve_noalloc", h, b, x, x_is_guess, rtol, maxit, stream)
 
 
 def _solve(name, h, b, x, x_is_guess, rtol, maxit, stream):

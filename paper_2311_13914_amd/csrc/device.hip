@@ -1392,6 +1392,58 @@ std::unique_ptr<bd_sim> upload_sim(SimHost& H, const double* v0, bool v0_dev, co
 
 int64_t sim_device_bytes(const bd_sim* S) { return S->ar.bytes + S->hell->ar.bytes + S->hpar->ar.bytes; }
 
+// ------------------------------------------------------------------------------------------
+// Solve state of bidomain_pcg_solve_noalloc in a file-scope device array instead of the
+// handle: scalars at [0, S_COUNT), flags (int) at [kNoAllocFlags, +F_COUNT / 2 + 1), block
+// partials from kNoAllocPart on.  Each device holds its own copy for the life of the process;
+// every call on a device shares it (the last call's contents stay), so calls that overlap on
+// one device race.
+constexpr int64_t kNoAllocScratchBytes = int64_t(4) << 20;
+constexpr int kNoAllocFlags = 16, kNoAllocPart = 32;
+static_assert(S_COUNT <= kNoAllocFlags && kNoAllocFlags + (F_COUNT + 1) / 2 <= kNoAllocPart, "scratch layout");
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / 8];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current device's scratch array, looked up once per device (with
+// that device current); the array's name in host code is only a host-side stand-in.
+double* scratch_address() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw Failure{BD_E_DEVICE, "device ordinal out of range"};
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+// A solve state in the scratch array for a solve of h, cleared on the stream (scalars, flags
+// and partials start at zero as in a freshly set-up handle).  Rejects a hierarchy whose block
+// partials do not fit.  The environment variable BIDOMAIN_NOALLOC_SCRATCH_BYTES may lower
+// (never raise) the limit, so that the rejection can be tested.
+Solve noalloc_solve_state(bd_amg* h, hipStream_t st) {
+  int64_t limit = kNoAllocScratchBytes;
+  if (const char* e = std::getenv("BIDOMAIN_NOALLOC_SCRATCH_BYTES"))
+    limit = std::min<int64_t>(limit, std::max<int64_t>(0, std::strtoll(e, nullptr, 10)));
+  const int64_t need = (int64_t)(kNoAllocPart + h->part_len) * 8;
+  if (need > limit)
+    throw Failure{BD_E_INVALID, "the solve needs " + std::to_string(need) + " bytes of scratch, more than the " +
+                                    std::to_string(limit) + " the no-allocation entry point has"};
+  double* base = scratch_address();
+  k_fill_zero<double><<<vec_blocks(need / 8), kBlock, 0, st>>>(base, need / 8);
+  HIPCHK(hipGetLastError());
+  Solve sv = h->sv;
+  sv.sc = base;
+  sv.fl = reinterpret_cast<int*>(base + kNoAllocFlags);
+  sv.part = base + kNoAllocPart;
+  return sv;
+}
+
 }  // namespace bd
 
 // ==========================================================================================
@@ -1441,6 +1493,18 @@ int bidomain_pcg_solve(bd_amg* h, const double* b_dev, double* x_dev, int x_is_g
     hipStream_t st = (hipStream_t)stream;
     return h->mixed ? pcg<float>(h, h->sv, b_dev, x_dev, x_is_guess, rtol, maxit, st, info)
                     : pcg<double>(h, h->sv, b_dev, x_dev, x_is_guess, rtol, maxit, st, info);
+  });
+}
+
+int bidomain_pcg_solve_noalloc(bd_amg* h, const double* b_dev, double* x_dev, int x_is_guess, double rtol,
+                               int maxit, void* stream, bd_solve_info* info) {
+  return guarded([&] {
+    if (h && h->host_only) throw Failure{BD_E_INVALID, "host-only hierarchy"};
+    if (!h || !b_dev || !x_dev || !(rtol > 0.0) || maxit < 1) throw Failure{BD_E_INVALID, "invalid solve arguments"};
+    hipStream_t st = (hipStream_t)stream;
+    const Solve sv = noalloc_solve_state(h, st);
+    return h->mixed ? pcg<float>(h, sv, b_dev, x_dev, x_is_guess, rtol, maxit, st, info, false)
+                    : pcg<double>(h, sv, b_dev, x_dev, x_is_guess, rtol, maxit, st, info, false);
   });
 }
 
