@@ -80,9 +80,9 @@ typedef struct {
    * level of at most 65,536 rows and columns that fits.  bidomain_amg_build_host never uses
    * the device. */
   int32_t galerkin_device;
-  /* 1: keep a level operator that equals its transpose and has at most 14 column - row
-   * offsets >= 0 (the 27-point fine operators) in the symmetric diagonal form (default);
-   * 0: CSR forms only. */
+  /* 1: keep a level operator that equals its transpose and whose column - row offsets >= 0
+   * are those of a 27-point stencil (the fine operators) in the symmetric diagonal form
+   * (default); 0: CSR forms only. */
   int32_t diag_form;
   /* Preconditioner of bidomain_pcg_solve (and of the simulation's solves): BD_PC_AMG, one
    * V-cycle (default); BD_PC_JACOBI, z = D^{-1} r; BD_PC_NONE, z = r (plain CG; the paper runs
@@ -137,7 +137,8 @@ typedef struct {
   int32_t col_bytes_r[BD_MAX_LEVELS];
   /* Stored diagonals (14) where the level operator is kept in the symmetric diagonal form,
    * else 0.  That form is taken for a square matrix equal to its transpose (values compared
-   * exactly) whose column - row offsets >= 0 number at most 14 (a 27-point stencil): only the
+   * exactly) whose column - row offsets >= 0 are those of a 27-point stencil ({0, 1} and four
+   * triples C - 1, C, C + 1, as on a grid at least 2 nodes wide in x): only the
    * diagonals of offset >= 0 are stored, n values each, and row i reads a(i, i - d) as
    * a(i - d, i).  It holds no column indices or CSR values (bd_amg_export still returns the
    * host CSR).  A structurally missing entry reads as zero times x, so a non-finite x value

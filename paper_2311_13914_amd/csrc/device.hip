@@ -255,9 +255,10 @@ namespace bd {
 
 // Symmetric diagonal form: taken where the matrix is square and equal to its transpose (every
 // entry a(i, j) has an entry a(j, i) of the same value, no duplicates), its column - row
-// offsets d >= 0 number at most kDiagK, and the kDiagK diagonals (8 bytes a slot) move fewer
-// bytes than the offset-dictionary form's values and index bytes (9 bytes an entry).  Square
-// matrices with too many offsets (coarse levels) are rejected after a few rows.
+// offsets d >= 0 are those of a 27-point stencil ({0, 1} and four triples C - 1, C, C + 1), and
+// the kDiagK diagonals (8 bytes a slot) move fewer bytes than the offset-dictionary form's
+// values and index bytes (9 bytes an entry).  Square matrices with too many offsets (coarse
+// levels) are rejected after a few rows.
 bool sym_diagonals(const Csr& H, StreamPlan& P) {
   const int32_t n = H.nrows;
   if (n == 0 || H.ncols != n) return false;
@@ -287,8 +288,13 @@ bool sym_diagonals(const Csr& H, StreamPlan& P) {
   std::sort(offs.begin(), offs.end());
   offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
   const int nu = (int)offs.size();
-  if (nu > kDiagK) return false;
-  for (int o = 0; o < kDiagK; ++o) P.doff[o] = o < nu ? offs[o] : 0;
+  if (nu != kDiagK) return false;
+  // the product gathers x in triples around the centres 0, C_1 .. C_4: the offsets must be
+  // {0, 1, C_t - 1, C_t, C_t + 1} (a 27-point stencil of a grid at least 2 nodes wide in x)
+  if (offs[1] != 1) return false;
+  for (int t = 0; t < 4; ++t)
+    if (offs[3 + 3 * t] - offs[2 + 3 * t] != 1 || offs[4 + 3 * t] - offs[3 + 3 * t] != 1) return false;
+  for (int o = 0; o < kDiagK; ++o) P.doff[o] = offs[o];
   auto slot = [&](int d) {
     for (int o = 0; o < nu; ++o)
       if (P.doff[o] == d) return o;

@@ -751,13 +751,112 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* 
 // structured hexahedral mesh), is stored as its diagonals of offset d_o >= 0 only:
 // dv[o * ds + i] = a(i, i + d_o), zero where that entry does not exist.  Row i takes
 // a(i, i + d_o) from dv[o][i] and a(i, i - d_o) = a(i - d_o, i) from dv[o][i - d_o].  One row
-// per lane: both value streams and both gathers x[i + d_o], x[i - d_o] are contiguous across
-// a wave's consecutive rows, so the product reads no column indices or row pointers, stages
-// nothing in LDS, and moves 14 values per row from HBM instead of 27; the shifted second
-// read of each diagonal comes from cache (a lane's own rows or those of recent blocks of the
-// same XCD).  Indices past either end are clamped and their terms weighted by zero (the
-// stored value there is zero; each diagonal holds at least one zero slot past row n - 1).
+// per lane: the value streams are contiguous across a wave's consecutive rows, so the product
+// reads no column indices or row pointers, stages nothing in LDS, and moves 14 values per row
+// from HBM instead of 27; the shifted second read of each diagonal comes from cache (a lane's
+// own rows or those of recent blocks of the same XCD).  Indices past either end are clamped and
+// their terms weighted by zero (the stored value there is zero; each diagonal holds at least
+// one zero slot past row n - 1).
 //
+// The 27 gathers of x fall into 9 triples x[i + C - 1], x[i + C], x[i + C + 1] around the
+// centres C = 0, +-C_1 .. +-C_4 (the plan accepts the form only for offsets
+// {0, 1, C_t - 1, C_t, C_t + 1}).  Each lane loads x[i + C] only; its neighbours are the values
+// of the adjacent lanes (rows i - 1, i + 1), moved by DPP wave shifts, and the two that fall
+// outside the wave come from scalar loads at wave-uniform addresses.  Likewise a(i, i - 1) is
+// the previous lane's a(i - 1, i).  That leaves 35 vector loads a row instead of 54: the
+// product is bound by the texture units' address and data processing of those loads (counters:
+// busy 96 % of the kernel), not by the HBM bytes.
+template <typename T, int CTRL>
+__device__ __forceinline__ T lane_move(T v) {
+  if constexpr (sizeof(T) == 8) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+  } else {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+  }
+}
+constexpr int kDppFromPrev = 0x138;  // wave_shr:1, lane l receives lane l - 1
+constexpr int kDppFromNext = 0x130;  // wave_shl:1, lane l receives lane l + 1
+
+__device__ __forceinline__ int clamp_index(long v, int n) { return (int)(v < 0 ? 0 : (v > n - 1 ? n - 1 : v)); }
+
+// An empty asm statement that takes v as an input: v must be computed at this point of the
+// program (no code is emitted for the statement itself).
+template <typename T>
+__device__ __forceinline__ void pin_value(T v) {
+  __asm__ volatile("" ::"v"(v));
+}
+template <typename T>
+__device__ __forceinline__ void pin_row(const RowIn<T>& in) {
+  pin_value(in.f); pin_value(in.x); pin_value(in.dinv); pin_value(in.r); pin_value(in.xs); pin_value(in.y);
+  pin_value(in.r64); pin_value(in.b); pin_value(in.r32); pin_value(in.r32o);
+}
+
+// Called by every lane of the wave (rows past n included: the lane shifts need all 64), which
+// stores only for rows below n.
+template <typename T, int OP>
+__device__ __forceinline__ void sdia_row(const SpArgs<T>& a, int row, double (&acc)[3], VcAcc<T>& vc) {
+  const int n = a.nrows;
+  const int lane = (int)threadIdx.x & 63;
+  const int wb = __builtin_amdgcn_readfirstlane(row - lane);  // the wave's first row
+  const T* __restrict__ dv = a.dv;
+  const T* __restrict__ x = a.x;
+  const int64_t ds = a.ds;
+  T vu[kDiagK], vl[kDiagK];
+  const int ru = min(row, n);
+#pragma unroll
+  for (int o = 0; o < kDiagK; ++o) vu[o] = dv[o * ds + ru];
+#pragma unroll
+  for (int o = 2; o < kDiagK; ++o) {
+    // before the first row (and past the last) the index points at the zero slot n, so every
+    // term is a plain product (a select on the product let the compiler sink loads into a branch)
+    const int j = row - a.doff[o];
+    vl[o] = dv[o * ds + (j < 0 ? n : min(j, n))];
+  }
+  // centres 0, +C_1, -C_1, ..., +C_4, -C_4 (C_t = doff[3 t])
+  T xm[9], xe0[9], xe1[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const int cen = t == 0 ? 0 : ((t & 1) ? a.doff[3 * ((t + 1) / 2)] : -a.doff[3 * (t / 2)]);
+    xm[t] = x[clamp_index((long)row + cen, n)];
+    xe0[t] = x[clamp_index((long)wb + cen - 1, n)];   // row wb - 1 + C: lane 0's left neighbour
+    xe1[t] = x[clamp_index((long)wb + 64 + cen, n)];  // row wb + 64 + C: lane 63's right neighbour
+  }
+  const T vl1e = dv[ds + (wb >= 1 ? min(wb - 1, n) : n)];
+  const RowIn<T> in = row_fetch<T, OP>(a, min(row, n - 1));
+  T xl[9], xr[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) {
+    const T pl = lane_move<T, kDppFromPrev>(xm[t]), pr = lane_move<T, kDppFromNext>(xm[t]);
+    xl[t] = lane == 0 ? xe0[t] : pl;
+    xr[t] = lane == 63 ? xe1[t] : pr;
+  }
+  {
+    const T p1 = lane_move<T, kDppFromPrev>(vu[1]);
+    vl[1] = lane == 0 ? vl1e : p1;
+  }
+  // d = 0, 1 and the mirror of 1; then per centre C_t the offsets C_t - 1, C_t, C_t + 1 above
+  // (left, middle, right of +C_t) and below (right, middle, left of -C_t)
+  T s[4] = {vu[0] * xm[0], vu[1] * xr[0], T(0), vl[1] * xl[0]};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int o = 2 + 3 * t, cu = 1 + 2 * t, cl = 2 + 2 * t;
+    s[(o + 0) & 3] += vu[o] * xl[cu];
+    s[(o + 1) & 3] += vu[o + 1] * xm[cu];
+    s[(o + 2) & 3] += vu[o + 2] * xr[cu];
+    s[(o + 2) & 3] += vl[o] * xr[cl];
+    s[(o + 3) & 3] += vl[o + 1] * xm[cl];
+    s[(o + 0) & 3] += vl[o + 2] * xl[cl];
+  }
+  const T sum = (s[0] + s[1]) + (s[2] + s[3]);
+  // Only rows below n store.  Pinning the sum and the row operands here keeps their loads ahead
+  // of that branch: the compiler otherwise sinks them into it and waits for each group in turn.
+  pin_value(sum);
+  pin_row(in);
+  if (row < n) row_apply<T, OP>(a, row, sum, in, acc, vc);
+}
+
 // Block order: 256-row chunks form a grid of Z "planes" of S chunks (S chunks span at least the
 // largest offset).  The sequence takes the planes in segments of kZseg, and within a segment
 // walks the columns (c fixed, z increasing): a chunk's far rows i - d_o lie in the chunks
@@ -765,35 +864,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* 
 // XCD, so their second read hits that XCD's L2 (measured at C2: 143 MB fetched per product
 // against 130 MB of algorithmic reads; plain row order 194 MB).  Rows stay consecutive across
 // a wave: two-dimensional tiles of a grid plane fetch no less and run slower.
-template <typename T, int OP>
-__device__ __forceinline__ void sdia_row(const SpArgs<T>& a, int row, double (&acc)[3], VcAcc<T>& vc) {
-  const int n = a.nrows;
-  const T* __restrict__ dv = a.dv;
-  const T* __restrict__ x = a.x;
-  T vu[kDiagK], xu[kDiagK], vl[kDiagK], xl[kDiagK];
-#pragma unroll
-  for (int o = 0; o < kDiagK; ++o) {
-    vu[o] = dv[o * a.ds + row];
-    xu[o] = x[min(row + a.doff[o], n - 1)];
-  }
-#pragma unroll
-  for (int o = 1; o < kDiagK; ++o) {
-    // before the first row the value index points at the zero slot n of the diagonal, so every
-    // term is a plain product (a select on the product let the compiler sink loads into a branch)
-    const int j = row - a.doff[o];
-    vl[o] = dv[o * a.ds + (j >= 0 ? j : n)];
-    xl[o] = x[max(j, 0)];
-  }
-  const RowIn<T> in = row_fetch<T, OP>(a, row);
-  T s[4] = {vu[0] * xu[0], T(0), T(0), T(0)};
-#pragma unroll
-  for (int o = 1; o < kDiagK; ++o) {
-    s[o & 3] += vu[o] * xu[o];
-    s[(o + 2) & 3] += vl[o] * xl[o];
-  }
-  row_apply<T, OP>(a, row, (s[0] + s[1]) + (s[2] + s[3]), in, acc, vc);
-}
-
 constexpr int kZseg = 8;
 
 template <typename T, int OP>
@@ -805,7 +875,7 @@ __device__ __forceinline__ void sdia_body(const SpArgs<T>& a, int b, int nb, dou
   const int row = (z * S + c) * kBlock + (int)threadIdx.x;
   double acc[3] = {0.0, 0.0, 0.0};
   VcAcc<T> vc;
-  if (row < a.nrows) sdia_row<T, OP>(a, row, acc, vc);
+  sdia_row<T, OP>(a, row, acc, vc);
   block_tail<T, OP>(a, acc, vc, b, nb, lds, lds32);
 }
 
