@@ -1,15 +1,19 @@
 #!/usr/bin/env python3
-"""Benchmark: decoupled Bidomain time stepping on one MI355X, float64 AMG-PCG.
+"""Benchmark: decoupled Bidomain time stepping on one MI355X, AMG-PCG for both systems.
 
-Workload (default): the 1 x 1 x 0.5 cm slab at 128 x 128 x 64 Q1 elements (1,081,665 nodes,
-28.6 M nonzeros), rotating axisymmetric fibers, seeded ellipsoidal plateau; each step is one
-Aliev-Panfilov membrane update, one parabolic solve and one elliptic solve (eqs. (4)-(7) of
-the paper), both AMG-preconditioned CG to rtol 1e-8 with the hierarchies built once.
+Workload (default): the 384 x 384 x 96-element slab (14,377,825 nodes, 384 M nonzeros; elements
+of aspect 2, rotating axisymmetric fibers, eight seeded plateau ellipsoids), the paper's
+per-GPU scale (Sec. 6).  Each step is one Aliev-Panfilov membrane update, one parabolic solve
+and one elliptic solve (eqs. (4)-(7)), both AMG-preconditioned to rtol 1e-8 with the
+hierarchies built once and reused.  The headline path runs the V-cycles in float32 inside
+float64 flexible CG; the plain float64 path runs the same steps on the same GPU beside it.
 
 Metric: elliptic PCG-AMG DOF*iters/s = n * (elliptic iterations) / (elliptic solve time), summed
-over the timed steps; solve times come from HIP events on the solve stream.  The JSON line also
-carries the roofline of the dominant fine-level kernel (the outer CG product q = A p, timed with
-HIP events around each launch) and the CPU oracle timed on a bounded sample of the same solve.
+over the timed steps; solve times come from HIP events on the solve stream, inputs resident in
+HBM.  The JSON line also carries the roofline of the fine-level outer CG product q = A p (HIP
+events around each launch that did the product), the whole-iteration byte rate, the CPU oracle
+timed on a bounded sample of the same workload (one core and all cores), and the p50/p99
+latencies of a bounded stream of served cases.
 """
 from __future__ import annotations
 
@@ -26,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-PMC_FILE = os.path.join(ROOT, "profiles", "pmc_outer_spmv_c2.json")
+PMC_FILES = [os.path.join(ROOT, "profiles", f) for f in ("pmc_outer_spmv_c5.json", "pmc_outer_spmv_c2.json")]
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_13914_amd", "csrc", f) for f in ("kernels.hpp", "device.hip")]
 
 
@@ -73,18 +77,20 @@ def iteration_bytes(info: dict, s: int) -> int:
 
 def traffic_from_profile(n, nnz):
     """Measured HBM bytes per launch of the outer product, from the committed rocprofv3 counter
-    summary -- only while the kernel sources are the ones that were profiled."""
-    if not os.path.exists(PMC_FILE):
-        return None
-    rec = json.load(open(PMC_FILE))
-    if rec.get("kernel_source_hash") != kernel_source_hash() or rec.get("n") != n or rec.get("nnz") != nnz:
-        return None
-    return rec.get("bytes_per_launch")
+    summary of this workload -- only while the kernel sources are the ones that were profiled."""
+    for path in PMC_FILES:
+        if not os.path.exists(path):
+            continue
+        rec = json.load(open(path))
+        if rec.get("kernel_source_hash") == kernel_source_hash() and rec.get("n") == n and rec.get("nnz") == nnz:
+            return rec.get("bytes_per_launch")
+    return None
 
 
-def cpu_baseline(case, iters: int):
-    """The CPU oracle on a bounded sample of the same elliptic solve: assembly and setup are run
-    (untimed), then `iters` AMG-PCG iterations are timed from the zero guess."""
+# ---- CPU oracle baseline ----------------------------------------------------------------
+def _oracle_sample_worker(case, reps, barrier, out):
+    """One oracle process: assemble and set up (untimed), then `reps` elliptic solves from a zero
+    guess to rtol 1e-8, each started together with the other processes' (barrier)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import amg, fem, krylov
@@ -97,13 +103,58 @@ def cpu_baseline(case, iters: int):
         t = time.perf_counter()
         h = amg.setup(A, amg.AMGOptions(nullspace=True))
         t_setup = time.perf_counter() - t
-        t = time.perf_counter()
-        res = krylov.amg_pcg(A, f, h, rtol=1e-8, maxit=iters, m=ops["m"])
-        dt = time.perf_counter() - t
-    return dict(value=case.n * res.iterations / dt, unit="DOF*iters/s", cores=1, kind="oracle",
-                sample=f"{res.iterations} AMG-PCG iterations of the elliptic solve on the same "
-                       f"{case.nx}x{case.ny}x{case.nz} slab from a zero guess (float64 numpy/scipy, "
-                       f"{dt:.1f} s timed; oracle setup {t_setup:.1f} s untimed)")
+        runs = []
+        for _ in range(reps):
+            if barrier is not None:
+                barrier.wait()
+            t = time.perf_counter()
+            res = krylov.amg_pcg(A, f, h, rtol=1e-8, maxit=500, m=ops["m"])
+            runs.append((res.iterations, time.perf_counter() - t))
+    out.put((t_setup, runs))
+
+
+def cpu_baseline(case, block, reps: int = 3):
+    """The oracle (plain float64 numpy/scipy, as it stands) on a bounded sample of the workload:
+    the block of `block` elements around the first stimulus ellipsoid, with the workload's element
+    sizes, fiber field and stimulus.  One process on one core, then one process per core of the
+    host's CPU share solving concurrently (whole-job rate: all processes' DOF*iters over the
+    slowest one's time); the median of `reps` solves each."""
+    import multiprocessing as mp
+
+    import bidomain_cases as bc
+
+    sample = bc.block_of(case, *block) if (case.nx, case.ny, case.nz) != tuple(block) else case
+    ctx = mp.get_context("spawn")
+
+    def run(procs):
+        q = ctx.Queue()
+        bar = ctx.Barrier(procs) if procs > 1 else None
+        ps = [ctx.Process(target=_oracle_sample_worker, args=(sample, reps, bar, q)) for _ in range(procs)]
+        for p in ps:
+            p.start()
+        res = [q.get() for _ in ps]
+        for p in ps:
+            p.join()
+        rates = []
+        for r in range(reps):
+            its = sum(x[1][r][0] for x in res)
+            slowest = max(x[1][r][1] for x in res)
+            rates.append(sample.n * its / slowest)
+        return float(np.median(rates)), res[0][0], res[0][1][0][0]
+
+    try:
+        share = len(os.sched_getaffinity(0))
+    except AttributeError:
+        share = os.cpu_count() or 1
+    procs = max(1, min(16, share))
+    one, t_setup, its = run(1)
+    allc, _, _ = run(procs) if procs > 1 else (one, None, None)
+    desc = (f"{sample.nx}x{sample.ny}x{sample.nz}-element block of the {case.nx}x{case.ny}x{case.nz} slab "
+            f"(n = {sample.n}, same element sizes, fibers and stimulus); elliptic AMG-PCG solve from a zero "
+            f"guess to rtol 1e-8 ({its} iterations), median of {reps}; oracle assembly and setup untimed "
+            f"({t_setup:.1f} s); all-core figure: {procs} concurrent single-threaded processes")
+    return dict(value=allc, unit="DOF*iters/s", cores=procs, kind="oracle", sample=desc,
+                one_core=dict(value=one, cores=1))
 
 
 def bench_solve(args):
@@ -172,16 +223,15 @@ def bench_solve(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_serve(args):
+def serve_stream(args, n_cases, nsteps, rate):
     """A seeded stream of slab cases (log-uniform sizes, Poisson arrivals) through the server:
     float32 V-cycles inside float64 CG, hierarchies and states resident in HBM, admission by
-    device budget and slots, all running solves batched per round."""
-    import torch
-
+    device budget and slots, all running solves batched per round.  Returns the latency and
+    throughput summary."""
     import bidomain_cases as bc
     import paper_2311_13914_amd as lib
 
-    reqs = bc.serving_stream(n_cases=args.serve_cases, nsteps=args.serve_steps, rate_per_s=args.rate, seed=4)
+    reqs = bc.serving_stream(n_cases=n_cases, nsteps=nsteps, rate_per_s=rate, seed=4)
     v0s = {r.ticket: bc.nodal_v0(r.case) for r in reqs}
     prec = lib.BD_F64 if args.no_mixed_serve else lib.BD_F32
     oe = lib.bidomain_default_opts(vcycle_precision=prec)
@@ -212,47 +262,120 @@ def bench_serve(args):
     assert not bad, bad[:3]
     case_lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()])
     queue_wait = np.array([r["t_admit"] - r["t_submit"] for r in done.values()])
+    setup_s = np.array([r["t_ready"] - r["t_admit"] for r in done.values()])
     dof_its = sum(ticket_of[t].case.n * (r["it_par"] + r["it_ell"]) for t, r in done.items())
-    out = {
-        "metric": "p50/p99 served solve latency", "value": float(np.percentile(lat, 50) * 1e3), "unit": "ms",
+    return {
+        "workload": f"C4 stream: {n_cases} slab cases, elements log-uniform 32x32x16..160x160x64, {nsteps} IMEX "
+                    f"steps each, Poisson arrivals {rate:g}/s, budget {args.budget_gb:g} GB, {args.slots} slots, "
+                    f"{'float64' if args.no_mixed_serve else 'float32'} V-cycles, rtol {args.rtol:g}",
+        "solves": int(len(lat)), "p50_solve_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_solve_ms": float(np.percentile(lat, 99) * 1e3),
+        "p50_case_s": float(np.percentile(case_lat, 50)), "p99_case_s": float(np.percentile(case_lat, 99)),
+        "max_case_s": float(case_lat.max()), "mean_queue_wait_s": float(queue_wait.mean()),
+        "mean_setup_s": float(setup_s.mean()), "makespan_s": wall,
+        "throughput_dof_iters_per_s": dof_its / wall, "rounds": st["rounds"],
+        "max_solves_per_round": st["max_batched"], "peak_running_cases": peak["running"],
+        "peak_bytes": peak["bytes"], "host_enqueue_s": round(st["host_enqueue_s"], 2),
+        "host_wait_s": round(st["host_wait_s"], 2), "host_exit_s": round(st["host_exit_s"], 2),
+        "note": f"with {n_cases} cases the case p99 is close to the maximum",
+    }
+
+
+def bench_serve(args):
+    out = serve_stream(args, args.serve_cases, args.serve_steps, args.rate)
+    line = {
+        "metric": "p50/p99 served solve latency", "value": out["p50_solve_ms"], "unit": "ms",
         "n_gpus": 1, "steps": args.serve_steps, "warmup": 0, "ms_per_step": None,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.no_mixed_serve else "f32-vcycle/f64", "data": "synthetic",
-        "config": {"workload": f"C4: {args.serve_cases} slab cases, elements log-uniform 32x32x16..160x160x64, "
-                               f"{args.serve_steps} IMEX steps each, Poisson arrivals {args.rate:g}/s, budget "
-                               f"{args.budget_gb:g} GB, {args.slots} slots, rtol {args.rtol:g}"},
-        "serving": {
-            "solves": int(len(lat)), "p50_solve_ms": float(np.percentile(lat, 50) * 1e3),
-            "p99_solve_ms": float(np.percentile(lat, 99) * 1e3),
-            "p50_case_s": float(np.percentile(case_lat, 50)), "p99_case_s": float(np.percentile(case_lat, 99)),
-            "max_case_s": float(case_lat.max()), "mean_queue_wait_s": float(queue_wait.mean()),
-            "makespan_s": wall, "throughput_dof_iters_per_s": dof_its / wall,
-            "rounds": st["rounds"], "peak_running_cases": peak["running"], "peak_bytes": peak["bytes"],
-            "host_enqueue_s": round(st["host_enqueue_s"], 2), "host_wait_s": round(st["host_wait_s"], 2),
-            "host_exit_s": round(st["host_exit_s"], 2),
-            "bytes_per_fine_nnz": [round(r["device_bytes"] / ticket_of[t].case.nnz27, 1) for t, r in
-                                   sorted(done.items(), key=lambda kv: ticket_of[kv[0]].case.nnz27)],
-        },
+        "config": {"workload": out["workload"]}, "serving": out,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(line), flush=True)
+
+
+def run_steps(args, case, mixed: bool, profile: bool):
+    """Build the simulation (setup untimed), run the warm-up steps, then time `args.steps` steps.
+    Returns the step statistics, the hierarchy statistics and the final v and u_e (device)."""
+    import torch
+
+    import bidomain_cases as bc
+    import paper_2311_13914_amd as lib
+
+    prec = lib.BD_F32 if mixed else lib.BD_F64
+    opts_e = lib.bidomain_default_opts(vcycle_precision=prec)
+    opts_p = lib.bidomain_default_opts(vcycle_precision=prec, threshold=0.0)  # parabolic default
+    opts_p.preconditioner = {"amg": lib.BD_PC_AMG, "jacobi": lib.BD_PC_JACOBI, "none": lib.BD_PC_NONE}[args.par_precond]
+    if opts_p.preconditioner != lib.BD_PC_AMG:
+        opts_p.vcycle_precision = lib.BD_F64
+    v0 = torch.tensor(bc.nodal_v0(case), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    t = time.perf_counter()
+    sim = lib.bidomain_sim_create(case, v0, rtol=args.rtol, ell_opts=opts_e, par_opts=opts_p, stream=stream)
+    setup_s = time.perf_counter() - t
+    del v0
+    info_e = lib.bidomain_amg_info(lib.bidomain_sim_hierarchy(sim, 0))
+    info_p = lib.bidomain_amg_info(lib.bidomain_sim_hierarchy(sim, 1))
+    tag = "float32 V-cycles" if mixed else "float64"
+    print(f"[bench] {tag}: n={case.n} setup {setup_s:.1f} s; elliptic levels {info_e['n']}; "
+          f"parabolic levels {info_p['n']}", file=sys.stderr, flush=True)
+    if args.warmup:
+        rc, _ = lib.bidomain_step(sim, args.warmup, args.rtol, stream=stream)
+        assert rc == lib.BD_OK, rc
+    lib.bidomain_profile_read(reset=True)
+    lib.bidomain_profile_enable(profile)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, info = lib.bidomain_step(sim, args.steps, args.rtol, stream=stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.bidomain_profile_enable(False)
+    prof_ms, prof_launches = lib.bidomain_profile_read(reset=True)
+    assert rc == lib.BD_OK, (rc, info)
+    v = torch.empty(case.n, dtype=torch.float64, device="cuda")
+    ue = torch.empty(case.n, dtype=torch.float64, device="cuda")
+    lib.bidomain_sim_get(sim, lib.BD_V, v)
+    lib.bidomain_sim_get(sim, lib.BD_UE, ue)
+    lib.bidomain_sim_destroy(sim)
+    torch.cuda.synchronize()
+    print(f"[bench] {tag}: {args.steps} steps in {wall:.3f} s; it_ell {info['it_ell']} it_par {info['it_par']}",
+          file=sys.stderr, flush=True)
+    return dict(info=info, info_e=info_e, info_p=info_p, wall=wall, setup_s=setup_s, prof_ms=prof_ms,
+                prof_launches=prof_launches, v=v, ue=ue)
+
+
+def step_summary(args, case, r):
+    info = r["info"]
+    return {"value": case.n * info["it_ell"] / (info["ms_ell"] * 1e-3),
+            "ms_per_step": r["wall"] * 1e3 / args.steps,
+            "phases_ms_per_step": {"memb": info["ms_memb"] / args.steps, "par": info["ms_par"] / args.steps,
+                                   "ell": info["ms_ell"] / args.steps},
+            "iters_per_step": {"par": info["it_par"] / args.steps, "ell": info["it_ell"] / args.steps},
+            "rel_residual_last": {"par": info["rel_res_par"], "ell": info["rel_res_ell"]},
+            "setup_s": round(r["setup_s"], 2)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--mixed", action="store_true", help="float32 V-cycle inside float64 flexible CG")
+    ap.add_argument("--f64", action="store_true", help="headline path with float64 V-cycles (default: float32 "
+                                                       "V-cycles inside float64 flexible CG)")
+    ap.add_argument("--mixed", action="store_true", help="(solve mode) float32 V-cycle beside the float64 one")
+    ap.add_argument("--no-f64-path", action="store_true", help="skip the float64 path run beside the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=12)
-    ap.add_argument("--workload", default="C2", choices=["C2", "C3", "C5"])
+    ap.add_argument("--cpu-block", default="128,128,32", help="elements of the oracle's sample block")
+    ap.add_argument("--no-serve", action="store_true", help="skip the bounded serving stream")
+    ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C5"])
     ap.add_argument("--mode", default="step", choices=["step", "solve", "serve"],
                     help="step: Bidomain time steps (default); solve: repeated single elliptic solves; "
                          "serve: a stream of cases through the batching server")
     ap.add_argument("--serve-cases", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=20)
-    ap.add_argument("--rate", type=float, default=2.0, help="serve: Poisson arrival rate (cases/s)")
+    ap.add_argument("--rate", type=float, default=1.0, help="serve: Poisson arrival rate (cases/s)")
+    ap.add_argument("--bounded-serve", default="16,5,2", help="cases,steps,rate of the serving stream in the "
+                                                              "step-mode line")
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--no-mixed-serve", action="store_true", help="serve: float64 V-cycles")
@@ -280,96 +403,85 @@ def main():
         return bench_serve(args)
     case = bc.config_case(args.workload)
     n, nnz = case.n, case.nnz27
-    prec = lib.BD_F32 if args.mixed else lib.BD_F64
-    opts_e = lib.bidomain_default_opts(vcycle_precision=prec)
-    opts_p = lib.bidomain_default_opts(vcycle_precision=prec, threshold=0.0)  # parabolic default
-    opts_p.preconditioner = {"amg": lib.BD_PC_AMG, "jacobi": lib.BD_PC_JACOBI, "none": lib.BD_PC_NONE}[args.par_precond]
-    v0 = torch.tensor(bc.nodal_v0(case), dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
-
-    t = time.perf_counter()
-    sim = lib.bidomain_sim_create(case, v0, rtol=args.rtol, ell_opts=opts_e, par_opts=opts_p, stream=stream)
-    setup_s = time.perf_counter() - t
-    info_e = lib.bidomain_amg_info(lib.bidomain_sim_hierarchy(sim, 0))
-    info_p = lib.bidomain_amg_info(lib.bidomain_sim_hierarchy(sim, 1))
-    print(f"[bench] {args.workload} n={n} setup {setup_s:.1f} s; elliptic levels {info_e['n']}; "
-          f"parabolic levels {info_p['n']}", file=sys.stderr, flush=True)
-
-    if args.warmup:
-        rc, _ = lib.bidomain_step(sim, args.warmup, args.rtol, stream=stream)
-        assert rc == lib.BD_OK, rc
-    lib.bidomain_profile_read(reset=True)
-    lib.bidomain_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc, info = lib.bidomain_step(sim, args.steps, args.rtol, stream=stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lib.bidomain_profile_enable(False)
-    prof_ms, prof_launches = lib.bidomain_profile_read(reset=True)
-    assert rc == lib.BD_OK, (rc, info)
-    lib.bidomain_sim_destroy(sim)
+    mixed = not args.f64
+    r = run_steps(args, case, mixed, profile=True)
+    info, info_e = r["info"], r["info_e"]
+    head = step_summary(args, case, r)
+    avg_ms = r["prof_ms"] / max(r["prof_launches"], 1)
+    diags = info_e["diags"][0]
+    bytes_launch = spmv_bytes(n, nnz, 8, info_e["col_bytes"][0], info_e["tiles"][0], diags)
+    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
+    it_bytes = iteration_bytes(info_e, 4 if mixed else 8)
+    it_ms = info["ms_ell"] / max(info["it_ell"], 1)
+    it_gbs = it_bytes / (it_ms * 1e-3) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic_from_profile(n, nnz),
+                    kernel=(("k_spmv_sdia<double, 8>" if diags else "k_spmv_stream<double, 8>")
+                            + " (OP_CG_Q: outer q = A p on the fine operator, float64, with p^T q)"),
+                    bytes_per_launch=bytes_launch, column_index_bytes=info_e["col_bytes"][0],
+                    stored_diagonals=diags, avg_launch_ms=round(avg_ms, 5), launches=r["prof_launches"],
+                    note="launches that did the product only (those enqueued past convergence return at once)")
+    iteration = dict(bytes=it_bytes, ms=round(it_ms, 4), achieved=round(it_gbs, 1),
+                     frac=round(it_gbs / PEAK_HBM_GBS, 4),
+                     note="whole elliptic PCG iteration (outer product, V-cycle, CG updates) by the cost "
+                          "model of iteration_bytes, over elliptic solve time / iterations")
+    out = {
+        "metric": "elliptic PCG-AMG DOF*iters/s",
+        "value": head["value"],
+        "unit": "DOF*iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f32-vcycle/f64" if mixed else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: Bidomain slab {case.nx}x{case.ny}x{case.nz} Q1 elements, n={n}, "
+                        f"nnz={nnz}, Aliev-Panfilov + parabolic + elliptic AMG-PCG per step, "
+                        + ("float32 V-cycles in float64 flexible CG" if mixed else "float64 AMG-PCG")
+                        + f", rtol {args.rtol:g}"
+                        + ("" if args.par_precond == "amg" else f"; parabolic CG preconditioner: {args.par_precond}"),
+            "elliptic_levels": info_e["n"],
+            "parabolic_levels": r["info_p"]["n"],
+            "operator_complexity_ell": round(info_e["operator_complexity"], 3),
+        },
+        "phases_ms_per_step": head["phases_ms_per_step"],
+        "iters_per_step": head["iters_per_step"],
+        "rel_residual_last": head["rel_residual_last"],
+        "setup_s": head["setup_s"],
+        "roofline": roofline,
+        "iteration_roofline": iteration,
+    }
+    if mixed and not args.no_f64_path:
+        v_m, ue_m = r["v"], r["ue"]
+        del r
+        r64 = run_steps(args, case, False, profile=False)
+        f64 = step_summary(args, case, r64)
+        f64["rel_diff_vs_mixed"] = {
+            "v": float(torch.linalg.norm(r64["v"] - v_m) / torch.linalg.norm(r64["v"])),
+            "ue": float(torch.linalg.norm(r64["ue"] - ue_m) / torch.linalg.norm(r64["ue"])),
+            "note": "after the same warm-up and timed steps, each solve at rtol 1e-8"}
+        out["f64_path"] = f64
+        del r64, v_m, ue_m
+    else:
+        del r
+    torch.cuda.empty_cache()
     if args.calib_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    print(f"[bench] {args.steps} steps in {wall:.3f} s; it_ell {info['it_ell']} it_par {info['it_par']}",
-          file=sys.stderr, flush=True)
-
-    ell_s = info["ms_ell"] * 1e-3
-    value = n * info["it_ell"] / ell_s
-    avg_ms = prof_ms / max(prof_launches, 1)
-    diags = info_e["diags"][0]
-    bytes_launch = spmv_bytes(n, nnz, 8, info_e["col_bytes"][0], info_e["tiles"][0], diags)
-    achieved = bytes_launch / (avg_ms * 1e-3) / 1e9
-    it_bytes = iteration_bytes(info_e, 4 if args.mixed else 8)
-    it_ms = info["ms_ell"] / max(info["it_ell"], 1)
-    it_gbs = it_bytes / (it_ms * 1e-3) / 1e9
-    iteration = dict(bytes=it_bytes, ms=round(it_ms, 4), achieved=round(it_gbs, 1),
-                     frac=round(it_gbs / PEAK_HBM_GBS, 4),
-                     note="whole elliptic PCG iteration (outer product, V-cycle, CG updates) by the cost "
-                          "model of iteration_bytes, over elliptic solve time / iterations")
-    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                    frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic_from_profile(n, nnz),
-                    kernel=(("k_spmv_sdia<double, 8>" if diags else "k_spmv_stream<double, 8>")
-                            + " (OP_CG_Q: outer q = A p on the fine operator, with p^T q)"),
-                    bytes_per_launch=bytes_launch, column_index_bytes=info_e["col_bytes"][0],
-                    stored_diagonals=diags,
-                    avg_launch_ms=round(avg_ms, 5), launches=prof_launches)
-
-    out = {
-        "metric": "elliptic PCG-AMG DOF*iters/s",
-        "value": value,
-        "unit": "DOF*iters/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True,
-        "scaling": "strong",
-        "vs_baseline": None,
-        "dtype": "f32-vcycle/f64" if args.mixed else "f64",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{args.workload}: Bidomain slab {case.nx}x{case.ny}x{case.nz} Q1 elements, n={n}, "
-                        f"nnz={nnz}, Aliev-Panfilov + parabolic + elliptic AMG-PCG per step, rtol {args.rtol:g}"
-                        + ("" if args.par_precond == "amg" else f"; parabolic CG preconditioner: {args.par_precond}"),
-            "elliptic_levels": info_e["n"],
-            "parabolic_levels": info_p["n"],
-            "operator_complexity_ell": round(info_e["operator_complexity"], 3),
-        },
-        "phases_ms_per_step": {"memb": info["ms_memb"] / args.steps, "par": info["ms_par"] / args.steps,
-                               "ell": info["ms_ell"] / args.steps},
-        "iters_per_step": {"par": info["it_par"] / args.steps, "ell": info["it_ell"] / args.steps},
-        "setup_s": round(setup_s, 2),
-        "roofline": roofline,
-        "iteration_roofline": iteration,
-    }
+    if not args.no_serve:
+        nc, ns, rate = args.bounded_serve.split(",")
+        print("[bench] bounded serving stream", file=sys.stderr, flush=True)
+        out["serving"] = serve_stream(args, int(nc), int(ns), float(rate))
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(case, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(case, tuple(int(v) for v in args.cpu_block.split(",")))
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

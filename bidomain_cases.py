@@ -99,6 +99,24 @@ def config_case(name: str) -> SlabCase:
     return make_case(name=name, **kw)
 
 
+def block_of(case: SlabCase, nx: int, ny: int, nz: int, around: int = 0) -> SlabCase:
+    """The nx x ny x nz-element block of `case` (same element sizes, same fiber field, same
+    stimulus ellipsoids) placed around the centre of ellipsoid `around`, as a slab of its own
+    with the origin at the block's corner: a bounded sample of a workload that is too large for
+    the CPU oracle."""
+    hx, hy, hz = case.h
+    cx, cy, cz = case.ellipsoids[around][:3] if case.ellipsoids else (0.0, 0.0, 0.0)
+    i0 = min(max(int(round(cx / hx)) - nx // 2, 0), case.nx - nx)
+    j0 = min(max(int(round(cy / hy)) - ny // 2, 0), case.ny - ny)
+    k0 = min(max(int(round(cz / hz)) - nz // 2, 0), case.nz - nz)
+    x0, y0, z0 = i0 * hx, j0 * hy, k0 * hz
+    ell = tuple((e[0] - x0, e[1] - y0, e[2] - z0, e[3], e[4], e[5]) for e in case.ellipsoids)
+    return replace(case, nx=nx, ny=ny, nz=nz, Lx=nx * hx, Ly=ny * hy, Lz=nz * hz,
+                   fiber_theta0=case.fiber_theta0 + case.fiber_rotation * z0 / case.Lz,
+                   fiber_rotation=case.fiber_rotation * (nz * hz) / case.Lz, ellipsoids=ell,
+                   name=f"{case.name or 'slab'}-block{nx}x{ny}x{nz}@{i0},{j0},{k0}")
+
+
 def node_coordinates(case: SlabCase):
     hx, hy, hz = case.h
     x = np.arange(case.nx + 1) * hx
