@@ -1,8 +1,10 @@
-"""Full-size parity at the benchmarked configuration (128 x 128 x 64 slab, float64, the launch
-configuration bench.py times): sampled rows of every level-0 product against the oracle's own
-assembly, and properties that hold at any size -- true residuals of both solves recomputed with
-the oracle's matrices, the integral-zero normalisation, charge balance of the parabolic step, and
-bitwise reproducibility of a step."""
+"""Full-size parity: at 128 x 128 x 64 (float64 and float32 V-cycles), sampled rows of every
+level-0 product against the oracle's own assembly, the elliptic solution against the oracle's
+rtol-1e-12 solution, and properties that hold at any size -- true residuals of both solves
+recomputed with the oracle's matrices, the integral-zero normalisation, charge balance of the
+parabolic step, and bitwise reproducibility of a step; at 384 x 384 x 96 (the benchmarked size,
+in bench.py's launch configuration), sampled rows of the fine product against rows built from the
+oracle's element matrices."""
 import numpy as np
 import pytest
 
@@ -105,16 +107,41 @@ def test_step_is_bitwise_reproducible(c2):
     assert np.array_equal(outs[0][0], outs[1][0])
 
 
+def _oracle_rows(case, rows, x):
+    """(A_ell x)_p for the sampled rows p, from the oracle's element matrices alone: row p sums
+    K_e[l(p), m] x[node_m(e)] over the (up to 8) elements e containing node p."""
+    nxp, nyp = case.nx + 1, case.ny + 1
+    K = {}
+    out = np.zeros(len(rows))
+    for t, p in enumerate(rows):
+        i, j, k = p % nxp, (p // nxp) % nyp, p // (nxp * nyp)
+        s = 0.0
+        for l in range(8):
+            a, b, c = fem.local_node_bits(l)
+            ex, ey, ez = i - a, j - b, k - c
+            if not (0 <= ex < case.nx and 0 <= ey < case.ny and 0 <= ez < case.nz):
+                continue
+            if ez not in K:
+                K[ez] = (fem.element_stiffness(case, ez, case.sig_il, case.sig_it)
+                         + fem.element_stiffness(case, ez, case.sig_el, case.sig_et))
+            for m2 in range(8):
+                a2, b2, c2 = fem.local_node_bits(m2)
+                s += K[ez][l, m2] * x[(ex + a2) + nxp * ((ey + b2) + nyp * (ez + c2))]
+        out[t] = s
+    return out
+
+
 def test_c5_fine_product_sampled():
     """The fine elliptic product at the largest single-GPU size bench.py runs (384 x 384 x 96
     elements, 14.4 M rows, 384 M nonzeros; the diagonal form, in its launch configuration) on
-    sampled rows -- both ends and 20,000 random ones -- against the library's host assembly, which
-    the host tests check against the oracle's at small sizes."""
+    sampled rows -- the first and last rows and 12,000 random ones -- against the same rows built
+    from the oracle's element stiffness matrices."""
     import torch
     case = bc.config_case("C5")
-    print(f"[gpu] C5 n={case.n}: host assembly", flush=True)
+    print(f"[gpu] C5 n={case.n}: library assembly and diagonal form", flush=True)
     rp, ci, v, _ = lib.bidomain_slab_assemble(case, lib.BD_MAT_AELL)
     h = lib.bidomain_amg_setup((rp, ci, v), lib.bidomain_default_opts(nullspace=1, max_levels=1))
+    del rp, ci, v
     try:
         assert lib.bidomain_amg_info(h)["diags"][0] == 14
         rng = np.random.default_rng(5)
@@ -122,8 +149,47 @@ def test_c5_fine_product_sampled():
         y = torch.empty(case.n, dtype=torch.float64, device="cuda")
         lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, _dev(x), y)
         ys = y.cpu().numpy()
-        rows = np.concatenate([[0, 1, case.n - 2, case.n - 1], rng.integers(0, case.n, 20000)])
-        ref = np.array([v[rp[i]:rp[i + 1]] @ x[ci[rp[i]:rp[i + 1]]] for i in rows])
-        assert np.max(np.abs(ys[rows] - ref)) <= 1e-13 * np.max(np.abs(ref))
+        edge = [0, 1, 2, case.nx, case.nx + 1, case.n - case.nx - 2, case.n - 2, case.n - 1]
+        rows = np.concatenate([edge, rng.integers(0, case.n, 12000)])
+        ref = _oracle_rows(case, rows, x)
+        assert np.max(np.abs(ys[rows] - ref)) <= 1e-12 * np.max(np.abs(ref))
     finally:
         lib.bidomain_amg_destroy(h)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_c2_elliptic_solution_matches_oracle(c2, precision):
+    """The 128 x 128 x 64 elliptic solve (f = -A_i v0, zero guess) against the oracle's solution
+    at rtol 1e-12 on the oracle's own hierarchy: relative error <= 1e-6, true relative residual
+    <= 1e-8, iteration count within 1 (float64) or 2 (float32 V-cycles) of the oracle's."""
+    import torch
+    from oracle import amg, krylov
+    case, ops = c2
+    A, m = ops["Aell"], ops["m"]
+    f = -(ops["Ai"] @ bc.nodal_v0(case))
+    if "ref" not in _C2_REF:
+        print("[gpu] C2 oracle setup and rtol-1e-12 solve", flush=True)
+        h_or = amg.setup(A, amg.AMGOptions(nullspace=True))
+        _C2_REF["ref"] = krylov.amg_pcg(A, f, h_or, rtol=1e-12, m=m).x
+        _C2_REF["f64"] = krylov.amg_pcg(A, f, h_or, rtol=1e-8, m=m).iterations
+        _C2_REF["f32"] = krylov.amg_fcg_mixed(A, f, h_or, rtol=1e-8, m=m).iterations
+    ref = _C2_REF["ref"]
+    prec = lib.BD_F32 if precision == "f32" else lib.BD_F64
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, vcycle_precision=prec), m)
+    try:
+        x = torch.zeros(case.n, dtype=torch.float64, device="cuda")
+        rc, info = lib.bidomain_pcg_solve(h, _dev(f), x, False, 1e-8, 500)
+        assert rc == lib.BD_OK, info
+        xs = x.cpu().numpy()
+        fh = f - f.mean()
+        assert np.linalg.norm(fh - A @ xs) <= 1e-8 * np.linalg.norm(fh) * (1 + 1e-6)
+        err = np.linalg.norm(xs - ref) / np.linalg.norm(ref)
+        print(f"[gpu] C2 {precision}: {info['iterations']} iterations (oracle {_C2_REF[precision]}), "
+              f"error {err:.2e}", flush=True)
+        assert err <= 1e-6
+        assert abs(info["iterations"] - _C2_REF[precision]) <= (1 if precision == "f64" else 2)
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+_C2_REF = {}
