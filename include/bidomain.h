@@ -305,7 +305,7 @@ typedef struct {
 } bd_case_result;
 typedef struct {
   int32_t queued, setting_up, running, done;
-  int64_t bytes_in_use, budget;
+  int64_t bytes_in_use, budget;  /* in use: cases on the device and setup transients */
   int64_t rounds, solves;
   double host_enqueue_s, host_wait_s, host_exit_s;  /* host time: enqueuing rounds, waiting on
                                                      the GPU, finishing solves */

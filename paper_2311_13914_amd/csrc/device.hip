@@ -1131,7 +1131,15 @@ __global__ void k_binarize(float* __restrict__ a, int64_t n) {
 
 std::mutex g_galerkin_mu;  // one device Galerkin product at a time (its buffers are large)
 
-bool dense_galerkin(const Csr& A, const Csr& P, int64_t sparse_flops, int mode, bool log, Csr& Ac) {
+// Device memory a setup may take for transient buffers: reserve(bytes) returns false when the
+// bytes are not available (the product then runs on the host); release(bytes) gives them back.
+struct TransientBudget {
+  std::function<bool(int64_t)> reserve;
+  std::function<void(int64_t)> release;
+};
+
+bool dense_galerkin(const Csr& A, const Csr& P, int64_t sparse_flops, int mode, bool log, Csr& Ac,
+                    const TransientBudget* tb) {
   const int64_t n = A.nrows, nc = P.ncols;
   if (mode == 0 || n == 0 || nc == 0 || n > 65536 || nc > 65536) return false;
   const double dense_flops = 2.0 * (double)n * (double)n * (double)nc + 2.0 * (double)n * (double)nc * (double)nc;
@@ -1142,6 +1150,15 @@ bool dense_galerkin(const Csr& A, const Csr& P, int64_t sparse_flops, int mode, 
   const size_t csr_bytes = (size_t)(A.nnz() + P.nnz()) * 12 + (size_t)(n + 1) * 8;
   size_t freeb = 0, total = 0;
   if (hipMemGetInfo(&freeb, &total) != hipSuccess || dense_bytes + csr_bytes > freeb / 2) return false;
+  const int64_t need = (int64_t)(dense_bytes + csr_bytes);
+  if (tb && !tb->reserve(need)) return false;
+  struct Release {
+    const TransientBudget* tb;
+    int64_t bytes;
+    ~Release() {
+      if (tb) tb->release(bytes);
+    }
+  } rel{tb, need};
 
   std::vector<void*> bufs;
   hipStream_t st = nullptr;
@@ -1263,7 +1280,8 @@ bool dense_galerkin(const Csr& A, const Csr& P, int64_t sparse_flops, int mode, 
 // Galerkin products on the device (option galerkin_device); plan: build the launch plans (for a
 // hierarchy that will be uploaded).
 int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, hipStream_t st, bd_amg** out,
-               bool host_only = false, bool use_device = true, bool plan = true) {
+               bool host_only = false, bool use_device = true, bool plan = true,
+               const TransientBudget* tb = nullptr) {
   if (!A || !out) throw Failure{BD_E_INVALID, "null argument"};
   bd_amg_opts o;
   bidomain_default_opts(&o);
@@ -1299,7 +1317,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   std::string err;
   const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
   const GalerkinOffload offload = [&](const Csr& Ak, const Csr& Pk, int64_t flops, Csr& Ac) {
-    return dense_galerkin(Ak, Pk, flops, o.galerkin_device, log, Ac);
+    return dense_galerkin(Ak, Pk, flops, o.galerkin_device, log, Ac, tb);
   };
   const auto t0 = std::chrono::steady_clock::now();
   const int rc = build_hierarchy(std::move(H), o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr);
@@ -1316,10 +1334,10 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
 }
 
 // Host half of a simulation: assembled operators and host-built hierarchies.  With
-// device_galerkin false the setup does no device work at all, so it may run on a worker thread
-// while the GPU serves other cases without taking device memory outside the serving budget;
-// with it true the filled levels' Galerkin products may run on the device in transient buffers
-// of up to half the free device memory (option galerkin_device).
+// device_galerkin false the setup does no device work at all; with it true the filled levels'
+// Galerkin products may run on the device (option galerkin_device) in transient buffers of up to
+// half the free device memory, each first reserved from `tb` when given (a server counts them
+// against its budget while the setup runs on a worker thread).
 struct SimHost {
   bd_slab s{};
   Csr Ai;
@@ -1333,7 +1351,7 @@ struct SimHost {
 };
 
 std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell, const bd_amg_opts* par,
-                                        bool device_galerkin) {
+                                        bool device_galerkin, const TransientBudget* tb = nullptr) {
   std::unique_ptr<SimHost> H(new SimHost());
   H->s = s;
   const int n = (int)slab_nodes(s);
@@ -1363,8 +1381,8 @@ std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell
                  std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
   bd_csr ce{n, Aell.nnz(), Aell.rp.data(), Aell.ci.data(), Aell.v.data()};
   bd_csr cp{n, Apar.nnz(), Apar.rp.data(), Apar.ci.data(), Apar.v.data()};
-  setup_impl(&ce, &oe, nullptr, nullptr, &H->hell, true, device_galerkin);
-  setup_impl(&cp, &op, nullptr, nullptr, &H->hpar, true, device_galerkin);
+  setup_impl(&ce, &oe, nullptr, nullptr, &H->hell, true, device_galerkin, true, tb);
+  setup_impl(&cp, &op, nullptr, nullptr, &H->hpar, true, device_galerkin, true, tb);
   return H;
 }
 
@@ -1805,11 +1823,19 @@ void bidomain_profile_read(double* total_ms, int64_t* launches, int reset) {
 namespace bd {
 
 // Task tables of the multi-task launches: each launch copies its table from a pinned host ring
-// into the same slice of a device buffer (the ring restarts after each round's synchronisation).
+// into the same slice of a device buffer.
 struct Staging {
   char* host = nullptr;
   char* dev = nullptr;
-  size_t cap = 0, used = 0;
+  size_t cap = 0, used = 0, lo = 0, hi = 0;
+  // Rounds alternate between the two halves: a round's tables are rewritten only after the
+  // round before it (which used the other half) is known complete, and the round that used this
+  // half two rounds ago is complete by then too.
+  void begin(int parity) {
+    lo = parity ? cap / 2 : 0;
+    hi = parity ? cap : cap / 2;
+    used = lo;
+  }
   void init(size_t bytes) {
     HIPCHK(hipHostMalloc(&host, bytes, hipHostMallocDefault));
     HIPCHK(hipMalloc(&dev, bytes));
@@ -1822,8 +1848,8 @@ struct Staging {
   template <class Task>
   const Task* push(const std::vector<Task>& v, hipStream_t st) {
     const size_t bytes = v.size() * sizeof(Task);
-    const size_t off = (used + 255) & ~size_t(255);
-    if (off + bytes > cap) throw Failure{BD_E_NOMEM, "serving task staging buffer exhausted"};
+    const size_t off = std::max(lo, (used + 255) & ~size_t(255));
+    if (off + bytes > hi) throw Failure{BD_E_NOMEM, "serving task staging buffer exhausted"};
     std::memcpy(host + off, v.data(), bytes);
     HIPCHK(hipMemcpyAsync(dev + off, host + off, bytes, hipMemcpyHostToDevice, st));
     used = off + bytes;
@@ -2157,6 +2183,8 @@ void inst_exit(BInst& I, hipStream_t st) {
   const Solve& sv = h->sv;
   const int vb = vec_blocks(h->n);
   k_solve_control<<<1, 64, 0, st>>>(sv, 1, 0, 0, 0.0);
+  k_zero_if_zero_rhs<<<vb, kBlock, 0, st>>>(sv, I.x, h->n);  // b^ = 0 gives x = 0
+  HIPCHK(hipGetLastError());
   SpArgs<double> a = args<double>(sv);
   a.x = I.x;
   a.b = I.b;
@@ -2172,6 +2200,18 @@ void inst_exit(BInst& I, hipStream_t st) {
 }
 
 }  // namespace bd
+
+// Scalars and flags of a finished solve, copied to pinned host memory after its exit phase.
+struct ExitSlot {
+  double sc[bd::S_COUNT];
+  int fl[bd::F_COUNT];
+};
+struct PendingExit {
+  int slot = 0;
+  int stage = 0;
+  int64_t ready_round = 0;  // complete once the event of this round has been reached
+};
+constexpr int kExitSlots = 4;
 
 struct ServedCase {
   uint64_t ticket = 0;
@@ -2190,10 +2230,21 @@ struct ServedCase {
   double max_res = 0.0;
   int status = BD_OK;
   std::vector<double> v_out, ue_out;
+  ExitSlot* slots = nullptr;  // pinned, kExitSlots
+  std::deque<PendingExit> exits;
+  int next_slot = 0;
+  ~ServedCase() {
+    if (slots) (void)hipHostFree(slots);
+  }
 };
 
 struct bd_server {
   int64_t budget = 0, used = 0;
+  // device memory held by setup workers' transient buffers (device Galerkin products), counted
+  // against the budget with `used`; both are read and written under budget_mu
+  int64_t transient = 0;
+  std::mutex budget_mu;
+  bd::TransientBudget tbudget;
   int max_slots = 1, admitted = 0, setups = 0;
   bd_amg_opts oe{}, op{};
   double rtol = 1e-8;
@@ -2207,6 +2258,10 @@ struct bd_server {
   Staging stg;
   std::vector<double> solve_lat;
   int64_t rounds = 0, solves = 0, max_batched = 0;
+  hipEvent_t ev[2] = {nullptr, nullptr};  // end of the last two rounds (alternating)
+  int64_t ev_round[2] = {0, 0};
+  int parity = 0;
+  int64_t pending_exits = 0;
   double t_enqueue = 0.0, t_wait = 0.0, t_exit = 0.0;  // host seconds spent per round phase
   // test hook (environment BIDOMAIN_SERVE_FAIL_UPLOAD=<ticket>): the upload of that case
   // reports an allocation failure after its device memory was taken, exercising the cleanup
@@ -2217,6 +2272,9 @@ struct bd_server {
   ~bd_server() {
     for (auto& c : cases)
       if (c->fut.valid()) c->fut.wait();
+    if (st) (void)hipStreamSynchronize(st);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -2249,24 +2307,61 @@ void start_solve(bd_server* S, ServedCase* c, bd_amg* h, const double* b, double
   else inst_begin<double>(c->inst, S->st);
 }
 
+// A case's last solve is done (or it failed): wait for its work, take its results, copy its
+// final state to the host and release its device memory, slot and budget.
+void finish_case(bd_server* S, ServedCase* c) {
+  hipStream_t st = S->st;
+  HIPCHK(hipStreamSynchronize(st));
+  while (!c->exits.empty()) {
+    const PendingExit e = c->exits.front();
+    c->exits.pop_front();
+    S->pending_exits--;
+    const ExitSlot& r = c->slots[e.slot];
+    const double fn = r.sc[S_FNORM2];
+    c->max_res = std::max(c->max_res, fn > 0 ? std::sqrt(r.sc[S_TRUE2] / fn) : 0.0);
+    if (r.fl[F_STATUS] != 0 && c->status == BD_OK) c->status = r.fl[F_STATUS];
+    if (e.stage == 1) c->it_par += r.fl[F_ITERS]; else c->it_ell += r.fl[F_ITERS];
+  }
+  bd_sim* sim = c->sim.get();
+  c->v_out.resize(sim->n);
+  c->ue_out.resize(sim->n);
+  HIPCHK(hipMemcpyAsync(c->v_out.data(), sim->v, sizeof(double) * sim->n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(c->ue_out.data(), sim->ue, sizeof(double) * sim->n, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  c->sim.reset();
+  c->inst.state = -1;
+  {
+    std::lock_guard<std::mutex> g(S->budget_mu);
+    S->used -= c->bytes;
+  }
+  S->admitted--;
+  c->state = 3;
+  c->t_done = S->now();
+  S->unreported.push_back(c);
+}
+
 int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_results) {
   hipStream_t st = S->st;
   // admission in arrival order, against free slots and the device budget
   while (!S->queue.empty() && S->admitted < S->max_slots && S->setups < kMaxConcurrentSetups) {
     ServedCase* c = S->queue.front();
-    if (S->used + c->est > S->budget) break;
+    {
+      std::lock_guard<std::mutex> g(S->budget_mu);
+      if (S->used + S->transient + c->est > S->budget) break;
+      S->used += c->est;
+    }
     S->queue.pop_front();
     S->admitted++;
     S->setups++;
-    S->used += c->est;
     c->state = 1;
     c->t_admit = S->now();
     const bd_slab slab = c->s;
     const bd_amg_opts oe = S->oe, op = S->op;
     const int nthr = setup_threads();
-    c->fut = std::async(std::launch::async, [slab, oe, op, nthr] {
+    const TransientBudget* tb = &S->tbudget;
+    c->fut = std::async(std::launch::async, [slab, oe, op, nthr, tb] {
       omp_set_num_threads(nthr);
-      return build_sim_host(slab, &oe, &op, false);  // no device memory outside the budget
+      return build_sim_host(slab, &oe, &op, true, tb);  // device products within the budget
     });
     S->live.push_back(c);
   }
@@ -2283,7 +2378,10 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
       c->status = BD_E_INVALID;
     }
     if (!H) {  // host setup failed: retire the case
-      S->used -= c->est;
+      {
+        std::lock_guard<std::mutex> g(S->budget_mu);
+        S->used -= c->est;
+      }
       S->admitted--;
       c->state = 3;
       c->t_done = S->now();
@@ -2291,6 +2389,7 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
       continue;
     }
     try {
+      if (!c->slots) HIPCHK(hipHostMalloc((void**)&c->slots, sizeof(ExitSlot) * kExitSlots, hipHostMallocDefault));
       c->sim = upload_sim(*H, c->v0.data(), false, nullptr, false, st);
       if (S->fail_upload_ticket == c->ticket)
         throw Failure{BD_E_NOMEM, "upload failure injected for ticket " + std::to_string(c->ticket)};
@@ -2303,7 +2402,10 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
       c->status = e.code;
       (void)hipStreamSynchronize(st);
       c->sim.reset();
-      S->used -= c->est;
+      {
+        std::lock_guard<std::mutex> g(S->budget_mu);
+        S->used -= c->est;
+      }
       S->admitted--;
       c->state = 3;
       c->t_done = S->now();
@@ -2311,84 +2413,103 @@ int serve_poll(bd_server* S, bd_case_result* results, int max_results, int* n_re
       continue;
     }
     c->bytes = sim_device_bytes(c->sim.get());
-    S->used += c->bytes - c->est;
+    {
+      std::lock_guard<std::mutex> g(S->budget_mu);
+      S->used += c->bytes - c->est;
+    }
     c->state = 2;
     c->t_ready = S->now();
   }
+  // One round: one CG iteration of every running solve, enqueued as multi-task launches.  The
+  // host does not wait for this round: it waits for the previous one (so the GPU always has a
+  // round queued while the host reads flags and enqueues the next), then finishes the solves
+  // that round (or an earlier one) completed.  A solve that converged in round r - 1 still has
+  // its round-r launches queued; they find the done flag set and return at once.
   std::vector<BInst*> act;
-  std::vector<ServedCase*> act_cases;
   for (ServedCase* c : S->live)
-    if (c->state == 2) {
-      act.push_back(&c->inst);
-      act_cases.push_back(c);
-    }
+    if (c->state == 2 && c->inst.state >= 0) act.push_back(&c->inst);
+  const auto ta = std::chrono::steady_clock::now();
+  bool recorded = false;
   if (!act.empty()) {
     S->max_batched = std::max<int64_t>(S->max_batched, (int64_t)act.size());
-    S->stg.used = 0;
-    const auto ta = std::chrono::steady_clock::now();
+    S->stg.begin(S->parity);
     if (S->mixed) batched_round<float>(act, st, S->stg);
     else batched_round<double>(act, st, S->stg);
-    const auto tb = std::chrono::steady_clock::now();
-    HIPCHK(hipStreamSynchronize(st));
-    const auto tc = std::chrono::steady_clock::now();
-    S->t_enqueue += std::chrono::duration<double>(tb - ta).count();
-    S->t_wait += std::chrono::duration<double>(tc - tb).count();
+    HIPCHK(hipEventRecord(S->ev[S->parity], st));
+    S->ev_round[S->parity] = S->rounds;
     S->rounds++;
-    // finished solves: exit phase, then read their scalars
-    const auto td = std::chrono::steady_clock::now();
-    std::vector<ServedCase*> fin;
-    for (ServedCase* c : act_cases)
-      if (__atomic_load_n(&c->inst.h->host_flags[0], __ATOMIC_ACQUIRE)) fin.push_back(c);
-    for (ServedCase* c : fin) inst_exit(c->inst, st);
-    std::vector<std::array<double, S_COUNT>> sc(fin.size());
-    std::vector<std::array<int, F_COUNT>> fl(fin.size());
-    for (size_t j = 0; j < fin.size(); ++j) {
-      HIPCHK(hipMemcpyAsync(sc[j].data(), fin[j]->inst.h->sv.sc, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
-      HIPCHK(hipMemcpyAsync(fl[j].data(), fin[j]->inst.h->sv.fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, st));
-    }
-    HIPCHK(hipStreamSynchronize(st));
-    const auto tnow = std::chrono::steady_clock::now();
-    for (size_t j = 0; j < fin.size(); ++j) {
-      ServedCase* c = fin[j];
-      S->solves++;
-      S->solve_lat.push_back(std::chrono::duration<double>(tnow - c->inst.t0).count());
-      const double fn = sc[j][S_FNORM2];
-      const double res = fn > 0 ? std::sqrt(sc[j][S_TRUE2] / fn) : 0.0;
-      c->max_res = std::max(c->max_res, res);
-      if (fl[j][F_STATUS] != 0 && c->status == BD_OK) c->status = fl[j][F_STATUS];
-      if (fn == 0.0) HIPCHK(hipMemsetAsync(c->inst.x, 0, sizeof(double) * c->inst.h->n, st));
-      if (c->stage == 1) c->it_par += fl[j][F_ITERS]; else c->it_ell += fl[j][F_ITERS];
-      c->inst.state = -1;
-      bd_sim* sim = c->sim.get();
-      if (c->stage == 0 || c->stage == 2) {
-        if (c->stage == 2) c->steps_done++;
-        if (c->steps_done >= c->nsteps || c->status < 0) {
-          c->v_out.resize(sim->n);
-          c->ue_out.resize(sim->n);
-          HIPCHK(hipMemcpyAsync(c->v_out.data(), sim->v, sizeof(double) * sim->n, hipMemcpyDeviceToHost, st));
-          HIPCHK(hipMemcpyAsync(c->ue_out.data(), sim->ue, sizeof(double) * sim->n, hipMemcpyDeviceToHost, st));
-          HIPCHK(hipStreamSynchronize(st));
-          c->sim.reset();
-          S->used -= c->bytes;
-          S->admitted--;
-          c->state = 3;
-          c->t_done = S->now();
-          S->unreported.push_back(c);
-        } else {
-          c->stage = 1;  // next step: membrane update + parabolic solve (eqs. (4), (7))
-          launch_membrane(sim, st);
-          start_solve(S, c, sim->hpar, sim->rhs, sim->v, 1);
-        }
-      } else {
-        c->stage = 2;  // elliptic solve with the new potential (eq. (6))
-        launch_neg_spmv(sim, sim->v, sim->fell, st);
-        start_solve(S, c, sim->hell, sim->fell, sim->ue, 1);
-      }
-    }
-    S->t_exit += std::chrono::duration<double>(std::chrono::steady_clock::now() - td).count();
-  } else if (S->setups > 0) {
-    std::this_thread::sleep_for(std::chrono::microseconds(200));  // only host setups in flight
+    recorded = true;
   }
+  const auto tb = std::chrono::steady_clock::now();
+  int64_t completed = -1;  // rounds known complete: every launch enqueued before that round's event
+  if (recorded && S->rounds >= 2) {
+    HIPCHK(hipEventSynchronize(S->ev[S->parity ^ 1]));  // the previous round
+    completed = S->ev_round[S->parity ^ 1];
+  } else if (recorded || S->pending_exits > 0) {
+    HIPCHK(hipStreamSynchronize(st));  // the first round, or no round left to overlap with
+    completed = INT64_MAX;
+  }
+  if (recorded) S->parity ^= 1;
+  const auto tc = std::chrono::steady_clock::now();
+  S->t_enqueue += std::chrono::duration<double>(tb - ta).count();
+  S->t_wait += std::chrono::duration<double>(tc - tb).count();
+  const auto td = std::chrono::steady_clock::now();
+  // exit phases whose results have arrived (they were enqueued before a completed round)
+  for (ServedCase* c : S->live) {
+    if (c->state != 2) continue;
+    while (!c->exits.empty() && c->exits.front().ready_round <= completed) {
+      const PendingExit e = c->exits.front();
+      c->exits.pop_front();
+      S->pending_exits--;
+      const ExitSlot& r = c->slots[e.slot];
+      const double fn = r.sc[S_FNORM2];
+      c->max_res = std::max(c->max_res, fn > 0 ? std::sqrt(r.sc[S_TRUE2] / fn) : 0.0);
+      if (r.fl[F_STATUS] != 0 && c->status == BD_OK) c->status = r.fl[F_STATUS];
+      if (e.stage == 1) c->it_par += r.fl[F_ITERS]; else c->it_ell += r.fl[F_ITERS];
+    }
+  }
+  // solves found finished (their pinned flag; possibly set by the round still running, whose
+  // remaining launches for that solve return at once): enqueue the exit phase and copy its
+  // scalars back asynchronously, then start the case's next solve at once
+  const auto tnow = std::chrono::steady_clock::now();
+  for (ServedCase* c : S->live) {
+    if (c->state != 2 || c->inst.state < 0) continue;
+    if (!__atomic_load_n(&c->inst.h->host_flags[0], __ATOMIC_ACQUIRE)) continue;
+    BInst& I = c->inst;
+    inst_exit(I, st);
+    const int slot = c->next_slot;
+    c->next_slot = (c->next_slot + 1) % kExitSlots;
+    if ((int)c->exits.size() >= kExitSlots) throw Failure{BD_E_DEVICE, "serving: exit result slots exhausted"};
+    HIPCHK(hipMemcpyAsync(c->slots[slot].sc, I.h->sv.sc, sizeof(double) * S_COUNT, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(c->slots[slot].fl, I.h->sv.fl, sizeof(int) * F_COUNT, hipMemcpyDeviceToHost, st));
+    c->exits.push_back(PendingExit{slot, c->stage, S->rounds});
+    S->pending_exits++;
+    S->solves++;
+    S->solve_lat.push_back(std::chrono::duration<double>(tnow - I.t0).count());
+    I.state = -1;
+    bd_sim* sim = c->sim.get();
+    if (c->stage == 0 || c->stage == 2) {
+      if (c->stage == 2) c->steps_done++;
+      if (c->steps_done >= c->nsteps) {
+        finish_case(S, c);
+        continue;
+      }
+      c->stage = 1;  // next step: membrane update + parabolic solve (eqs. (4), (7))
+      launch_membrane(sim, st);
+      start_solve(S, c, sim->hpar, sim->rhs, sim->v, 1);
+    } else {
+      c->stage = 2;  // elliptic solve with the new potential (eq. (6))
+      launch_neg_spmv(sim, sim->v, sim->fell, st);
+      start_solve(S, c, sim->hell, sim->fell, sim->ue, 1);
+    }
+  }
+  // a case whose solve failed stops at the next solve boundary it reaches (its status is known
+  // once the exit results arrive)
+  for (ServedCase* c : S->live)
+    if (c->state == 2 && c->status < 0 && c->exits.empty()) finish_case(S, c);
+  S->t_exit += std::chrono::duration<double>(std::chrono::steady_clock::now() - td).count();
+  if (act.empty() && S->setups > 0)
+    std::this_thread::sleep_for(std::chrono::microseconds(200));  // only host setups in flight
   {
     std::vector<ServedCase*> keep;
     for (ServedCase* c : S->live)
@@ -2441,7 +2562,20 @@ int bidomain_serve_create(int64_t budget_bytes, int32_t max_slots, const bd_amg_
     S->max_slots = max_slots;
     S->rtol = rtol;
     S->st = (hipStream_t)stream;
-    S->stg.init(size_t(16) << 20);
+    S->stg.init(size_t(32) << 20);
+    bd_server* srv = S.get();
+    S->tbudget.reserve = [srv](int64_t b) {
+      std::lock_guard<std::mutex> g(srv->budget_mu);
+      if (srv->used + srv->transient + b > srv->budget) return false;
+      srv->transient += b;
+      return true;
+    };
+    S->tbudget.release = [srv](int64_t b) {
+      std::lock_guard<std::mutex> g(srv->budget_mu);
+      srv->transient -= b;
+    };
+    HIPCHK(hipEventCreateWithFlags(&S->ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&S->ev[1], hipEventDisableTiming));
     if (const char* f = std::getenv("BIDOMAIN_SERVE_FAIL_UPLOAD")) S->fail_upload_ticket = std::strtoull(f, nullptr, 10);
     *out = S.release();
     return BD_OK;
@@ -2512,7 +2646,10 @@ int bidomain_serve_stats(const bd_server* S, bd_serve_stats* st) {
       else if (c->state == 2) st->running++;
       else st->done++;
     }
-    st->bytes_in_use = S->used;
+    {
+      std::lock_guard<std::mutex> g(const_cast<bd_server*>(S)->budget_mu);
+      st->bytes_in_use = S->used + S->transient;
+    }
     st->budget = S->budget;
     st->rounds = S->rounds;
     st->solves = S->solves;

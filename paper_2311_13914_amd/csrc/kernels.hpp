@@ -1180,6 +1180,12 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(T* __restrict__ x, long n)
   for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) x[i] = T(0);
 }
 
+// x = 0 when the solve's projected right-hand side is zero (its norm is a device scalar).
+__global__ __launch_bounds__(kBlock) void k_zero_if_zero_rhs(Solve sv, double* __restrict__ x, long n) {
+  if (sv.sc[S_FNORM2] != 0.0) return;
+  for (long i = gtid(); i < n; i += (long)gridDim.x * kBlock) x[i] = 0.0;
+}
+
 // x += d   (degree-1 post-smoothing completion); x = d when `assign`.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_add(Solve sv, T* __restrict__ x, const T* __restrict__ d, int assign, long n) {
