@@ -42,6 +42,16 @@ class SlabCase:
     fiber_rotation: float = 2.0 * math.pi / 3.0
     cm: float = 1.0  # chi * C_m (1000 1/cm * 1 uF/cm^2)
     dt: float = 0.05  # ms
+    # Aliev-Panfilov membrane model (Aliev & Panfilov 1996), its published parameters; one model
+    # time unit is ap_t_unit ms and u = (v - ap_v_rest) / ap_v_scale
+    ap_k: float = 8.0
+    ap_a: float = 0.15
+    ap_eps0: float = 0.002
+    ap_mu1: float = 0.2
+    ap_mu2: float = 0.3
+    ap_t_unit: float = 12.9
+    ap_v_scale: float = 105.0
+    ap_v_rest: float = -85.0
     v_rest: float = -85.0
     v_plateau: float = 20.0
     ellipsoids: Tuple[Ellipsoid, ...] = field(default_factory=tuple)

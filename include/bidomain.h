@@ -226,6 +226,13 @@ int bidomain_amg_apply(bd_amg* h, int op, int level, const void* in_dev, void* o
  * p = i + (nx+1)(j + (ny+1)k).  Conductivities (S/cm) are axisymmetric (eq. (2) with
  * sigma_n = sigma_t) around in-plane fibers at angle theta(z) = fiber_theta0 +
  * fiber_rotation * z / Lz.  cm = chi C_m (mF/cm^3), dt in ms.
+ *
+ * Membrane model (the ionic current of eq. (1) and the gating update of eq. (4)): the
+ * two-variable Aliev-Panfilov model (Aliev & Panfilov, Chaos Solitons Fractals 7 (1996) 293),
+ * whose published parameters are ap_k = 8, ap_a = 0.15, ap_eps0 = 0.002, ap_mu1 = 0.2,
+ * ap_mu2 = 0.3, with one model time unit = ap_t_unit = 12.9 ms and the dimensionless potential
+ * u = (v - ap_v_rest) / ap_v_scale (ap_v_rest = -85 mV, ap_v_scale = 105 mV).  All must be
+ * finite; ap_k, ap_eps0, ap_mu2, ap_t_unit and ap_v_scale positive (else BD_E_INVALID).
  */
 typedef struct {
   int32_t nx, ny, nz;
@@ -233,6 +240,7 @@ typedef struct {
   double sig_il, sig_it, sig_el, sig_et;
   double fiber_theta0, fiber_rotation;
   double cm, dt;
+  double ap_k, ap_a, ap_eps0, ap_mu1, ap_mu2, ap_t_unit, ap_v_scale, ap_v_rest;
 } bd_slab;
 
 enum { BD_MAT_AI = 0, BD_MAT_AE = 1, BD_MAT_AELL = 2, BD_MAT_APAR = 3 };

@@ -37,13 +37,23 @@ AP_VSCALE_MV = 105.0
 AP_VREST_MV = -85.0
 
 
-def aliev_panfilov(v, w, dt, cm):
+AP_PUBLISHED = (AP_K, AP_A, AP_EPS0, AP_MU1, AP_MU2, AP_TUNIT_MS, AP_VSCALE_MV, AP_VREST_MV)
+
+
+def case_ap_params(case):
+    """The case's membrane parameters (k, a, eps0, mu1, mu2, time unit, potential scale, rest)."""
+    names = ("ap_k", "ap_a", "ap_eps0", "ap_mu1", "ap_mu2", "ap_t_unit", "ap_v_scale", "ap_v_rest")
+    return tuple(getattr(case, nm, dflt) for nm, dflt in zip(names, AP_PUBLISHED))
+
+
+def aliev_panfilov(v, w, dt, cm, params=AP_PUBLISHED):
     """One membrane step: returns (w^{n+1}, I_ion)."""
-    u = (v - AP_VREST_MV) / AP_VSCALE_MV
-    dtp = dt / AP_TUNIT_MS
-    eps = AP_EPS0 + AP_MU1 * w / (u + AP_MU2)
-    w_new = (w + dtp * eps * (-AP_K * u * (u - AP_A - 1.0))) / (1.0 + dtp * eps)
-    iion = -cm * (AP_VSCALE_MV / AP_TUNIT_MS) * (AP_K * u * (u - AP_A) * (1.0 - u) - u * w_new)
+    k, a, eps0, mu1, mu2, t_unit, v_scale, v_rest = params
+    u = (v - v_rest) / v_scale
+    dtp = dt / t_unit
+    eps = eps0 + mu1 * w / (u + mu2)
+    w_new = (w + dtp * eps * (-k * u * (u - a - 1.0))) / (1.0 + dtp * eps)
+    iion = -cm * (v_scale / t_unit) * (k * u * (u - a) * (1.0 - u) - u * w_new)
     return w_new, iion
 
 
@@ -84,7 +94,7 @@ def step(sim: Sim, iapp=None):
     """Eqs. (4)-(7): membrane update, parabolic solve, elliptic solve."""
     c, o = sim.case, sim.ops
     m = o["m"]
-    w_new, iion = aliev_panfilov(sim.v, sim.w, c.dt, c.cm)
+    w_new, iion = aliev_panfilov(sim.v, sim.w, c.dt, c.cm, case_ap_params(c))
     rhs = (c.cm / c.dt) * (m * sim.v) - o["Ai"] @ sim.ue - m * iion
     if iapp is not None:
         rhs = rhs + m * iapp

@@ -66,7 +66,9 @@ class bd_slab(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("Lx", C.c_double), ("Ly", C.c_double),
                 ("Lz", C.c_double), ("sig_il", C.c_double), ("sig_it", C.c_double), ("sig_el", C.c_double),
                 ("sig_et", C.c_double), ("fiber_theta0", C.c_double), ("fiber_rotation", C.c_double),
-                ("cm", C.c_double), ("dt", C.c_double)]
+                ("cm", C.c_double), ("dt", C.c_double), ("ap_k", C.c_double), ("ap_a", C.c_double),
+                ("ap_eps0", C.c_double), ("ap_mu1", C.c_double), ("ap_mu2", C.c_double), ("ap_t_unit", C.c_double),
+                ("ap_v_scale", C.c_double), ("ap_v_rest", C.c_double)]
 
 
 class bd_step_info(C.Structure):

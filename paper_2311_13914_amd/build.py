@@ -55,5 +55,22 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+HOST_CHECK = os.path.join(BUILD, "host_check_asan")
+
+
+def build_host_check(verbose: bool = False) -> str:
+    """The host setup code (assembly, AMG setup) with its self-check driver, built with
+    AddressSanitizer and UndefinedBehaviorSanitizer (g++, host code only; no HIP source)."""
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = [os.path.join(CSRC, f) for f in ["host_check.cpp"] + HOST_SOURCES]
+    _run(["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+          "-fno-sanitize-recover=all", "-fopenmp", "-Wall", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+          *srcs, "-o", HOST_CHECK], verbose)
+    return HOST_CHECK
+
+
 if __name__ == "__main__":
-    print(build(verbose=True))
+    if "--host-check" in sys.argv:
+        print(build_host_check(verbose=True))
+    else:
+        print(build(verbose=True))

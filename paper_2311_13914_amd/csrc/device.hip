@@ -1042,10 +1042,14 @@ struct bd_sim {
 
 namespace bd {
 
-// Aliev-Panfilov (Chaos Solitons Fractals 7 (1996) 293): k = 8, a = 0.15, eps0 = 0.002,
-// mu1 = 0.2, mu2 = 0.3, one model time unit = 12.9 ms; u = (v + 85) / 105.
-constexpr double kApK = 8.0, kApA = 0.15, kApEps0 = 0.002, kApMu1 = 0.2, kApMu2 = 0.3;
-constexpr double kApTunit = 12.9, kApVscale = 105.0, kApVrest = -85.0;
+// Aliev-Panfilov parameters of the slab (bd_slab; published values k = 8, a = 0.15,
+// eps0 = 0.002, mu1 = 0.2, mu2 = 0.3, one model time unit = 12.9 ms, u = (v + 85) / 105).
+struct ApParams {
+  double k, a, eps0, mu1, mu2, t_unit, v_scale, v_rest;
+};
+inline ApParams ap_params(const bd_slab& s) {
+  return ApParams{s.ap_k, s.ap_a, s.ap_eps0, s.ap_mu1, s.ap_mu2, s.ap_t_unit, s.ap_v_scale, s.ap_v_rest};
+}
 
 // One membrane step and the parabolic right-hand side (eqs. (4), (7)):
 //   w <- (w + dt' eps (-k u (u - a - 1))) / (1 + dt' eps),   eps = eps0 + mu1 w / (u + mu2),
@@ -1056,20 +1060,20 @@ __global__ __launch_bounds__(kBlock) void k_membrane_rhs(const int* __restrict__
                                                          const double* __restrict__ av, const double* __restrict__ ue,
                                                          const double* __restrict__ v, double* __restrict__ w,
                                                          const double* __restrict__ m, double* __restrict__ rhs,
-                                                         double dt, double cm, int n) {
+                                                         double dt, double cm, ApParams ap, int n) {
   constexpr int RPT = kBlock / G;
   const int row = xcd_tile(blockIdx.x, gridDim.x) * RPT + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (row >= n) return;
   const double s = row_product<double, G>(rp, ci, av, ue, row, lane);
   if (lane != 0) return;
-  const double u = (v[row] - kApVrest) / kApVscale;
-  const double dtp = dt / kApTunit;
+  const double u = (v[row] - ap.v_rest) / ap.v_scale;
+  const double dtp = dt / ap.t_unit;
   const double wo = w[row];
-  const double eps = kApEps0 + kApMu1 * wo / (u + kApMu2);
-  const double wn = (wo + dtp * eps * (-kApK * u * (u - kApA - 1.0))) / (1.0 + dtp * eps);
+  const double eps = ap.eps0 + ap.mu1 * wo / (u + ap.mu2);
+  const double wn = (wo + dtp * eps * (-ap.k * u * (u - ap.a - 1.0))) / (1.0 + dtp * eps);
   w[row] = wn;
-  const double iion = -cm * (kApVscale / kApTunit) * (kApK * u * (u - kApA) * (1.0 - u) - u * wn);
+  const double iion = -cm * (ap.v_scale / ap.t_unit) * (ap.k * u * (u - ap.a) * (1.0 - u) - u * wn);
   rhs[row] = (cm / dt) * m[row] * v[row] - s - m[row] * iion;
 }
 
@@ -1474,30 +1478,6 @@ Solve noalloc_solve_state(bd_amg* h, hipStream_t st) {
 // C ABI
 extern "C" {
 
-void bidomain_default_opts(bd_amg_opts* o) {
-  if (!o) return;
-  std::memset(o, 0, sizeof(*o));
-  o->coarsening = BD_SA;
-  o->threshold = 0.06;
-  o->square_graph_levels = 1;
-  o->prolong_smooths = 1;
-  o->coarse_eq_limit = 100;
-  o->max_levels = 25;
-  o->smoother = BD_CHEBYSHEV;
-  o->smoother_degree = 2;
-  o->cheb_lo = 0.05;
-  o->cheb_hi = 1.05;
-  o->esteig_iters = 10;
-  o->seed = 0;
-  o->vcycle_precision = BD_F64;
-  o->nullspace = BD_NULL_NONE;
-  o->stagnation_ratio = 0.9;
-  o->coarse_dense_max = 2048;
-  o->galerkin_device = 1;
-  o->diag_form = 1;
-  o->preconditioner = BD_PC_AMG;
-}
-
 const char* bidomain_last_error(void) { return g_last_error.c_str(); }
 
 int bidomain_amg_setup(const bd_csr* A, const bd_amg_opts* opts, const double* null_weights, void* stream,
@@ -1656,6 +1636,11 @@ static void check_slab(const bd_slab* s) {
   if (!s || s->nx < 1 || s->ny < 1 || s->nz < 1 || !(s->Lx > 0) || !(s->Ly > 0) || !(s->Lz > 0) || !(s->dt > 0) ||
       !(s->cm > 0) || !(s->sig_it > 0) || !(s->sig_il > 0) || !(s->sig_et > 0) || !(s->sig_el > 0))
     throw Failure{BD_E_INVALID, "invalid slab description"};
+  if (!(s->ap_k > 0) || !(s->ap_eps0 > 0) || !(s->ap_mu2 > 0) || !(s->ap_t_unit > 0) || !(s->ap_v_scale > 0) ||
+      !std::isfinite(s->ap_k) || !std::isfinite(s->ap_a) || !std::isfinite(s->ap_eps0) || !std::isfinite(s->ap_mu1) ||
+      !std::isfinite(s->ap_mu2) || !std::isfinite(s->ap_t_unit) || !std::isfinite(s->ap_v_scale) ||
+      !std::isfinite(s->ap_v_rest))
+    throw Failure{BD_E_INVALID, "invalid Aliev-Panfilov parameters in the slab description"};
   if (bd::slab_nodes(*s) > INT32_MAX || bd_slab_nnz27(s) > INT32_MAX)
     throw Failure{BD_E_INVALID, "slab too large for 32-bit CSR indices"};
 }
@@ -1696,9 +1681,9 @@ static void launch_membrane(bd_sim* S, hipStream_t st) {
   const int rpt = kBlock / G;
   const int nb = (S->n + rpt - 1) / rpt;
   switch (G) {
-    case 4: k_membrane_rhs<4><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, S->n); break;
-    case 8: k_membrane_rhs<8><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, S->n); break;
-    default: k_membrane_rhs<16><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, S->n); break;
+    case 4: k_membrane_rhs<4><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, ap_params(S->s), S->n); break;
+    case 8: k_membrane_rhs<8><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, ap_params(S->s), S->n); break;
+    default: k_membrane_rhs<16><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, ap_params(S->s), S->n); break;
   }
   HIPCHK(hipGetLastError());
 }

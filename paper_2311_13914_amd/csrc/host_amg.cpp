@@ -841,3 +841,28 @@ int build_hierarchy(Csr A0, const bd_amg_opts& o, HostHierarchy& H, std::string&
 }
 
 }  // namespace bd
+
+// The App. A defaults (declared in bidomain.h; host code, so the setup can run without HIP).
+extern "C" void bidomain_default_opts(bd_amg_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->coarsening = BD_SA;
+  o->threshold = 0.06;
+  o->square_graph_levels = 1;
+  o->prolong_smooths = 1;
+  o->coarse_eq_limit = 100;
+  o->max_levels = 25;
+  o->smoother = BD_CHEBYSHEV;
+  o->smoother_degree = 2;
+  o->cheb_lo = 0.05;
+  o->cheb_hi = 1.05;
+  o->esteig_iters = 10;
+  o->seed = 0;
+  o->vcycle_precision = BD_F64;
+  o->nullspace = BD_NULL_NONE;
+  o->stagnation_ratio = 0.9;
+  o->coarse_dense_max = 2048;
+  o->galerkin_device = 1;
+  o->diag_form = 1;
+  o->preconditioner = BD_PC_AMG;
+}

@@ -1,0 +1,159 @@
+// Host-side self-check of the library's setup code (Q1 assembly and the AMG setup phase), built
+// with AddressSanitizer and UndefinedBehaviorSanitizer by `python -m paper_2311_13914_amd.build
+// --host-check`: every host routine runs on small and ragged slabs with each coarsening,
+// smoother and null-space option, and the results are checked against the identities they
+// must satisfy (exact symmetry, zero row sums of the stiffness, the lumped mass summing to the
+// volume, R = P^T, P B_c = B and A_c B_c = 0 for smoothed aggregation, P 1 = 1 on zero-row-sum
+// rows for classical coarsening).  Exit status 0 when every check passes.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "bd_host.hpp"
+
+using namespace bd;
+
+static int g_fail = 0;
+#define CHECK(cond, ...)                        \
+  do {                                          \
+    if (!(cond)) {                              \
+      std::fprintf(stderr, "FAIL: " __VA_ARGS__); \
+      std::fprintf(stderr, "\n");               \
+      ++g_fail;                                 \
+    }                                           \
+  } while (0)
+
+static bd_slab slab(int nx, int ny, int nz) {
+  bd_slab s{};
+  s.nx = nx; s.ny = ny; s.nz = nz;
+  s.Lx = 1.0; s.Ly = 1.0; s.Lz = 0.5;
+  s.sig_il = 3.0e-3; s.sig_it = 3.1525e-4; s.sig_el = 2.0e-3; s.sig_et = 1.3514e-3;
+  s.fiber_theta0 = -M_PI / 3.0; s.fiber_rotation = 2.0 * M_PI / 3.0;
+  s.cm = 1.0; s.dt = 0.05;
+  s.ap_k = 8.0; s.ap_a = 0.15; s.ap_eps0 = 0.002; s.ap_mu1 = 0.2; s.ap_mu2 = 0.3;
+  s.ap_t_unit = 12.9; s.ap_v_scale = 105.0; s.ap_v_rest = -85.0;
+  return s;
+}
+
+static double max_abs(const Csr& A) {
+  double m = 0.0;
+  for (double v : A.v) m = std::max(m, std::fabs(v));
+  return m;
+}
+
+static std::vector<double> matvec(const Csr& A, const std::vector<double>& x) {
+  std::vector<double> y(A.nrows, 0.0);
+  for (int32_t i = 0; i < A.nrows; ++i)
+    for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) y[i] += A.v[k] * x[A.ci[k]];
+  return y;
+}
+
+// exact transpose equality of the value arrays (the setup symmetrises every coarse operator)
+static bool exactly_symmetric(const Csr& A) {
+  const Csr T = transpose(A);
+  return T.rp == A.rp && T.ci == A.ci && T.v == A.v;
+}
+
+static void check_hierarchy(const HostHierarchy& H, const bd_amg_opts& o, const char* what) {
+  CHECK(!H.lv.empty(), "%s: empty hierarchy", what);
+  for (size_t k = 0; k < H.lv.size(); ++k) {
+    const HostLevel& L = H.lv[k];
+    // a one-row coarsest level of the pure Neumann operator is zero up to rounding (the
+    // constant spans it; its correction is zero), so its diagonal need not be positive
+    const bool null_row = o.nullspace == BD_NULL_CONSTANT && k > 0 && L.A.nrows == 1;
+    CHECK(null_row || validate(L.A).empty(), "%s: level %zu operator: %s", what, k, validate(L.A).c_str());
+    CHECK(k == 0 || exactly_symmetric(L.A), "%s: level %zu not symmetric", what, k);
+    CHECK((int)L.Dinv.size() == L.A.nrows, "%s: level %zu Dinv size", what, k);
+    if (k + 1 == H.lv.size()) break;
+    const Csr& P = L.P;
+    const Csr& R = L.R;
+    const HostLevel& C = H.lv[k + 1];
+    CHECK(P.nrows == L.A.nrows && P.ncols == C.A.nrows, "%s: level %zu P shape", what, k);
+    const Csr Pt = transpose(P);
+    CHECK(Pt.rp == R.rp && Pt.ci == R.ci && Pt.v == R.v, "%s: level %zu R != P^T", what, k);
+    CHECK(C.A.nrows < L.A.nrows, "%s: level %zu does not coarsen", what, k);
+    if (o.coarsening == BD_SA && o.nullspace == BD_NULL_CONSTANT) {  // A B = 0, so P B_c = B
+      const std::vector<double> PB = matvec(P, C.B);
+      double err = 0.0, ref = 0.0;
+      for (int32_t i = 0; i < P.nrows; ++i) {
+        err = std::max(err, std::fabs(PB[i] - L.B[i]));
+        ref = std::max(ref, std::fabs(L.B[i]));
+      }
+      CHECK(err <= 1e-12 * ref, "%s: level %zu P B_c != B (%g)", what, k, err / ref);
+      if (C.A.nrows > 1) {
+        const std::vector<double> AB = matvec(C.A, C.B);
+        double e = 0.0, bmax = 0.0;
+        for (size_t i = 0; i < AB.size(); ++i) e = std::max(e, std::fabs(AB[i]));
+        for (double b : C.B) bmax = std::max(bmax, std::fabs(b));
+        CHECK(e <= 1e-12 * max_abs(C.A) * bmax, "%s: level %zu A_c B_c != 0", what, k + 1);
+      }
+    } else if (o.coarsening == BD_RS) {
+      const std::vector<double> one(P.ncols, 1.0), ones_f(L.A.nrows, 1.0);
+      const std::vector<double> P1 = matvec(P, one), A1 = matvec(L.A, ones_f);
+      for (int32_t i = 0; i < P.nrows; ++i)
+        if (std::fabs(A1[i]) <= 1e-13 * max_abs(L.A) && P.rp[i + 1] > P.rp[i])
+          CHECK(std::fabs(P1[i] - 1.0) <= 1e-13, "%s: level %zu row %d P 1 = %g", what, k, i, P1[i]);
+    }
+  }
+  if (H.coarse_mode == 0) {
+    const int nM = H.lv.back().A.nrows;
+    CHECK((int64_t)H.G.size() == (int64_t)nM * nM, "%s: coarse inverse size", what);
+    for (double g : H.G) CHECK(std::isfinite(g), "%s: non-finite coarse inverse", what);
+  }
+}
+
+int main() {
+  const int dims[][3] = {{1, 1, 1}, {2, 2, 1}, {5, 4, 3}, {16, 16, 8}, {23, 19, 9}};
+  for (const auto& d : dims) {
+    const bd_slab s = slab(d[0], d[1], d[2]);
+    Csr Ai, Ae;
+    assemble_slab_stiffness(s, s.sig_il, s.sig_it, Ai);
+    assemble_slab_stiffness(s, s.sig_el, s.sig_et, Ae);
+    std::vector<double> m;
+    slab_lumped_mass(s, m);
+    const int64_t n = slab_nodes(s);
+    CHECK(Ai.nrows == n && (int64_t)m.size() == n, "slab %dx%dx%d sizes", d[0], d[1], d[2]);
+    CHECK(validate(Ai).empty(), "slab %dx%dx%d CSR: %s", d[0], d[1], d[2], validate(Ai).c_str());
+    CHECK(exactly_symmetric(Ai), "slab %dx%dx%d A_i not symmetric", d[0], d[1], d[2]);
+    double vol = 0.0;
+    for (double x : m) vol += x;
+    CHECK(std::fabs(vol - 0.5) <= 1e-13, "slab %dx%dx%d mass sum %g", d[0], d[1], d[2], vol);
+    const std::vector<double> r = matvec(Ai, std::vector<double>(n, 1.0));
+    for (double x : r) CHECK(std::fabs(x) <= 1e-13 * max_abs(Ai), "slab %dx%dx%d A_i 1 != 0", d[0], d[1], d[2]);
+    Csr Aell = Ai, Apar = Ai;
+    for (int32_t i = 0; i < Aell.nrows; ++i)
+      for (int32_t k = Aell.rp[i]; k < Aell.rp[i + 1]; ++k) {
+        Aell.v[k] += Ae.v[k];
+        if (Apar.ci[k] == i) Apar.v[k] += s.cm / s.dt * m[i];
+      }
+    for (int variant = 0; variant < 5; ++variant) {
+      bd_amg_opts o;
+      bidomain_default_opts(&o);
+      o.coarse_eq_limit = n < 200 ? 4 : 100;
+      o.galerkin_device = 0;
+      const char* what = "sa";
+      Csr A = Aell;
+      o.nullspace = BD_NULL_CONSTANT;
+      if (variant == 1) { o.square_graph_levels = 0; what = "sa-unsquared"; }
+      if (variant == 2) { o.coarsening = BD_RS; o.threshold = 0.5; what = "rs"; }
+      if (variant == 3) { o.smoother = BD_JACOBI; o.smoother_degree = 3; what = "sa-jacobi"; }
+      if (variant == 4) { A = Apar; o.nullspace = BD_NULL_NONE; o.threshold = 0.0; what = "parabolic"; }
+      HostHierarchy H;
+      std::string err;
+      const int rc = build_hierarchy(A, o, H, err);
+      CHECK(rc == BD_OK, "slab %dx%dx%d %s: setup failed: %s", d[0], d[1], d[2], what, err.c_str());
+      if (rc == BD_OK) check_hierarchy(H, o, what);
+    }
+  }
+  // malformed input is rejected, not read out of bounds
+  Csr bad;
+  bad.nrows = bad.ncols = 3;
+  bad.rp = {0, 2, 3, 5};
+  bad.ci = {1, 0, 1, 2, 2};
+  bad.v = {1, 1, 1, 1, 1};
+  CHECK(!validate(bad).empty(), "unsorted columns accepted");
+  std::printf(g_fail ? "host check: %d failures\n" : "host check ok\n", g_fail);
+  return g_fail ? 1 : 0;
+}

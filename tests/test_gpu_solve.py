@@ -302,9 +302,12 @@ def test_tiny_meshes(torch, dims):
         lib.bidomain_amg_destroy(h)
 
 
-@pytest.mark.parametrize("mixed", [False, True])
-def test_time_steps_match_oracle(torch, mixed):
+@pytest.mark.parametrize("mixed,membrane", [(False, "published"), (True, "published"), (False, "other")])
+def test_time_steps_match_oracle(torch, mixed, membrane):
     c = bc.make_case(24, 24, 12, seed=2)
+    if membrane == "other":  # membrane parameters reach the kernel from the slab description
+        from dataclasses import replace
+        c = replace(c, ap_k=6.5, ap_a=0.12, ap_eps0=0.003, ap_mu1=0.15, ap_mu2=0.25, ap_t_unit=10.0)
     v0 = bc.nodal_v0(c)
     sim_or = bidomain.create(c, v0, rtol=1e-12)
     prec = lib.BD_F32 if mixed else lib.BD_F64

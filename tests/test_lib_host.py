@@ -129,3 +129,27 @@ def test_malformed_csr_is_rejected():
     with pytest.raises(lib.BidomainError) as e:
         lib.bidomain_amg_build_host(two)
     assert "diagonal must be positive in row 4" in str(e.value)
+
+
+@pytest.mark.parametrize("field,value", [("ap_t_unit", 0.0), ("ap_k", -1.0), ("ap_v_scale", float("nan")),
+                                         ("ap_a", float("inf"))])
+def test_invalid_membrane_parameters_are_rejected(field, value):
+    from dataclasses import replace
+    c = replace(bc.make_case(4, 4, 2, seed=1), **{field: value})
+    with pytest.raises(lib.BidomainError) as e:
+        lib.bidomain_slab_assemble(c, lib.BD_MAT_AELL)
+    assert e.value.status == lib.BD_E_INVALID
+
+
+@pytest.mark.slow
+def test_host_code_under_address_and_undefined_behaviour_sanitizers():
+    """The host setup code built with -fsanitize=address,undefined runs its self-check (small and
+    ragged slabs, every coarsening, smoother and null-space option) without a sanitizer report."""
+    import subprocess
+    from paper_2311_13914_amd import build
+    exe = build.build_host_check()
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1",
+               OMP_NUM_THREADS="4")
+    res = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    assert res.returncode == 0, res.stdout[-2000:] + res.stderr[-4000:]
+    assert "host check ok" in res.stdout

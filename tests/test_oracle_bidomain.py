@@ -61,7 +61,7 @@ def test_conservation_without_currents(monkeypatch):
     c = bc.make_case(8, 8, 4, seed=2)
     v0 = bc.nodal_v0(c)
     sim = bidomain.create(c, v0, rtol=1e-12)
-    monkeypatch.setattr(bidomain, "aliev_panfilov", lambda v, w, dt, cm: (w, np.zeros_like(v)))
+    monkeypatch.setattr(bidomain, "aliev_panfilov", lambda v, w, dt, cm, *p: (w, np.zeros_like(v)))
     m = sim.ops["m"]
     q0 = m @ sim.v
     for _ in range(5):
