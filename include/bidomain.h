@@ -44,7 +44,10 @@ extern "C" {
 #define BD_E_BUDGET (-6)       /* serving: the case does not fit the device budget         */
 
 /* ---- options ----------------------------------------------------------------------- */
-enum { BD_SA = 0, BD_RS = 1 };                 /* coarsening                                */
+/* coarsening: smoothed aggregation (GAMG's method), classical Ruge-Stueben first pass (the HMIS
+ * split of a one-process run), or the PMIS split (the parallel independent-set coarsening of
+ * BoomerAMG's GPU setup); the last two use the strength of eq. (10) and direct interpolation */
+enum { BD_SA = 0, BD_RS = 1, BD_PMIS = 2 };
 enum { BD_CHEBYSHEV = 0, BD_JACOBI = 1 };      /* level smoother                            */
 enum { BD_F64 = 0, BD_F32 = 1 };               /* V-cycle precision                          */
 enum { BD_NULL_NONE = 0, BD_NULL_CONSTANT = 1 };/* kernel of the operator                    */
@@ -58,8 +61,8 @@ enum { BD_PC_AMG = 0, BD_PC_JACOBI = 1, BD_PC_NONE = 2 }; /* preconditioner of t
  * strong threshold alpha of eq. (10) (0.5 is the paper's CPU optimum).
  */
 typedef struct {
-  int32_t coarsening;          /* BD_SA | BD_RS                                          */
-  double threshold;            /* SA theta (default 0.06) or RS alpha                     */
+  int32_t coarsening;          /* BD_SA | BD_RS | BD_PMIS                                */
+  double threshold;            /* SA theta (default 0.06) or the alpha of eq. (10)        */
   int32_t square_graph_levels; /* levels whose MIS runs on the squared graph (1)         */
   int32_t prolong_smooths;     /* Jacobi smoothings of the tentative prolongator (1)     */
   int32_t coarse_eq_limit;     /* stop coarsening at or below this many rows (100)       */
@@ -68,7 +71,8 @@ typedef struct {
   int32_t smoother_degree;     /* Chebyshev degree or Jacobi sweeps per application (2)  */
   double cheb_lo, cheb_hi;     /* Chebyshev interval factors (0.05, 1.05)                */
   int32_t esteig_iters;        /* CG steps of the eigenvalue estimate (10)               */
-  uint64_t seed;               /* SplitMix64 seed of the estimate's start vector (0)     */
+  uint64_t seed;               /* SplitMix64 seed of the estimate's start vector (seed + level)
+                                * and of the PMIS draws (seed + 0x504D4953 + level) (0)   */
   int32_t vcycle_precision;    /* BD_F64 | BD_F32 (then the outer CG is flexible CG)     */
   int32_t nullspace;           /* BD_NULL_NONE | BD_NULL_CONSTANT                        */
   double stagnation_ratio;     /* stop coarsening when n_c > ratio * n_k (0.9)           */

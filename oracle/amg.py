@@ -22,7 +22,9 @@ Readings where the paper is silent or ambiguous:
     SplitMix64 start vector (seed + level), via the CG/Lanczos tridiagonal;
   * A_c = R (A P), then symmetrised (A_c + A_c^T) / 2; no dropping;
   * classical (Ruge-Stueben) first pass and Stueben's direct interpolation, with both
-    positive and negative couplings interpolated separately;
+    positive and negative couplings interpolated separately; or the PMIS split (the parallel
+    independent-set coarsening of [des06], on which BoomerAMG's GPU setup relies) with the same
+    strength and interpolation, its random tie-breaking draws from SplitMix64;
   * coarsening stops once a level has at most `coarse_eq_limit` rows, at `max_levels`, or
     when it would keep more than `stagnation_ratio` of the rows (weakly coupled operators,
     e.g. the mass-dominated parabolic matrix on coarse meshes);
@@ -46,7 +48,8 @@ TIE = 1e-12
 
 @dataclass
 class AMGOptions:
-    coarsening: str = "sa"          # "sa" (smoothed aggregation) or "rs" (classical)
+    coarsening: str = "sa"          # "sa" (smoothed aggregation), "rs" (classical, first pass)
+                                    # or "pmis" (classical strength, PMIS split)
     threshold: float = 0.06         # SA theta; for "rs" the strong threshold alpha
     square_graph_levels: int = 1
     prolong_smooths: int = 1
@@ -295,6 +298,51 @@ def rs_first_pass(S: sp.csr_matrix) -> np.ndarray:
     return (state == CPT).astype(np.int8)
 
 
+def pmis_random(seed: int, level: int, n: int) -> np.ndarray:
+    """The PMIS tie-breaking draws of a level: uniform in [0, 1) from the SplitMix64 stream seeded
+    with seed + PMIS_SEED_OFFSET + level (top 53 bits / 2^53)."""
+    z = splitmix64(seed + PMIS_SEED_OFFSET + level, n)
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+PMIS_SEED_OFFSET = 0x504D4953   # keeps these draws apart from the eigenvalue estimates' (seed + k)
+
+
+def pmis_split(S: sp.csr_matrix, rand: np.ndarray) -> np.ndarray:
+    """Parallel modified independent set (PMIS; De Sterck, Yang & Heys, SIAM J. Matrix Anal.
+    Appl. 27 (2006), the independent-set coarsening behind the HMIS of [des06]).
+
+    Measure lam_i = |S_i^T| + rand_i.  Points that influence no other point (|S_i^T| = 0) are F
+    points from the start.  Then, in rounds until every point is decided: an undecided point
+    whose measure exceeds that of every undecided neighbour in the symmetrised strength graph
+    S + S^T (equal measures: the lower index wins) becomes a C point, and the undecided points
+    that depend strongly on one of the new C points become F points.  Measures never change.
+    Returns 1 for C points, 0 for F points."""
+    n = S.shape[0]
+    ST = S.T.tocsr()
+    influence = np.diff(ST.indptr)
+    lam = influence + rand
+    N = (abs(S) + abs(ST)).tocsr()
+    rows = np.repeat(np.arange(n), np.diff(N.indptr))
+    cols = N.indices
+    off = rows != cols
+    rows, cols = rows[off], cols[off]
+    UND, CPT, FPT = 0, 1, 2
+    state = np.zeros(n, dtype=np.int8)
+    state[influence == 0] = FPT
+    while np.any(state == UND):
+        und = state == UND
+        e = und[rows] & und[cols]
+        beats = (lam[cols] > lam[rows]) | ((lam[cols] == lam[rows]) & (cols < rows))
+        loses = np.zeros(n, dtype=bool)
+        loses[rows[e & beats]] = True
+        new_c = und & ~loses
+        state[new_c] = CPT
+        dep = (S @ new_c.astype(np.float64)) > 0
+        state[und & ~new_c & dep] = FPT
+    return (state == CPT).astype(np.int8)
+
+
 def rs_direct_interpolation(A: sp.csr_matrix, S: sp.csr_matrix, cpts: np.ndarray) -> sp.csr_matrix:
     """Direct interpolation (Stueben): for F point i with interpolatory set P_i = C cap S_i,
     w_ij = -alpha_i a_ij / abar_ii (a_ij < 0), -beta_i a_ij / abar_ii (a_ij > 0), where
@@ -376,9 +424,12 @@ def setup(A: sp.csr_matrix, opts: AMGOptions) -> Hierarchy:
             Pt, Bc = tentative_prolongator(agg, B, nc)
             P = smooth_prolongator(A, lvl.Dinv, Pt, lvl.lam, opts.prolong_smooths)
             lvl.agg = agg
-        elif opts.coarsening == "rs":
+        elif opts.coarsening in ("rs", "pmis"):
             S = rs_strength(A, opts.threshold)
-            cpts = rs_first_pass(S)
+            if opts.coarsening == "rs":
+                cpts = rs_first_pass(S)
+            else:
+                cpts = pmis_split(S, pmis_random(opts.seed, k, n))
             P = rs_direct_interpolation(A, S, cpts)
             nc = P.shape[1]
             Bc = np.ones(nc)

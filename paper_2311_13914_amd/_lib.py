@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libbidomain.so")
 
 BD_OK, BD_E_NOT_CONVERGED = 0, 1
 BD_E_INVALID, BD_E_NOMEM, BD_E_DEVICE, BD_E_BREAKDOWN, BD_E_NONFINITE, BD_E_BUDGET = -1, -2, -3, -4, -5, -6
-BD_SA, BD_RS = 0, 1
+BD_SA, BD_RS, BD_PMIS = 0, 1, 2
 BD_CHEBYSHEV, BD_JACOBI = 0, 1
 BD_F64, BD_F32 = 0, 1
 BD_NULL_NONE, BD_NULL_CONSTANT = 0, 1

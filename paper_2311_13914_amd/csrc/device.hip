@@ -1292,7 +1292,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   if (opts) o = *opts;
   if (o.smoother_degree < 1 || o.coarse_eq_limit < 1 || o.max_levels < 1 || !(o.cheb_hi > o.cheb_lo) ||
       !(o.cheb_lo >= 0.0) || o.esteig_iters < 1 || !(o.threshold >= 0.0) || !(o.stagnation_ratio > 0.0) ||
-      o.coarse_dense_max < 1 || (o.coarsening != BD_SA && o.coarsening != BD_RS) ||
+      o.coarse_dense_max < 1 || (o.coarsening != BD_SA && o.coarsening != BD_RS && o.coarsening != BD_PMIS) ||
       o.galerkin_device < 0 || o.galerkin_device > 2 || o.diag_form < 0 || o.diag_form > 1 ||
       o.preconditioner < BD_PC_AMG || o.preconditioner > BD_PC_NONE ||
       (o.preconditioner != BD_PC_AMG && o.vcycle_precision != BD_F64) ||

@@ -506,6 +506,7 @@ Csr sa_prolongator(const Csr& A, const std::vector<double>& Dinv, const std::vec
 
 // ------------------------------------------------------------------------------------------
 // Classical coarsening.
+constexpr uint64_t kPmisSeedOffset = 0x504D4953;  // PMIS draws: seed + offset + level
 Csr rs_strength(const Csr& A, double alpha) {
   Csr S;
   const int32_t n = A.nrows;
@@ -569,6 +570,60 @@ std::vector<uint8_t> rs_split(const Csr& S) {
       const int32_t m = S.ci[l];
       if (st[m] == UND) pq.push({--lam[m], -m});
     }
+  }
+  return st;
+}
+
+// PMIS split (De Sterck, Yang & Heys 2006, the independent-set coarsening of the HMIS the paper
+// cites): measure lam_i = |S_i^T| + r_i with r_i uniform in [0, 1) from SplitMix64; points that
+// influence no other point are F points; then in rounds, every undecided point whose measure
+// beats all undecided neighbours in S + S^T (equal measures: lower index wins) becomes C, and the
+// undecided points depending strongly on a new C point become F.  Each round reads the previous
+// round's states only, so its loops run in parallel and the result does not depend on order.
+std::vector<uint8_t> pmis_split(const Csr& S, uint64_t seed) {
+  const int32_t n = S.nrows;
+  const Csr ST = transpose(S);
+  enum : uint8_t { UND = 0, CP = 1, FP = 2 };
+  std::vector<double> lam(n);
+  std::vector<uint8_t> st(n, UND), newc(n, 0);
+#pragma omp parallel for schedule(static, 4096)
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t infl = ST.rp[i + 1] - ST.rp[i];
+    lam[i] = (double)infl + (double)(splitmix64_at(seed, (uint64_t)i) >> 11) * 0x1.0p-53;
+    if (infl == 0) st[i] = FP;
+  }
+  auto beats = [&](int32_t j, int32_t i) { return lam[j] > lam[i] || (lam[j] == lam[i] && j < i); };
+  for (;;) {
+    int64_t undecided = 0;
+#pragma omp parallel for schedule(static, 4096) reduction(+ : undecided)
+    for (int32_t i = 0; i < n; ++i) {
+      newc[i] = 0;
+      if (st[i] != UND) continue;
+      ++undecided;
+      bool best = true;
+      for (int32_t k = S.rp[i]; k < S.rp[i + 1] && best; ++k) {
+        const int32_t j = S.ci[k];
+        if (j != i && st[j] == UND && beats(j, i)) best = false;
+      }
+      for (int32_t k = ST.rp[i]; k < ST.rp[i + 1] && best; ++k) {
+        const int32_t j = ST.ci[k];
+        if (j != i && st[j] == UND && beats(j, i)) best = false;
+      }
+      newc[i] = best;
+    }
+    if (undecided == 0) break;
+#pragma omp parallel for schedule(static, 4096)
+    for (int32_t i = 0; i < n; ++i) {
+      if (st[i] != UND || newc[i]) continue;
+      for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k)
+        if (newc[S.ci[k]]) {
+          st[i] = FP;
+          break;
+        }
+    }
+#pragma omp parallel for schedule(static, 4096)
+    for (int32_t i = 0; i < n; ++i)
+      if (newc[i]) st[i] = CP;
   }
   return st;
 }
@@ -790,7 +845,8 @@ int build_hierarchy(Csr A0, const bd_amg_opts& o, HostHierarchy& H, std::string&
       stamp(k, "aggregates and smoothed prolongator");
     } else {
       const Csr S = rs_strength(cur.A, o.threshold);
-      const std::vector<uint8_t> st = rs_split(S);
+      const std::vector<uint8_t> st =
+          o.coarsening == BD_PMIS ? pmis_split(S, o.seed + kPmisSeedOffset + (uint64_t)k) : rs_split(S);
       P = rs_interpolation(cur.A, S, st);
       nc = P.ncols;
       Bc.assign(nc, 1.0);

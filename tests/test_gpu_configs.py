@@ -6,10 +6,10 @@ seeded inputs (through the C ABI):
 * the lane-group product (rows longer than a CSR-stream tile holds, as on the coarse levels of
   the largest slabs) inside the V-cycle and the CG: its fused smoothing, residual and reduction
   epilogues, with 16-bit and 32-bit column indices;
-* the mixed-precision form (float32 V-cycle inside float64 flexible CG) with smoothed-aggregation
-  and classical hierarchies on an aspect-2 slab with eight stimulus ellipsoids (the stimulus law
-  and element shape of the 256 x 256 x 64 and 384 x 384 x 96 workloads), large enough that the
-  classical hierarchy's first coarse level has more than 65,536 rows.
+* the mixed-precision form (float32 V-cycle inside float64 flexible CG) with smoothed-aggregation,
+  classical (first-pass) and PMIS hierarchies on an aspect-2 slab with eight stimulus ellipsoids
+  (the stimulus law and element shape of the 256 x 256 x 64 and 384 x 384 x 96 workloads), large
+  enough that the classical hierarchies' first coarse level has more than 65,536 rows.
 
 Bars as in test_gpu_solve: level operations 1e-12 (V-cycle 1e-10) relative to the oracle's on the
 oracle's own hierarchy; solves reach the true relative residual 1e-8, relative error <= 1e-6
@@ -171,11 +171,11 @@ def aspect2():
     return c, ops, f
 
 
-@pytest.mark.parametrize("coarsening", ["sa", "rs"])
+@pytest.mark.parametrize("coarsening", ["sa", "rs", "pmis"])
 def test_mixed_form_on_aspect2_slab(torch, aspect2, coarsening):
     c, ops, f = aspect2
     A, m = ops["Aell"], ops["m"]
-    thr = 0.5 if coarsening == "rs" else 0.06
+    thr = 0.06 if coarsening == "sa" else 0.5
     h_or = amg.setup(A, amg.AMGOptions(nullspace=True, coarsening=coarsening, threshold=thr))
     ref = krylov.amg_pcg(A, f, h_or, rtol=1e-12, m=m)
     or64 = krylov.amg_pcg(A, f, h_or, rtol=1e-8, m=m)
@@ -183,9 +183,9 @@ def test_mixed_form_on_aspect2_slab(torch, aspect2, coarsening):
     sizes = [lv.A.shape[0] for lv in h_or.levels]
     print(f"[gpu] aspect-2 slab n={c.n} {coarsening} levels={sizes} oracle_its f64={or64.iterations} "
           f"f32={or32.iterations}", flush=True)
-    if coarsening == "rs":
+    if coarsening != "sa":
         assert sizes[1] > 65536
-    code = lib.BD_RS if coarsening == "rs" else lib.BD_SA
+    code = {"sa": lib.BD_SA, "rs": lib.BD_RS, "pmis": lib.BD_PMIS}[coarsening]
     for prec, its, slack in ((lib.BD_F64, or64.iterations, 1), (lib.BD_F32, or32.iterations, 2)):
         h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, coarsening=code, threshold=thr,
                                                                 vcycle_precision=prec), m)

@@ -73,7 +73,7 @@ def _compare_hierarchies(h_lib, h_or, tol=1e-11):
             assert abs(Rl - lv.R).max() <= tol * abs(lv.R).max(), f"R_{k}"
 
 
-@pytest.mark.parametrize("variant", ["sa_ell", "sa_par", "rs_ell"])
+@pytest.mark.parametrize("variant", ["sa_ell", "sa_par", "rs_ell", "pmis_ell"])
 @pytest.mark.parametrize("dims", [(16, 16, 8), (24, 20, 10)])
 def test_host_setup_matches_oracle(variant, dims):
     c = bc.make_case(*dims, seed=1)
@@ -82,9 +82,12 @@ def test_host_setup_matches_oracle(variant, dims):
         A, oo, lo = ops["Aell"], amg.AMGOptions(nullspace=True), dict(nullspace=1)
     elif variant == "sa_par":
         A, oo, lo = ops["Apar"], amg.AMGOptions(), dict()
-    else:
+    elif variant == "rs_ell":
         A, oo, lo = ops["Aell"], amg.AMGOptions(coarsening="rs", threshold=0.5, nullspace=True), \
             dict(coarsening=lib.BD_RS, threshold=0.5, nullspace=1)
+    else:
+        A, oo, lo = ops["Aell"], amg.AMGOptions(coarsening="pmis", threshold=0.5, nullspace=True, seed=3), \
+            dict(coarsening=lib.BD_PMIS, threshold=0.5, nullspace=1, seed=3)
     h_or = amg.setup(A, oo)
     h = lib.bidomain_amg_build_host(A, lib.bidomain_default_opts(**lo))
     try:

@@ -251,3 +251,64 @@ def test_sa_strength_uses_absolute_scaled_coupling():
     np.testing.assert_allclose(G[0].data, np.array([4, 3, 2]) / 50 ** 0.5, rtol=1e-15)
     assert G[2].indices.tolist() == [0]         # symmetric: the positive edge is kept both ways
     assert amg.sa_strength(A, 0.3)[0].indices.tolist() == [1, 2]
+
+
+def _digraph(rows):
+    n = len(rows)
+    A = np.zeros((n, n))
+    for i, js in enumerate(rows):
+        A[i, js] = 1.0
+    return sp.csr_matrix(A)
+
+
+def test_pmis_on_a_path_follows_the_measures():
+    """Symmetric path 0-1-2-3-4: |S_i^T| = 1, 2, 2, 2, 1.
+    Draws (.1, .5, .3, .9, .2): measures 1.1, 2.5, 2.3, 2.9, 1.2; points 1 and 3 beat all their
+    neighbours and become C in the first round, and 0, 2, 4 (each depending on one of them) F.
+    Draws (.9, .1, .8, .2, .7): measures 1.9, 2.1, 2.8, 2.2, 1.7; round 1 selects 2 and makes 1, 3
+    F; in round 2, 0 and 4 have no undecided neighbour left and become C."""
+    S = _digraph([[1], [0, 2], [1, 3], [2, 4], [3]])
+    assert amg.pmis_split(S, np.array([0.1, 0.5, 0.3, 0.9, 0.2])).tolist() == [0, 1, 0, 1, 0]
+    assert amg.pmis_split(S, np.array([0.9, 0.1, 0.8, 0.2, 0.7])).tolist() == [1, 0, 1, 0, 1]
+
+
+def test_pmis_independence_uses_both_directions():
+    """S: 0 depends on 1, 2, 4; 1 and 2 on 0; 4 on 2, 3; 3 on nothing.  |S^T| = 2, 1, 2, 1, 1;
+    draws (.45, .85, .25, .35, .95): measures 2.45, 1.85, 2.25, 1.35, 1.95.
+    Round 1: 0 beats its neighbours 1, 2, 4 in S + S^T (4 is a neighbour only through 0 -> 4) and
+    becomes C; 1 and 2 depend on 0 and become F; 4 does not depend on 0 and stays.  Round 2: 4
+    beats 3 and becomes C (3 depends on nothing, so it stays).  Round 3: 3 has no undecided
+    neighbour and becomes C.  C = {0, 3, 4}: later C points may influence earlier ones.  Taking
+    only S_i (not S_i^T) as the neighbourhood would let 4 into round 1's set next to 0."""
+    S = _digraph([[1, 2, 4], [0], [0], [], [2, 3]])
+    assert amg.pmis_split(S, np.array([0.45, 0.85, 0.25, 0.35, 0.95])).tolist() == [1, 0, 0, 1, 1]
+
+
+def test_pmis_f_points_are_those_depending_on_a_new_c_point():
+    """S: 0 -> 2, 1 -> 0, 2 -> 1, 3, 3 -> 1, 4 -> 1, 3.  |S^T| = 1, 3, 1, 2, 0, so 4 is F from
+    the start.  Draws (.25, .55, .85, .25, .15): measures 1.25, 3.55, 1.85, 2.25.  Round 1: 1 is C;
+    2 and 3 depend on 1 and become F; 0 only influences 1 (1 -> 0) and stays.  Round 2: 0 has no
+    undecided neighbour and becomes C.  C = {0, 1}; marking every neighbour of a new C point F
+    (instead of its dependants) would leave C = {1}."""
+    S = _digraph([[2], [0], [1, 3], [1], [1, 3]])
+    assert amg.pmis_split(S, np.array([0.25, 0.55, 0.85, 0.25, 0.15])).tolist() == [1, 1, 0, 0, 0]
+
+
+def test_pmis_invariants_on_c1():
+    c = bc.config_case("C1")
+    A = fem.assemble_operators(c)["Aell"]
+    h = amg.setup(A, amg.AMGOptions(coarsening="pmis", threshold=0.5, nullspace=True))
+    assert h.nlevels >= 2
+    for k, lv in enumerate(h.levels[:-1]):
+        S = amg.rs_strength(lv.A, 0.5)
+        ST = S.T.tocsr()
+        cp = lv.cpts.astype(bool)
+        influence = np.diff(ST.indptr)
+        for i in np.flatnonzero(~cp):
+            # an F point either influences nobody or depends strongly on a C point
+            strong = S.indices[S.indptr[i]:S.indptr[i + 1]]
+            assert influence[i] == 0 or cp[strong].any()
+        # the draws are the documented SplitMix64 stream, and the split is what they give
+        r = amg.pmis_random(0, k, lv.A.shape[0])
+        assert 0.0 <= r.min() and r.max() < 1.0
+        assert np.array_equal(amg.pmis_split(S, r), lv.cpts)
