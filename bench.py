@@ -354,6 +354,54 @@ def step_summary(args, case, r):
             "setup_s": round(r["setup_s"], 2)}
 
 
+SWEEP = {"sa": (0.0, 0.01, 0.02, 0.03, 0.04, 0.05, 0.06, 0.07),
+         "pmis": (0.25, 0.3, 0.4, 0.5, 0.6, 0.7),
+         "rs": (0.25, 0.3, 0.4, 0.5, 0.6, 0.7)}
+
+
+def bench_sweep(args):
+    """Threshold calibration on the truncated ellipsoid (Sec. 6 Test 1): for each coarsening and
+    threshold of the paper's ranges (SA: the aggregation threshold of its GAMG table; PMIS and the
+    classical first pass: the strong threshold of its BoomerAMG tables), a simulation of
+    args.sweep_steps IMEX steps from the apical stimulus; reports the mean elliptic iterations and
+    device time per step and the hierarchy.  One JSON line on stdout, a table on stderr."""
+    import torch
+
+    import bidomain_cases as bc
+    import paper_2311_13914_amd as lib
+
+    case = bc.ellipsoid_case(args.sweep_mesh)
+    prec = lib.BD_F64 if args.f64 else lib.BD_F32
+    v0 = torch.tensor(bc.ellipsoid_v0(case), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    rows = []
+    for coarsening, ths in SWEEP.items():
+        code = {"sa": lib.BD_SA, "rs": lib.BD_RS, "pmis": lib.BD_PMIS}[coarsening]
+        for th in ths:
+            opts_e = lib.bidomain_default_opts(coarsening=code, threshold=th, vcycle_precision=prec)
+            opts_p = lib.bidomain_default_opts(vcycle_precision=prec, threshold=0.0)
+            t = time.perf_counter()
+            sim = lib.bidomain_sim_create(case, v0, rtol=args.rtol, ell_opts=opts_e, par_opts=opts_p, stream=stream)
+            setup_s = time.perf_counter() - t
+            info_e = lib.bidomain_amg_info(lib.bidomain_sim_hierarchy(sim, 0))
+            rc, info = lib.bidomain_step(sim, args.sweep_steps, args.rtol, stream=stream)
+            lib.bidomain_sim_destroy(sim)
+            assert rc == lib.BD_OK, (coarsening, th, rc, info)
+            row = dict(coarsening=coarsening, threshold=th, levels=info_e["n"],
+                       operator_complexity=round(info_e["operator_complexity"], 3),
+                       it_ell_mean=round(info["it_ell"] / args.sweep_steps, 2),
+                       ms_ell_mean=round(info["ms_ell"] / args.sweep_steps, 3),
+                       it_par_mean=round(info["it_par"] / args.sweep_steps, 2), setup_s=round(setup_s, 3))
+            rows.append(row)
+            print(f"[sweep] {coarsening:4s} {th:5.2f}: it_ell {row['it_ell_mean']:6.2f}  ms_ell "
+                  f"{row['ms_ell_mean']:7.3f}  levels {row['levels']}  complexity {row['operator_complexity']}",
+                  file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "elliptic_iterations_per_step", "mode": "threshold_sweep",
+                      "workload": f"truncated ellipsoid {case.n_theta}x{case.n_phi}x{case.n_r} ({case.n} nodes)",
+                      "steps": args.sweep_steps, "dt_ms": case.dt, "rtol": args.rtol,
+                      "vcycle": "f64" if args.f64 else "f32", "rows": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,9 +416,12 @@ def main():
     ap.add_argument("--cpu-block", default="128,128,32", help="elements of the oracle's sample block")
     ap.add_argument("--no-serve", action="store_true", help="skip the bounded serving stream")
     ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C5"])
-    ap.add_argument("--mode", default="step", choices=["step", "solve", "serve"],
+    ap.add_argument("--mode", default="step", choices=["step", "solve", "serve", "sweep"],
                     help="step: Bidomain time steps (default); solve: repeated single elliptic solves; "
-                         "serve: a stream of cases through the batching server")
+                         "serve: a stream of cases through the batching server; sweep: AMG threshold "
+                         "calibration on the truncated ellipsoid")
+    ap.add_argument("--sweep-mesh", default="E1", choices=["E1", "E2"])
+    ap.add_argument("--sweep-steps", type=int, default=100, help="sweep: IMEX steps per threshold (5 ms)")
     ap.add_argument("--serve-cases", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=20)
     ap.add_argument("--rate", type=float, default=1.0, help="serve: Poisson arrival rate (cases/s)")
@@ -401,6 +452,8 @@ def main():
         return bench_solve(args)
     if args.mode == "serve":
         return bench_serve(args)
+    if args.mode == "sweep":
+        return bench_sweep(args)
     case = bc.config_case(args.workload)
     n, nnz = case.n, case.nnz27
     mixed = not args.f64

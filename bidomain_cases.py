@@ -5,9 +5,11 @@ serving arrival times -- and evaluates the initial transmembrane potential at th
 nodes. It holds none of the solver's arithmetic (no assembly, no AMG, no Krylov step),
 so both the CPU oracle and the HIP library may take their inputs from here.
 
-The paper's own workloads (a truncated-ellipsoid ventricle and a patient mesh with the
-TP06 membrane model, Sec. 3) are not reproducible here; a 1 x 1 x 0.5 cm slab with the
-paper's kind of fiber rotation (Sec. 2, eq. (2)) and a plateau stimulus stands in.
+The benchmarked workloads are slabs: a 1 x 1 x 0.5 cm slab with the paper's kind of fiber
+rotation (Sec. 2, eq. (2)) and a plateau stimulus stands in for the paper's patient mesh, and
+the TP06 membrane model is replaced by Aliev-Panfilov.  The paper's structured geometry, the
+truncated ellipsoid of Sec. 3, is also defined here (EllipsoidCase: its parameters and the
+stimulated index block; the geometry itself is computed by the oracle and by the library).
 
 Node numbering: p = i + (nx+1) * (j + (ny+1) * k), x fastest.
 """
@@ -125,6 +127,91 @@ def block_of(case: SlabCase, nx: int, ny: int, nz: int, around: int = 0) -> Slab
                    fiber_theta0=case.fiber_theta0 + case.fiber_rotation * z0 / case.Lz,
                    fiber_rotation=case.fiber_rotation * (nz * hz) / case.Lz, ellipsoids=ell,
                    name=f"{case.name or 'slab'}-block{nx}x{ny}x{nz}@{i0},{j0},{k0}")
+
+
+@dataclass(frozen=True)
+class EllipsoidCase:
+    """One Bidomain case on the truncated ellipsoid of Sec. 3 (eq. (8), Table 1), n_theta x n_phi
+    x n_r elements, periodic in theta.  Units as for SlabCase; conductivities, membrane and time
+    step as for the slab.
+
+    Node numbering: p = i + n_theta * (j + (n_phi + 1) * k), theta fastest, r slowest (k = 0 is
+    the endocardium)."""
+
+    n_theta: int
+    n_phi: int
+    n_r: int
+    a1: float = 2.2
+    a2: float = 3.3
+    b1: float = 2.2
+    b2: float = 3.3
+    c1: float = 5.9
+    c2: float = 6.4
+    theta_min: float = -1.5 * math.pi
+    theta_max: float = 0.5 * math.pi
+    phi_min: float = -0.375 * math.pi
+    phi_max: float = 0.125 * math.pi
+    sig_il: float = 3.0e-3
+    sig_it: float = 3.1525e-4
+    sig_el: float = 2.0e-3
+    sig_et: float = 1.3514e-3
+    # fiber angle from the theta direction towards the phi direction: +60 deg at the
+    # endocardium (r = 0), -60 deg at the epicardium (r = 1)
+    fiber_endo: float = math.pi / 3.0
+    fiber_epi: float = -math.pi / 3.0
+    cm: float = 1.0
+    dt: float = 0.05
+    ap_k: float = 8.0
+    ap_a: float = 0.15
+    ap_eps0: float = 0.002
+    ap_mu1: float = 0.2
+    ap_mu2: float = 0.3
+    ap_t_unit: float = 12.9
+    ap_v_scale: float = 105.0
+    ap_v_rest: float = -85.0
+    v_rest: float = -85.0
+    v_plateau: float = 20.0
+    # stimulated block in index fractions: theta [s0, s1), phi [s2, s3], r [s4, s5] -- an
+    # endocardial patch near the apex (phi_min is the apical end)
+    stim: Tuple[float, float, float, float, float, float] = (0.0, 0.125, 0.0, 0.25, 0.0, 0.25)
+    name: str = ""
+
+    @property
+    def n(self) -> int:
+        return self.n_theta * (self.n_phi + 1) * (self.n_r + 1)
+
+    @property
+    def nnz27(self) -> int:
+        return 3 * self.n_theta * (3 * self.n_phi + 1) * (3 * self.n_r + 1)
+
+    @property
+    def paper_dofs(self) -> int:
+        return 2 * self.n
+
+
+# The paper's structured meshes (elements n_theta x n_phi x n_r): the threshold-calibration mesh
+# of Test 1 and the strong-scaling mesh of Test 2.
+ELLIPSOID_CONFIGS = {
+    "E1": dict(n_theta=32, n_phi=32, n_r=16),
+    "E2": dict(n_theta=128, n_phi=128, n_r=64),
+}
+
+
+def ellipsoid_case(name: str, **kw) -> EllipsoidCase:
+    return EllipsoidCase(name=name, **{**ELLIPSOID_CONFIGS[name], **kw})
+
+
+def ellipsoid_v0(case: EllipsoidCase) -> np.ndarray:
+    """Initial transmembrane potential: v_plateau on the stimulated index block, v_rest elsewhere."""
+    s0, s1, s2, s3, s4, s5 = case.stim
+    i = np.arange(case.n_theta) / case.n_theta
+    j = np.arange(case.n_phi + 1) / case.n_phi
+    k = np.arange(case.n_r + 1) / case.n_r
+    K, J, I = np.meshgrid(k, j, i, indexing="ij")
+    inside = (I >= s0) & (I < s1) & (J >= s2) & (J <= s3) & (K >= s4) & (K <= s5)
+    v = np.full(case.n, case.v_rest, dtype=np.float64)
+    v[inside.ravel()] = case.v_plateau
+    return v
 
 
 def node_coordinates(case: SlabCase):

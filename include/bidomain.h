@@ -258,6 +258,44 @@ enum { BD_MAT_AI = 0, BD_MAT_AE = 1, BD_MAT_AELL = 2, BD_MAT_APAR = 3 };
 int bidomain_slab_assemble(const bd_slab* s, int which, int32_t* row_ptr, int32_t* col_idx,
                            double* val, double* mass);
 
+/* ---- the truncated ellipsoid (idealised left ventricle) ----------------------------------- */
+/*
+ * The structured geometry of Sec. 3, eq. (8) with the axes of Table 1 (a1 = b1 = 2.2,
+ * a2 = b2 = 3.3, c1 = 5.9, c2 = 6.4 cm; theta in [-3 pi/2, pi/2], phi in [-3 pi/8, pi/8]):
+ *   x = a(r) cos(theta) cos(phi),  y = b(r) sin(theta) cos(phi),  z = c(r) sin(phi),
+ * a(r) = a1 + r (a2 - a1) and likewise b, c; r in [0, 1] runs from the endocardium to the
+ * epicardium.  (Eq. (8) prints cos(theta) sin(phi) for y; the ellipsoid has sin(theta) cos(phi).)
+ * theta spans one full period (theta_max - theta_min = 2 pi, else BD_E_INVALID), so the mesh of
+ * n_theta x n_phi x n_r isoparametric trilinear elements is periodic in theta and has
+ * n = n_theta (n_phi + 1)(n_r + 1) nodes, p = i + n_theta (j + (n_phi + 1) k) at
+ * (theta_i, phi_j, r_k) on uniform grids; n_theta >= 3, n_phi >= 1, n_r >= 1, and
+ * -pi/2 < phi_min < phi_max < pi/2.  Fibers lie in the tangent plane of the r-surfaces at angle
+ * alpha(r) = fiber_endo + r (fiber_epi - fiber_endo) from the theta direction towards the phi
+ * direction (the paper's rotation: counterclockwise from epi- to endocardium, e.g. -60 deg at
+ * the epicardium to +60 deg at the endocardium); conductivities, cm, dt and the Aliev-Panfilov
+ * parameters mean what they mean in bd_slab and are validated the same way.
+ */
+typedef struct {
+  int32_t n_theta, n_phi, n_r;
+  double a1, a2, b1, b2, c1, c2;
+  double theta_min, theta_max, phi_min, phi_max;
+  double sig_il, sig_it, sig_el, sig_et;
+  double fiber_endo, fiber_epi;
+  double cm, dt;
+  double ap_k, ap_a, ap_eps0, ap_mu1, ap_mu2, ap_t_unit, ap_v_scale, ap_v_rest;
+} bd_ellipsoid;
+
+/*
+ * Assemble one ellipsoid operator on the host (which as for the slab), 2x2x2 Gauss points on
+ * the reference cube with the fiber taken at each point's parameters, lumped mass = integral of
+ * each basis function.  Full 27-point pattern with structural zeros, columns sorted; caller-owned
+ * host buffers of n + 1 (row_ptr), nnz = 3 n_theta (3 n_phi + 1)(3 n_r + 1) (col_idx, val) and
+ * n (mass, may be NULL) entries.  An element whose interpolated geometry has a non-positive
+ * Jacobian at a Gauss point (axes that shrink from endo- to epicardium, say) is BD_E_INVALID.
+ */
+int bidomain_ellipsoid_assemble(const bd_ellipsoid* e, int which, int32_t* row_ptr, int32_t* col_idx,
+                                double* val, double* mass);
+
 typedef struct bd_sim bd_sim;
 
 typedef struct {
@@ -280,6 +318,10 @@ typedef struct {
 int bidomain_sim_create(const bd_slab* s, const bd_amg_opts* ell, const bd_amg_opts* par,
                         const double* v0_dev, const double* w0_dev, double rtol, void* stream,
                         bd_sim** out);
+/* The same on the truncated ellipsoid (bidomain_ellipsoid_assemble's operators). */
+int bidomain_ellipsoid_sim_create(const bd_ellipsoid* e, const bd_amg_opts* ell, const bd_amg_opts* par,
+                                  const double* v0_dev, const double* w0_dev, double rtol, void* stream,
+                                  bd_sim** out);
 
 /*
  * Advance nsteps IMEX steps (eqs. (4)-(7)): Aliev-Panfilov membrane update, parabolic solve

@@ -25,7 +25,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import amg, fem, krylov
+from . import amg, ellipsoid, fem, krylov
 
 AP_K = 8.0
 AP_A = 0.15
@@ -78,8 +78,14 @@ def _solve(A, f, h, x0, rtol, m, mixed):
     return krylov.amg_pcg(A, f, h, x0=x0, rtol=rtol, m=m)
 
 
-def create(case, v0, w0=None, rtol=1e-8, ell_opts=None, par_opts=None, mixed=False):
-    ops = fem.assemble_operators(case)
+def assemble(case):
+    """The case's operators: the truncated ellipsoid (a case with n_theta) or the slab."""
+    return ellipsoid.assemble_operators(case) if hasattr(case, "n_theta") else fem.assemble_operators(case)
+
+
+def create(case, v0, w0=None, rtol=1e-8, ell_opts=None, par_opts=None, mixed=False, ops=None):
+    """ops: the case's operators when already assembled (assemble(case))."""
+    ops = ops if ops is not None else assemble(case)
     ell_opts = ell_opts or amg.AMGOptions(nullspace=True)
     par_opts = par_opts or amg.AMGOptions(nullspace=False, threshold=0.0)
     h_ell = amg.setup(ops["Aell"], ell_opts)

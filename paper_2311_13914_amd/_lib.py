@@ -71,6 +71,14 @@ class bd_slab(C.Structure):
                 ("ap_v_scale", C.c_double), ("ap_v_rest", C.c_double)]
 
 
+class bd_ellipsoid(C.Structure):
+    _fields_ = [("n_theta", C.c_int32), ("n_phi", C.c_int32), ("n_r", C.c_int32)] + \
+        [(f, C.c_double) for f in ("a1", "a2", "b1", "b2", "c1", "c2", "theta_min", "theta_max", "phi_min",
+                                   "phi_max", "sig_il", "sig_it", "sig_el", "sig_et", "fiber_endo", "fiber_epi",
+                                   "cm", "dt", "ap_k", "ap_a", "ap_eps0", "ap_mu1", "ap_mu2", "ap_t_unit",
+                                   "ap_v_scale", "ap_v_rest")]
+
+
 class bd_step_info(C.Structure):
     _fields_ = [("steps", C.c_int32), ("it_par", C.c_int32), ("it_ell", C.c_int32), ("ms_memb", C.c_double),
                 ("ms_par", C.c_double), ("ms_ell", C.c_double), ("rel_res_par", C.c_double),
@@ -109,6 +117,10 @@ _SIGS = {
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "bidomain_sim_create": (C.c_int, [C.POINTER(bd_slab), C.POINTER(bd_amg_opts), C.POINTER(bd_amg_opts), _vp, _vp,
                                       C.c_double, _vp, C.POINTER(_vp)]),
+    "bidomain_ellipsoid_assemble": (C.c_int, [C.POINTER(bd_ellipsoid), C.c_int, C.POINTER(C.c_int32),
+                                              C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "bidomain_ellipsoid_sim_create": (C.c_int, [C.POINTER(bd_ellipsoid), C.POINTER(bd_amg_opts),
+                                                C.POINTER(bd_amg_opts), _vp, _vp, C.c_double, _vp, C.POINTER(_vp)]),
     "bidomain_step": (C.c_int, [_vp, C.c_int, C.c_double, _vp, C.POINTER(bd_step_info)]),
     "bidomain_sim_get": (C.c_int, [_vp, C.c_int, _vp, _vp]),
     "bidomain_sim_hierarchy": (_vp, [_vp, C.c_int]),
@@ -208,6 +220,11 @@ def bidomain_default_opts(**overrides) -> bd_amg_opts:
 def make_slab(case) -> bd_slab:
     """A bd_slab from any object with the slab attributes (nx, ny, nz, Lx, ..., cm, dt)."""
     return bd_slab(*(getattr(case, f[0]) for f in bd_slab._fields_))
+
+
+def make_ellipsoid(case) -> bd_ellipsoid:
+    """A bd_ellipsoid from any object with its attributes (n_theta, n_phi, n_r, a1, ..., ap_v_rest)."""
+    return bd_ellipsoid(*(getattr(case, f[0]) for f in bd_ellipsoid._fields_))
 
 
 # ---- hierarchy ---------------------------------------------------------------------------
@@ -346,15 +363,34 @@ def bidomain_slab_assemble(case, which: int):
     return rp, ci, v, m
 
 
+def bidomain_ellipsoid_assemble(case, which: int):
+    e = make_ellipsoid(case)
+    n = e.n_theta * (e.n_phi + 1) * (e.n_r + 1)
+    nnz = 3 * e.n_theta * (3 * e.n_phi + 1) * (3 * e.n_r + 1)
+    rp = np.empty(n + 1, np.int32)
+    ci = np.empty(nnz, np.int32)
+    v = np.empty(nnz, np.float64)
+    m = np.empty(n, np.float64)
+    _check(load().bidomain_ellipsoid_assemble(C.byref(e), which, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              ci.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              v.ctypes.data_as(C.POINTER(C.c_double)),
+                                              m.ctypes.data_as(C.POINTER(C.c_double))),
+           "bidomain_ellipsoid_assemble")
+    return rp, ci, v, m
+
+
 def bidomain_sim_create(case, v0, w0=None, rtol: float = 1e-8, ell_opts=None, par_opts=None, stream=None):
-    s = make_slab(case)
-    n = (s.nx + 1) * (s.ny + 1) * (s.nz + 1)
+    """A simulation of a slab case, or of an ellipsoid case (a case with n_theta)."""
+    ellipsoid = hasattr(case, "n_theta")
+    s = make_ellipsoid(case) if ellipsoid else make_slab(case)
+    n = case.n_theta * (case.n_phi + 1) * (case.n_r + 1) if ellipsoid else (s.nx + 1) * (s.ny + 1) * (s.nz + 1)
     pv = _dev(v0, "float64", n, "v0")
     pw = _dev(w0, "float64", n, "w0") if w0 is not None else None
     out = _vp()
-    _check(load().bidomain_sim_create(C.byref(s), C.byref(ell_opts) if ell_opts else None,
-                                      C.byref(par_opts) if par_opts else None, pv, pw, float(rtol),
-                                      _stream(stream), C.byref(out)), "bidomain_sim_create")
+    fn = load().bidomain_ellipsoid_sim_create if ellipsoid else load().bidomain_sim_create
+    _check(fn(C.byref(s), C.byref(ell_opts) if ell_opts else None, C.byref(par_opts) if par_opts else None, pv, pw,
+              float(rtol), _stream(stream), C.byref(out)),
+           "bidomain_ellipsoid_sim_create" if ellipsoid else "bidomain_sim_create")
     return out.value
 
 

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libbidomain.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-HOST_SOURCES = ["host_assemble.cpp", "host_amg.cpp"]
+HOST_SOURCES = ["host_assemble.cpp", "host_ellipsoid.cpp", "host_amg.cpp"]
 HIP_SOURCES = ["device.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -66,4 +66,11 @@ void assemble_slab_stiffness(const bd_slab& s, double sig_l, double sig_t, Csr& 
 void slab_lumped_mass(const bd_slab& s, std::vector<double>& m);
 int64_t slab_nodes(const bd_slab& s);
 
+// Q1 operators of the theta-periodic truncated ellipsoid (isoparametric, 27-point pattern,
+// structural zeros kept).  Returns false if an element's interpolated geometry has a non-positive
+// Jacobian at a Gauss point.  mass (may be null): integral of each basis function.
+bool assemble_ellipsoid(const bd_ellipsoid& e, double sig_l, double sig_t, Csr& A, std::vector<double>* mass);
+int64_t ellipsoid_nodes(const bd_ellipsoid& e);
+int64_t ellipsoid_nnz(const bd_ellipsoid& e);
+
 }  // namespace bd

@@ -1024,10 +1024,31 @@ int pcg(bd_amg* h, const Solve& sv, const double* b, double* x, int guess, doubl
 
 }  // namespace bd
 
+namespace bd {
+// Aliev-Panfilov parameters of a case (bd_slab, bd_ellipsoid; published values k = 8, a = 0.15,
+// eps0 = 0.002, mu1 = 0.2, mu2 = 0.3, one model time unit = 12.9 ms, u = (v + 85) / 105).
+struct ApParams {
+  double k, a, eps0, mu1, mu2, t_unit, v_scale, v_rest;
+};
+template <typename Case>
+inline ApParams ap_params(const Case& s) {
+  return ApParams{s.ap_k, s.ap_a, s.ap_eps0, s.ap_mu1, s.ap_mu2, s.ap_t_unit, s.ap_v_scale, s.ap_v_rest};
+}
+// What a time step needs of a case beyond its operators.
+struct SimPhysics {
+  double cm = 0, dt = 0;
+  ApParams ap{};
+};
+template <typename Case>
+inline SimPhysics sim_physics(const Case& s) {
+  return SimPhysics{s.cm, s.dt, ap_params(s)};
+}
+}  // namespace bd
+
 // ==========================================================================================
 // Simulation handle.
 struct bd_sim {
-  bd_slab s{};
+  bd::SimPhysics ph{};
   int n = 0;
   bd_amg* hell = nullptr;
   bd_amg* hpar = nullptr;
@@ -1042,14 +1063,6 @@ struct bd_sim {
 
 namespace bd {
 
-// Aliev-Panfilov parameters of the slab (bd_slab; published values k = 8, a = 0.15,
-// eps0 = 0.002, mu1 = 0.2, mu2 = 0.3, one model time unit = 12.9 ms, u = (v + 85) / 105).
-struct ApParams {
-  double k, a, eps0, mu1, mu2, t_unit, v_scale, v_rest;
-};
-inline ApParams ap_params(const bd_slab& s) {
-  return ApParams{s.ap_k, s.ap_a, s.ap_eps0, s.ap_mu1, s.ap_mu2, s.ap_t_unit, s.ap_v_scale, s.ap_v_rest};
-}
 
 // One membrane step and the parabolic right-hand side (eqs. (4), (7)):
 //   w <- (w + dt' eps (-k u (u - a - 1))) / (1 + dt' eps),   eps = eps0 + mu1 w / (u + mu2),
@@ -1343,7 +1356,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
 // half the free device memory, each first reserved from `tb` when given (a server counts them
 // against its budget while the setup runs on a worker thread).
 struct SimHost {
-  bd_slab s{};
+  SimPhysics ph{};
   Csr Ai;
   std::vector<double> m;
   bd_amg* hell = nullptr;
@@ -1354,23 +1367,21 @@ struct SimHost {
   }
 };
 
-std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell, const bd_amg_opts* par,
-                                        bool device_galerkin, const TransientBudget* tb = nullptr) {
+// Hierarchies of a case from its assembled A_i, A_e (same pattern) and lumped mass.
+std::unique_ptr<SimHost> build_sim_host_ops(Csr Ai, const Csr& Ae, std::vector<double> m, const SimPhysics& ph,
+                                            const bd_amg_opts* ell, const bd_amg_opts* par, bool device_galerkin,
+                                            const TransientBudget* tb) {
   std::unique_ptr<SimHost> H(new SimHost());
-  H->s = s;
-  const int n = (int)slab_nodes(s);
-  const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
-  const auto t0 = std::chrono::steady_clock::now();
-  Csr Ae;
-  assemble_slab_stiffness(s, s.sig_il, s.sig_it, H->Ai);
-  assemble_slab_stiffness(s, s.sig_el, s.sig_et, Ae);
-  slab_lumped_mass(s, H->m);
+  H->ph = ph;
+  H->Ai = std::move(Ai);
+  H->m = std::move(m);
+  const int n = H->Ai.nrows;
   Csr Aell = H->Ai, Apar = H->Ai;
 #pragma omp parallel for schedule(static, 4096)
   for (int32_t i = 0; i < n; ++i)
     for (int32_t k = Aell.rp[i]; k < Aell.rp[i + 1]; ++k) {
       Aell.v[k] += Ae.v[k];
-      if (Apar.ci[k] == i) Apar.v[k] += s.cm / s.dt * H->m[i];
+      if (Apar.ci[k] == i) Apar.v[k] += ph.cm / ph.dt * H->m[i];
     }
   bd_amg_opts oe, op;
   bidomain_default_opts(&oe);
@@ -1380,9 +1391,6 @@ std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell
   if (par) op = *par;
   oe.nullspace = BD_NULL_CONSTANT;
   op.nullspace = BD_NULL_NONE;
-  if (log)
-    std::fprintf(stderr, "[setup] slab operators assembled: %.2f s\n",
-                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
   bd_csr ce{n, Aell.nnz(), Aell.rp.data(), Aell.ci.data(), Aell.v.data()};
   bd_csr cp{n, Apar.nnz(), Apar.rp.data(), Apar.ci.data(), Apar.v.data()};
   setup_impl(&ce, &oe, nullptr, nullptr, &H->hell, true, device_galerkin, true, tb);
@@ -1390,13 +1398,28 @@ std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell
   return H;
 }
 
+std::unique_ptr<SimHost> build_sim_host(const bd_slab& s, const bd_amg_opts* ell, const bd_amg_opts* par,
+                                        bool device_galerkin, const TransientBudget* tb = nullptr) {
+  const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  Csr Ai, Ae;
+  std::vector<double> m;
+  assemble_slab_stiffness(s, s.sig_il, s.sig_it, Ai);
+  assemble_slab_stiffness(s, s.sig_el, s.sig_et, Ae);
+  slab_lumped_mass(s, m);
+  if (log)
+    std::fprintf(stderr, "[setup] slab operators assembled: %.2f s\n",
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  return build_sim_host_ops(std::move(Ai), Ae, std::move(m), sim_physics(s), ell, par, device_galerkin, tb);
+}
+
 // Device half: hierarchies, A_i, the lumped mass and the state vectors in HBM (takes the
 // hierarchies from H).  v0 / w0: n doubles on the device or the host (w0 may be null: w = 0).
 std::unique_ptr<bd_sim> upload_sim(SimHost& H, const double* v0, bool v0_dev, const double* w0, bool w0_dev,
                                    hipStream_t st) {
   std::unique_ptr<bd_sim> S(new bd_sim());
-  S->s = H.s;
-  S->n = (int)slab_nodes(H.s);
+  S->ph = H.ph;
+  S->n = H.Ai.nrows;
   const int n = S->n;
   S->hell = H.hell;
   S->hpar = H.hpar;
@@ -1632,17 +1655,77 @@ static int64_t bd_slab_nnz27(const bd_slab* s) {
   return (int64_t)(3 * s->nx + 1) * (3 * s->ny + 1) * (3 * s->nz + 1);
 }
 
+static void check_membrane(const bd::ApParams& p, const char* what) {
+  if (!(p.k > 0) || !(p.eps0 > 0) || !(p.mu2 > 0) || !(p.t_unit > 0) || !(p.v_scale > 0) || !std::isfinite(p.k) ||
+      !std::isfinite(p.a) || !std::isfinite(p.eps0) || !std::isfinite(p.mu1) || !std::isfinite(p.mu2) ||
+      !std::isfinite(p.t_unit) || !std::isfinite(p.v_scale) || !std::isfinite(p.v_rest))
+    throw Failure{BD_E_INVALID, std::string("invalid Aliev-Panfilov parameters in the ") + what + " description"};
+}
+
 static void check_slab(const bd_slab* s) {
   if (!s || s->nx < 1 || s->ny < 1 || s->nz < 1 || !(s->Lx > 0) || !(s->Ly > 0) || !(s->Lz > 0) || !(s->dt > 0) ||
       !(s->cm > 0) || !(s->sig_it > 0) || !(s->sig_il > 0) || !(s->sig_et > 0) || !(s->sig_el > 0))
     throw Failure{BD_E_INVALID, "invalid slab description"};
-  if (!(s->ap_k > 0) || !(s->ap_eps0 > 0) || !(s->ap_mu2 > 0) || !(s->ap_t_unit > 0) || !(s->ap_v_scale > 0) ||
-      !std::isfinite(s->ap_k) || !std::isfinite(s->ap_a) || !std::isfinite(s->ap_eps0) || !std::isfinite(s->ap_mu1) ||
-      !std::isfinite(s->ap_mu2) || !std::isfinite(s->ap_t_unit) || !std::isfinite(s->ap_v_scale) ||
-      !std::isfinite(s->ap_v_rest))
-    throw Failure{BD_E_INVALID, "invalid Aliev-Panfilov parameters in the slab description"};
+  check_membrane(ap_params(*s), "slab");
   if (bd::slab_nodes(*s) > INT32_MAX || bd_slab_nnz27(s) > INT32_MAX)
     throw Failure{BD_E_INVALID, "slab too large for 32-bit CSR indices"};
+}
+
+static void check_ellipsoid(const bd_ellipsoid* e) {
+  const double pi = 3.14159265358979323846;
+  auto finite_pos = [](double v) { return std::isfinite(v) && v > 0; };
+  if (!e || e->n_theta < 3 || e->n_phi < 1 || e->n_r < 1 || !finite_pos(e->a1) || !finite_pos(e->a2) ||
+      !finite_pos(e->b1) || !finite_pos(e->b2) || !finite_pos(e->c1) || !finite_pos(e->c2) || !finite_pos(e->dt) ||
+      !finite_pos(e->cm) || !finite_pos(e->sig_il) || !finite_pos(e->sig_it) || !finite_pos(e->sig_el) ||
+      !finite_pos(e->sig_et) || !std::isfinite(e->fiber_endo) || !std::isfinite(e->fiber_epi) ||
+      !std::isfinite(e->theta_min) || !std::isfinite(e->theta_max))
+    throw Failure{BD_E_INVALID, "invalid ellipsoid description"};
+  if (!(std::fabs((e->theta_max - e->theta_min) - 2 * pi) <= 1e-12 * 2 * pi))
+    throw Failure{BD_E_INVALID, "the ellipsoid mesh is periodic in theta: theta_max - theta_min must be 2 pi"};
+  if (!(e->phi_min > -0.5 * pi && e->phi_min < e->phi_max && e->phi_max < 0.5 * pi))
+    throw Failure{BD_E_INVALID, "ellipsoid phi range must satisfy -pi/2 < phi_min < phi_max < pi/2"};
+  check_membrane(ap_params(*e), "ellipsoid");
+  if (bd::ellipsoid_nodes(*e) > INT32_MAX || bd::ellipsoid_nnz(*e) > INT32_MAX)
+    throw Failure{BD_E_INVALID, "ellipsoid too large for 32-bit CSR indices"};
+}
+
+static void ellipsoid_operator(const bd_ellipsoid& e, double sl, double st, Csr& A, std::vector<double>* m) {
+  if (!bd::assemble_ellipsoid(e, sl, st, A, m))
+    throw Failure{BD_E_INVALID, "ellipsoid element with a non-positive Jacobian"};
+}
+
+// A_i, A_e and the lumped mass: one of the operators the assemble calls return.
+static void pick_operator(int which, Csr&& Ai, const Csr& Ae, const std::vector<double>& m, double cm, double dt,
+                          int32_t* row_ptr, int32_t* col_idx, double* val) {
+  Csr A = std::move(Ai);
+  if (which == BD_MAT_AE) {
+    A.v = Ae.v;
+  } else if (which == BD_MAT_AELL) {
+    for (size_t k = 0; k < A.v.size(); ++k) A.v[k] += Ae.v[k];
+  } else if (which == BD_MAT_APAR) {
+    for (int32_t i = 0; i < A.nrows; ++i)
+      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+        if (A.ci[k] == i) A.v[k] += cm / dt * m[i];
+  }
+  std::copy(A.rp.begin(), A.rp.end(), row_ptr);
+  std::copy(A.ci.begin(), A.ci.end(), col_idx);
+  std::copy(A.v.begin(), A.v.end(), val);
+}
+
+int bidomain_ellipsoid_assemble(const bd_ellipsoid* e, int which, int32_t* row_ptr, int32_t* col_idx, double* val,
+                                double* mass) {
+  return guarded([&] {
+    check_ellipsoid(e);
+    if (which < BD_MAT_AI || which > BD_MAT_APAR || !row_ptr || !col_idx || !val)
+      throw Failure{BD_E_INVALID, "invalid assemble arguments"};
+    Csr Ai, Ae;
+    std::vector<double> m;
+    ellipsoid_operator(*e, e->sig_il, e->sig_it, Ai, &m);
+    if (which == BD_MAT_AE || which == BD_MAT_AELL) ellipsoid_operator(*e, e->sig_el, e->sig_et, Ae, nullptr);
+    pick_operator(which, std::move(Ai), Ae, m, e->cm, e->dt, row_ptr, col_idx, val);
+    if (mass) std::copy(m.begin(), m.end(), mass);
+    return BD_OK;
+  });
 }
 
 int bidomain_slab_assemble(const bd_slab* s, int which, int32_t* row_ptr, int32_t* col_idx, double* val,
@@ -1651,26 +1734,12 @@ int bidomain_slab_assemble(const bd_slab* s, int which, int32_t* row_ptr, int32_
     check_slab(s);
     if (which < BD_MAT_AI || which > BD_MAT_APAR || !row_ptr || !col_idx || !val)
       throw Failure{BD_E_INVALID, "invalid assemble arguments"};
-    Csr A;
+    Csr Ai, Ae;
     std::vector<double> m;
     slab_lumped_mass(*s, m);
-    if (which == BD_MAT_AE) {
-      assemble_slab_stiffness(*s, s->sig_el, s->sig_et, A);
-    } else {
-      assemble_slab_stiffness(*s, s->sig_il, s->sig_it, A);
-      if (which == BD_MAT_AELL) {
-        Csr E;
-        assemble_slab_stiffness(*s, s->sig_el, s->sig_et, E);
-        for (size_t k = 0; k < A.v.size(); ++k) A.v[k] += E.v[k];
-      } else if (which == BD_MAT_APAR) {
-        for (int32_t i = 0; i < A.nrows; ++i)
-          for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-            if (A.ci[k] == i) A.v[k] += s->cm / s->dt * m[i];
-      }
-    }
-    std::copy(A.rp.begin(), A.rp.end(), row_ptr);
-    std::copy(A.ci.begin(), A.ci.end(), col_idx);
-    std::copy(A.v.begin(), A.v.end(), val);
+    assemble_slab_stiffness(*s, s->sig_il, s->sig_it, Ai);
+    if (which == BD_MAT_AE || which == BD_MAT_AELL) assemble_slab_stiffness(*s, s->sig_el, s->sig_et, Ae);
+    pick_operator(which, std::move(Ai), Ae, m, s->cm, s->dt, row_ptr, col_idx, val);
     if (mass) std::copy(m.begin(), m.end(), mass);
     return BD_OK;
   });
@@ -1681,9 +1750,9 @@ static void launch_membrane(bd_sim* S, hipStream_t st) {
   const int rpt = kBlock / G;
   const int nb = (S->n + rpt - 1) / rpt;
   switch (G) {
-    case 4: k_membrane_rhs<4><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, ap_params(S->s), S->n); break;
-    case 8: k_membrane_rhs<8><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, ap_params(S->s), S->n); break;
-    default: k_membrane_rhs<16><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->s.dt, S->s.cm, ap_params(S->s), S->n); break;
+    case 4: k_membrane_rhs<4><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->ph.dt, S->ph.cm, S->ph.ap, S->n); break;
+    case 8: k_membrane_rhs<8><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->ph.dt, S->ph.cm, S->ph.ap, S->n); break;
+    default: k_membrane_rhs<16><<<nb, kBlock, 0, st>>>(S->Ai.rp, S->Ai.ci, S->Ai.v, S->ue, S->v, S->w, S->m, S->rhs, S->ph.dt, S->ph.cm, S->ph.ap, S->n); break;
   }
   HIPCHK(hipGetLastError());
 }
@@ -1700,22 +1769,42 @@ static void launch_neg_spmv(bd_sim* S, const double* x, double* y, hipStream_t s
   HIPCHK(hipGetLastError());
 }
 
+// Uploads a case's hierarchies and state and solves for u_e^0 from v^0 (eq. (6)).
+static int start_sim(SimHost& H, const double* v0_dev, const double* w0_dev, double rtol, hipStream_t st,
+                     bd_sim** out) {
+  std::unique_ptr<bd_sim> S = upload_sim(H, v0_dev, true, w0_dev, true, st);
+  launch_neg_spmv(S.get(), S->v, S->fell, st);
+  bd_solve_info inf;
+  const int rc = S->hell->mixed ? pcg<float>(S->hell, S->hell->sv, S->fell, S->ue, 0, rtol, 1000, st, &inf)
+                                : pcg<double>(S->hell, S->hell->sv, S->fell, S->ue, 0, rtol, 1000, st, &inf);
+  if (rc < 0) return rc;
+  *out = S.release();
+  return BD_OK;
+}
+
 int bidomain_sim_create(const bd_slab* s, const bd_amg_opts* ell, const bd_amg_opts* par, const double* v0_dev,
                         const double* w0_dev, double rtol, void* stream, bd_sim** out) {
   return guarded([&] {
     check_slab(s);
     if (!v0_dev || !out || !(rtol > 0)) throw Failure{BD_E_INVALID, "invalid simulation arguments"};
-    hipStream_t st = (hipStream_t)stream;
     std::unique_ptr<SimHost> H = build_sim_host(*s, ell, par, true);
-    std::unique_ptr<bd_sim> S = upload_sim(*H, v0_dev, true, w0_dev, true, st);
-    // u_e^0 from v^0 (eq. (6))
-    launch_neg_spmv(S.get(), S->v, S->fell, st);
-    bd_solve_info inf;
-    const int rc = S->hell->mixed ? pcg<float>(S->hell, S->hell->sv, S->fell, S->ue, 0, rtol, 1000, st, &inf)
-                                  : pcg<double>(S->hell, S->hell->sv, S->fell, S->ue, 0, rtol, 1000, st, &inf);
-    if (rc < 0) return rc;
-    *out = S.release();
-    return BD_OK;
+    return start_sim(*H, v0_dev, w0_dev, rtol, (hipStream_t)stream, out);
+  });
+}
+
+int bidomain_ellipsoid_sim_create(const bd_ellipsoid* e, const bd_amg_opts* ell, const bd_amg_opts* par,
+                                  const double* v0_dev, const double* w0_dev, double rtol, void* stream,
+                                  bd_sim** out) {
+  return guarded([&] {
+    check_ellipsoid(e);
+    if (!v0_dev || !out || !(rtol > 0)) throw Failure{BD_E_INVALID, "invalid simulation arguments"};
+    Csr Ai, Ae;
+    std::vector<double> m;
+    ellipsoid_operator(*e, e->sig_il, e->sig_it, Ai, &m);
+    ellipsoid_operator(*e, e->sig_el, e->sig_et, Ae, nullptr);
+    std::unique_ptr<SimHost> H =
+        build_sim_host_ops(std::move(Ai), Ae, std::move(m), sim_physics(*e), ell, par, true, nullptr);
+    return start_sim(*H, v0_dev, w0_dev, rtol, (hipStream_t)stream, out);
   });
 }
 

@@ -156,3 +156,43 @@ def test_host_code_under_address_and_undefined_behaviour_sanitizers():
     res = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
     assert res.returncode == 0, res.stdout[-2000:] + res.stderr[-4000:]
     assert "host check ok" in res.stdout
+
+
+@pytest.mark.parametrize("dims", [(3, 1, 1), (8, 6, 3), (13, 7, 4)])
+def test_host_ellipsoid_assembly_matches_oracle(dims):
+    from oracle import ellipsoid
+    c = bc.EllipsoidCase(*dims)
+    ops = ellipsoid.assemble_operators(c)
+    for which, key in ((lib.BD_MAT_AI, "Ai"), (lib.BD_MAT_AE, "Ae"), (lib.BD_MAT_AELL, "Aell"),
+                       (lib.BD_MAT_APAR, "Apar")):
+        rp, ci, v, m = lib.bidomain_ellipsoid_assemble(c, which)
+        A = ops[key]
+        assert np.array_equal(rp, A.indptr) and np.array_equal(ci, A.indices)
+        assert np.max(np.abs(v - A.data)) <= 1e-14 * np.max(np.abs(A.data))
+        np.testing.assert_allclose(m, ops["m"], rtol=1e-13)
+
+
+def test_host_ellipsoid_setup_matches_oracle():
+    """The SA hierarchy of the periodic mesh (its seam makes the fine level a CSR-stream matrix
+    rather than a diagonal-form one)."""
+    from oracle import ellipsoid
+    c = bc.EllipsoidCase(16, 12, 6)
+    A = ellipsoid.assemble_operators(c)["Aell"]
+    h_or = amg.setup(A, amg.AMGOptions(nullspace=True))
+    h = lib.bidomain_amg_build_host(A, lib.bidomain_default_opts(nullspace=1))
+    try:
+        _compare_hierarchies(h, h_or)
+    finally:
+        lib.bidomain_amg_destroy(h)
+
+
+@pytest.mark.parametrize("change", [dict(n_theta=2), dict(n_phi=0), dict(theta_max=0.4 * np.pi),
+                                    dict(phi_min=-0.5 * np.pi), dict(phi_max=-0.4 * np.pi), dict(a1=0.0),
+                                    dict(sig_it=-1.0), dict(ap_mu2=0.0), dict(dt=float("nan")),
+                                    dict(a1=3.3, a2=0.5, b1=3.3, b2=0.5, c1=6.4, c2=0.6)])
+def test_invalid_ellipsoids_are_rejected(change):
+    from dataclasses import replace
+    c = replace(bc.EllipsoidCase(6, 4, 2), **change)
+    with pytest.raises(lib.BidomainError) as e:
+        lib.bidomain_ellipsoid_assemble(c, lib.BD_MAT_AELL)
+    assert e.value.status == lib.BD_E_INVALID
