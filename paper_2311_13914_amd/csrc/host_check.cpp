@@ -1,7 +1,7 @@
 // Host-side self-check of the library's setup code (Q1 assembly and the AMG setup phase), built
 // with AddressSanitizer and UndefinedBehaviorSanitizer by `python -m paper_2311_13914_amd.build
 // --host-check`: every host routine runs on small and ragged slabs with each coarsening,
-// smoother and null-space option, and the results are checked against the identities they
+// smoother and null-space option, and on small periodic ellipsoid meshes, and the results are checked against the identities they
 // must satisfy (exact symmetry, zero row sums of the stiffness, the lumped mass summing to the
 // volume, R = P^T, P B_c = B and A_c B_c = 0 for smoothed aggregation, P 1 = 1 on zero-row-sum
 // rows for classical coarsening).  Exit status 0 when every check passes.
@@ -128,7 +128,7 @@ int main() {
         Aell.v[k] += Ae.v[k];
         if (Apar.ci[k] == i) Apar.v[k] += s.cm / s.dt * m[i];
       }
-    for (int variant = 0; variant < 5; ++variant) {
+    for (int variant = 0; variant < 6; ++variant) {
       bd_amg_opts o;
       bidomain_default_opts(&o);
       o.coarse_eq_limit = n < 200 ? 4 : 100;
@@ -140,12 +140,44 @@ int main() {
       if (variant == 2) { o.coarsening = BD_RS; o.threshold = 0.5; what = "rs"; }
       if (variant == 3) { o.smoother = BD_JACOBI; o.smoother_degree = 3; what = "sa-jacobi"; }
       if (variant == 4) { A = Apar; o.nullspace = BD_NULL_NONE; o.threshold = 0.0; what = "parabolic"; }
+      if (variant == 5) { o.coarsening = BD_PMIS; o.threshold = 0.5; o.seed = 7; what = "pmis"; }
       HostHierarchy H;
       std::string err;
       const int rc = build_hierarchy(A, o, H, err);
       CHECK(rc == BD_OK, "slab %dx%dx%d %s: setup failed: %s", d[0], d[1], d[2], what, err.c_str());
       if (rc == BD_OK) check_hierarchy(H, o, what);
     }
+  }
+  // the theta-periodic truncated ellipsoid (n_theta = 3 is the smallest periodic ring)
+  const int edims[][3] = {{3, 1, 1}, {4, 2, 1}, {7, 5, 3}, {16, 12, 6}};
+  for (const auto& d : edims) {
+    bd_ellipsoid e{};
+    e.n_theta = d[0]; e.n_phi = d[1]; e.n_r = d[2];
+    e.a1 = 2.2; e.a2 = 3.3; e.b1 = 2.0; e.b2 = 3.1; e.c1 = 5.9; e.c2 = 6.4;
+    e.theta_min = -1.5 * M_PI; e.theta_max = 0.5 * M_PI; e.phi_min = -0.375 * M_PI; e.phi_max = 0.125 * M_PI;
+    e.sig_il = 3.0e-3; e.sig_it = 3.1525e-4; e.sig_el = 2.0e-3; e.sig_et = 1.3514e-3;
+    e.fiber_endo = M_PI / 3.0; e.fiber_epi = -M_PI / 3.0;
+    Csr A;
+    std::vector<double> m;
+    const bool ok = assemble_ellipsoid(e, e.sig_il + e.sig_el, e.sig_it + e.sig_et, A, &m);
+    CHECK(ok, "ellipsoid %dx%dx%d: non-positive Jacobian", d[0], d[1], d[2]);
+    if (!ok) continue;
+    CHECK(A.nrows == ellipsoid_nodes(e) && A.nnz() == ellipsoid_nnz(e), "ellipsoid %dx%dx%d sizes", d[0], d[1], d[2]);
+    CHECK(validate(A).empty(), "ellipsoid %dx%dx%d CSR: %s", d[0], d[1], d[2], validate(A).c_str());
+    CHECK(exactly_symmetric(A), "ellipsoid %dx%dx%d not symmetric", d[0], d[1], d[2]);
+    for (double x : m) CHECK(x > 0, "ellipsoid %dx%dx%d non-positive mass", d[0], d[1], d[2]);
+    const std::vector<double> r = matvec(A, std::vector<double>(A.nrows, 1.0));
+    for (double x : r) CHECK(std::fabs(x) <= 1e-13 * max_abs(A), "ellipsoid %dx%dx%d A 1 != 0", d[0], d[1], d[2]);
+    bd_amg_opts o;
+    bidomain_default_opts(&o);
+    o.coarse_eq_limit = A.nrows < 200 ? 4 : 100;
+    o.galerkin_device = 0;
+    o.nullspace = BD_NULL_CONSTANT;
+    HostHierarchy H;
+    std::string err;
+    const int rc = build_hierarchy(A, o, H, err);
+    CHECK(rc == BD_OK, "ellipsoid %dx%dx%d: setup failed: %s", d[0], d[1], d[2], err.c_str());
+    if (rc == BD_OK) check_hierarchy(H, o, "ellipsoid sa");
   }
   // malformed input is rejected, not read out of bounds
   Csr bad;
