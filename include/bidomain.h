@@ -77,12 +77,16 @@ typedef struct {
   int32_t nullspace;           /* BD_NULL_NONE | BD_NULL_CONSTANT                        */
   double stagnation_ratio;     /* stop coarsening when n_c > ratio * n_k (0.9)           */
   int32_t coarse_dense_max;    /* largest coarsest level solved directly (2048)          */
-  /* Galerkin products R (A P) of the setup as dense GEMMs on the device (rocBLAS, float64,
-   * structural pattern from 0/1 GEMMs, so the result equals the sparse product up to
-   * rounding order): 0 never, 1 for levels where the dense work is within a few thousand
-   * times the sparse work and fits in half the free device memory (default), 2 for every
-   * level of at most 65,536 rows and columns that fits.  bidomain_amg_build_host never uses
-   * the device. */
+  /* Galerkin products R (A P) of the setup on the device, with this library's kernels: sparse
+   * products (every entry summed in the host product's order with separately rounded
+   * operations, so equal to the host's bit for bit) or, for the filled coarse levels, float64
+   * MFMA products of the dense expansions that skip empty tiles (the same pattern, values
+   * equal up to rounding order).  0 never; 1 (default) levels with at least 5e7 partial
+   * products in A P, dense where both dimensions are at most 65,536 and the dense work is
+   * within 1000 times the partial products, sparse otherwise; 2 every level, sparse; 3 every
+   * level, dense where the dimensions allow.  A product whose buffers do not fit in half the
+   * free device memory (or in a server's budget) falls back to the sparse form, then to the
+   * host.  bidomain_amg_build_host never uses the device. */
   int32_t galerkin_device;
   /* 1: keep a level operator that equals its transpose and whose column - row offsets >= 0
    * are those of a 27-point stencil (the fine operators) in the symmetric diagonal form
@@ -208,6 +212,23 @@ void bidomain_amg_destroy(bd_amg* h);
  */
 int bidomain_amg_export(const bd_amg* h, int level, int which, int32_t* rows, int32_t* cols,
                         int64_t* nnz, int32_t* row_ptr, int32_t* col_idx, double* val);
+
+/*
+ * The Galerkin product of the setup phase (Alg. 1): C = (R A P + (R A P)^T) / 2 with R = P^T,
+ * on the structural pattern of the product (no entry dropped), on the host (on_device = 0), as
+ * the device's sparse product (1; equal to the host's bit for bit) or as its dense MFMA product
+ * (2; n and nc at most 65,536; the same pattern, values equal up to rounding order) -- the
+ * kernels the setup uses with galerkin_device.
+ * A: n x n CSR (sorted columns, positive diagonal, as for bidomain_amg_setup); P: n x nc CSR
+ * (columns in [0, nc)); host arrays, read only.  *c_nnz receives the nonzero count and c_row_ptr
+ * (nc + 1 entries, may be NULL) the row offsets; pass NULL c_col_idx and c_val to query the size,
+ * else both must hold `capacity` >= *c_nnz entries (BD_E_INVALID otherwise).  BD_E_NOMEM when
+ * the device product's buffers do not fit in half the free device memory.
+ */
+int bidomain_galerkin(int32_t n, int32_t nc, const int32_t* a_row_ptr, const int32_t* a_col_idx,
+                      const double* a_val, const int32_t* p_row_ptr, const int32_t* p_col_idx,
+                      const double* p_val, int on_device, int64_t capacity, int32_t* c_row_ptr,
+                      int32_t* c_col_idx, double* c_val, int64_t* c_nnz);
 
 /*
  * Apply one operation of the V-cycle on level k, on device vectors of the hierarchy's

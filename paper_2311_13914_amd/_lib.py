@@ -117,6 +117,10 @@ _SIGS = {
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "bidomain_sim_create": (C.c_int, [C.POINTER(bd_slab), C.POINTER(bd_amg_opts), C.POINTER(bd_amg_opts), _vp, _vp,
                                       C.c_double, _vp, C.POINTER(_vp)]),
+    "bidomain_galerkin": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double), C.c_int, C.c_int64, C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "bidomain_ellipsoid_assemble": (C.c_int, [C.POINTER(bd_ellipsoid), C.c_int, C.POINTER(C.c_int32),
                                               C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "bidomain_ellipsoid_sim_create": (C.c_int, [C.POINTER(bd_ellipsoid), C.POINTER(bd_amg_opts),
@@ -277,6 +281,28 @@ def bidomain_amg_info(h) -> dict:
                 grid_complexity=s.grid_complexity, device_bytes=s.device_bytes, col_bytes=list(s.col_bytes[:L]),
                 tiles=list(s.tiles[:L]), col_bytes_p=list(s.col_bytes_p[:L]), col_bytes_r=list(s.col_bytes_r[:L]),
                 diags=list(s.diags[:L]), vcycle_precision=s.vcycle_precision)
+
+
+def bidomain_galerkin(A, P, on_device):
+    """(R A P + (R A P)^T) / 2 with R = P^T (scipy CSR inputs; returns a scipy CSR matrix).
+    on_device: False / 0 host, True / 1 the device's sparse product, 2 its dense MFMA product."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix(A)
+    P = sp.csr_matrix(P)
+    n, nc = P.shape
+    a = [np.ascontiguousarray(x, dt) for x, dt in ((A.indptr, np.int32), (A.indices, np.int32), (A.data, np.float64))]
+    p = [np.ascontiguousarray(x, dt) for x, dt in ((P.indptr, np.int32), (P.indices, np.int32), (P.data, np.float64))]
+    ip, dp = C.POINTER(C.c_int32), C.POINTER(C.c_double)
+    args = [C.c_int32(n), C.c_int32(nc), a[0].ctypes.data_as(ip), a[1].ctypes.data_as(ip), a[2].ctypes.data_as(dp),
+            p[0].ctypes.data_as(ip), p[1].ctypes.data_as(ip), p[2].ctypes.data_as(dp), int(on_device)]
+    nnz = C.c_int64()
+    rp = np.empty(nc + 1, np.int32)
+    _check(load().bidomain_galerkin(*args, 0, rp.ctypes.data_as(ip), None, None, C.byref(nnz)), "bidomain_galerkin")
+    ci = np.empty(nnz.value, np.int32)
+    v = np.empty(nnz.value, np.float64)
+    _check(load().bidomain_galerkin(*args, nnz.value, rp.ctypes.data_as(ip), ci.ctypes.data_as(ip),
+                                    v.ctypes.data_as(dp), C.byref(nnz)), "bidomain_galerkin")
+    return sp.csr_matrix((v, ci, rp), shape=(nc, nc))
 
 
 def bidomain_amg_destroy(h):

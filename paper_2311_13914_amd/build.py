@@ -49,7 +49,7 @@ def build(verbose: bool = False) -> str:
         _run([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    _run(["g++", "-shared", "-o", tmp, *objs, f"-L{ROCM}/lib", "-lamdhip64", "-lrocblas", "-fopenmp",
+    _run(["g++", "-shared", "-o", tmp, *objs, f"-L{ROCM}/lib", "-lamdhip64", "-fopenmp",
           f"-Wl,-rpath,{ROCM}/lib"], verbose)
     os.replace(tmp, LIB)
     return LIB

@@ -24,8 +24,11 @@ struct Csr {
 
 // C = A^T (columns sorted).
 Csr transpose(const Csr& A);
-// C = A B on the structural pattern of the product (no value is dropped).
+// C = A B on the structural pattern of the product (no value is dropped); every entry summed in
+// the order of A's row, each product and sum rounded separately.
 Csr spgemm(const Csr& A, const Csr& B);
+// (A + A^T) / 2 on A's pattern (a mirror entry that does not exist counts as zero).
+Csr symmetrized(const Csr& A);
 std::vector<double> diagonal(const Csr& A);
 // Checks the boundary's CSR contract; returns an empty string when valid.
 std::string validate(const Csr& A);
@@ -49,10 +52,10 @@ struct HostHierarchy {
   std::vector<double> G;        // n_M x n_M row-major: A_M^{-1}, or the pseudo-inverse on b-perp
 };
 
-// Galerkin product on another engine: given A_k, P_k and the number of partial products of
-// the sparse A_k P_k, either fills A_c = symmetrized R_k (A_k P_k) (R_k = P_k^T) and returns
-// true, or returns false and the host computes it.
-using GalerkinOffload = std::function<bool(const Csr& A, const Csr& P, int64_t sparse_flops, Csr& Ac)>;
+// Galerkin product on another engine: given A_k, P_k, R_k = P_k^T and the number of partial
+// products of A_k P_k, either fills A_c = symmetrized R_k (A_k P_k) exactly as the host would
+// and returns true, or returns false and the host computes it.
+using GalerkinOffload = std::function<bool(const Csr& A, const Csr& P, const Csr& R, int64_t sparse_flops, Csr& Ac)>;
 
 // Setup phase: returns BD_OK or a BD_E_* code with a message in err.
 int build_hierarchy(Csr A, const bd_amg_opts& o, HostHierarchy& H, std::string& err,

@@ -2,10 +2,10 @@
 // of fused kernels, PCG / flexible CG with all scalars kept on the device, the Bidomain
 // time step (eqs. (4)-(7)) and the C ABI declared in bidomain.h.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -20,6 +20,8 @@
 #include "bd_host.hpp"
 #include "bidomain.h"
 #include "kernels.hpp"
+#include "spgemm.hpp"
+#include "galerkin_dense.hpp"
 
 namespace bd {
 
@@ -1124,27 +1126,9 @@ void device_upload(bd_amg* h, const double* weights, bool need_ci, hipStream_t s
 }
 
 // ------------------------------------------------------------------------------------------
-// Dense Galerkin products on the device (setup phase).  The filled coarse levels of smoothed
-// aggregation make R (A P) a dense-matrix product in all but name; as float64 GEMMs (rocBLAS)
-// they take milliseconds instead of the host's minutes.  The structural pattern of the result
-// (which the sparse product keeps, explicit zeros included) comes from the same two products
-// on 0/1 matrices in float32: the counts are integers below 2^24, so they are exact.
-
-// Row-major dense copy of a CSR matrix (row i at i * ld) and its 0/1 pattern; one block per row.
-__global__ void k_densify(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
-                          int nrows, int64_t ld, double* __restrict__ dval, float* __restrict__ dpat) {
-  for (int i = blockIdx.x; i < nrows; i += gridDim.x)
-    for (int k = rp[i] + (int)threadIdx.x; k < rp[i + 1]; k += blockDim.x) {
-      const int64_t o = (int64_t)i * ld + ci[k];
-      dval[o] = v[k];
-      dpat[o] = 1.0f;
-    }
-}
-
-__global__ void k_binarize(float* __restrict__ a, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    a[i] = a[i] > 0.5f ? 1.0f : 0.0f;
-}
+// Sparse Galerkin products on the device (setup phase): A_c = (R (A P) + (R (A P))^T) / 2 with
+// this library's product kernels (spgemm.hpp).  They sum every entry in the host product's
+// order with separately rounded operations, so the hierarchy is the host's bit for bit.
 
 std::mutex g_galerkin_mu;  // one device Galerkin product at a time (its buffers are large)
 
@@ -1155,142 +1139,294 @@ struct TransientBudget {
   std::function<void(int64_t)> release;
 };
 
-bool dense_galerkin(const Csr& A, const Csr& P, int64_t sparse_flops, int mode, bool log, Csr& Ac,
-                    const TransientBudget* tb) {
-  const int64_t n = A.nrows, nc = P.ncols;
-  if (mode == 0 || n == 0 || nc == 0 || n > 65536 || nc > 65536) return false;
-  const double dense_flops = 2.0 * (double)n * (double)n * (double)nc + 2.0 * (double)n * (double)nc * (double)nc;
-  if (mode == 1 && (sparse_flops < 500000000LL || dense_flops > 4000.0 * (double)sparse_flops || dense_flops > 2e14))
-    return false;
-  std::lock_guard<std::mutex> lock(g_galerkin_mu);
-  const size_t dense_bytes = (size_t)(12 * n * n + 24 * n * nc + 12 * nc * nc);
-  const size_t csr_bytes = (size_t)(A.nnz() + P.nnz()) * 12 + (size_t)(n + 1) * 8;
-  size_t freeb = 0, total = 0;
-  if (hipMemGetInfo(&freeb, &total) != hipSuccess || dense_bytes + csr_bytes > freeb / 2) return false;
-  const int64_t need = (int64_t)(dense_bytes + csr_bytes);
-  if (tb && !tb->reserve(need)) return false;
-  struct Release {
-    const TransientBudget* tb;
-    int64_t bytes;
-    ~Release() {
-      if (tb) tb->release(bytes);
-    }
-  } rel{tb, need};
+namespace {
 
+struct DevCsr {
+  int n = 0, ncols = 0;
+  int64_t nnz = 0;
+  int *rp = nullptr, *ci = nullptr;
+  double* v = nullptr;
+};
+
+// Transient buffers of one Galerkin product: each allocation must fit in half the free device
+// memory and, with a budget, be reserved from it first; all are freed (and the reservations
+// given back) when the scope ends.  `ok` turns false at the first refusal.
+struct DevScratch {
+  const TransientBudget* tb = nullptr;
   std::vector<void*> bufs;
-  hipStream_t st = nullptr;
-  rocblas_handle hb = nullptr;
+  int64_t reserved = 0;
   bool ok = true;
-  auto alloc = [&](size_t bytes) -> void* {
-    void* p = nullptr;
-    if (!ok || hipMalloc(&p, bytes) != hipSuccess) {
+  ~DevScratch() {
+    for (void* q : bufs) (void)hipFree(q);
+    if (tb && reserved) tb->release(reserved);
+  }
+  template <typename T>
+  T* alloc(int64_t count) {
+    if (!ok) return nullptr;
+    const int64_t bytes = std::max<int64_t>(1, count) * (int64_t)sizeof(T);
+    size_t freeb = 0, total = 0;
+    if (hipMemGetInfo(&freeb, &total) != hipSuccess || bytes > (int64_t)(freeb / 2)) {
       ok = false;
       return nullptr;
     }
-    bufs.push_back(p);
-    return p;
+    if (tb) {
+      if (!tb->reserve(bytes)) {
+        ok = false;
+        return nullptr;
+      }
+      reserved += bytes;
+    }
+    void* q = nullptr;
+    if (hipMalloc(&q, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      ok = false;
+      return nullptr;
+    }
+    bufs.push_back(q);
+    return (T*)q;
+  }
+  void check(hipError_t e) {
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      ok = false;
+    }
+  }
+};
+
+DevCsr upload_csr(DevScratch& s, const Csr& H, hipStream_t st) {
+  DevCsr D;
+  D.n = H.nrows;
+  D.ncols = H.ncols;
+  D.nnz = H.nnz();
+  D.rp = s.alloc<int>(D.n + 1);
+  D.ci = s.alloc<int>(D.nnz);
+  D.v = s.alloc<double>(D.nnz);
+  if (!s.ok) return D;
+  s.check(hipMemcpyAsync(D.rp, H.rp.data(), sizeof(int) * (D.n + 1), hipMemcpyHostToDevice, st));
+  if (D.nnz) {
+    s.check(hipMemcpyAsync(D.ci, H.ci.data(), sizeof(int) * D.nnz, hipMemcpyHostToDevice, st));
+    s.check(hipMemcpyAsync(D.v, H.v.data(), sizeof(double) * D.nnz, hipMemcpyHostToDevice, st));
+  }
+  return D;
+}
+
+int grid_for(int64_t units, int per_block, int cap) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (units + per_block - 1) / per_block));
+}
+
+// C = A B on the device (C's buffers from s); false when memory is refused or a call fails.
+// log: print the time of each pass.
+bool device_spgemm(DevScratch& s, const DevCsr& A, const DevCsr& B, DevCsr& C, hipStream_t st, bool log) {
+  using namespace sg;
+  const int n = A.n, p = B.ncols;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto lap = [&](const char* what) {
+    if (!log) return;
+    s.check(hipStreamSynchronize(st));
+    std::fprintf(stderr, "[setup]   product %d x %d (B %d cols, nnz A %lld B %lld): %s at %.3f s\n", n, A.ncols, p,
+                 (long long)A.nnz, (long long)B.nnz, what,
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
   };
-  auto hip_ok = [&](hipError_t e) { ok = ok && e == hipSuccess; };
-  auto blas_ok = [&](rocblas_status e) { ok = ok && e == rocblas_status_success; };
-  double *dA = (double*)alloc(8 * n * n), *dPt = (double*)alloc(8 * n * nc), *dAP = (double*)alloc(8 * n * nc),
-         *dRAP = (double*)alloc(8 * nc * nc);
-  float *sA = (float*)alloc(4 * n * n), *sPt = (float*)alloc(4 * n * nc), *sAP = (float*)alloc(4 * n * nc),
-        *sRAP = (float*)alloc(4 * nc * nc);
-  int *arp = (int*)alloc(4 * (n + 1)), *aci = (int*)alloc(4 * std::max<int64_t>(1, A.nnz())),
-      *prp = (int*)alloc(4 * (n + 1)), *pci = (int*)alloc(4 * std::max<int64_t>(1, P.nnz()));
-  double *av = (double*)alloc(8 * std::max<int64_t>(1, A.nnz())), *pv = (double*)alloc(8 * std::max<int64_t>(1, P.nnz()));
-  std::vector<double> rap;
-  std::vector<float> pat;
-  if (ok) hip_ok(hipStreamCreate(&st));
-  if (ok) blas_ok(rocblas_create_handle(&hb));
-  if (ok) blas_ok(rocblas_set_stream(hb, st));
-  if (ok) {
-    hip_ok(hipMemcpyAsync(arp, A.rp.data(), 4 * (n + 1), hipMemcpyHostToDevice, st));
-    hip_ok(hipMemcpyAsync(aci, A.ci.data(), 4 * A.nnz(), hipMemcpyHostToDevice, st));
-    hip_ok(hipMemcpyAsync(av, A.v.data(), 8 * A.nnz(), hipMemcpyHostToDevice, st));
-    hip_ok(hipMemcpyAsync(prp, P.rp.data(), 4 * (n + 1), hipMemcpyHostToDevice, st));
-    hip_ok(hipMemcpyAsync(pci, P.ci.data(), 4 * P.nnz(), hipMemcpyHostToDevice, st));
-    hip_ok(hipMemcpyAsync(pv, P.v.data(), 8 * P.nnz(), hipMemcpyHostToDevice, st));
-    hip_ok(hipMemsetAsync(dA, 0, 8 * n * n, st));
-    hip_ok(hipMemsetAsync(sA, 0, 4 * n * n, st));
-    hip_ok(hipMemsetAsync(dPt, 0, 8 * n * nc, st));
-    hip_ok(hipMemsetAsync(sPt, 0, 4 * n * nc, st));
+  int* u = s.alloc<int>(n);
+  int* cnt = s.alloc<int>(n);
+  if (!s.ok) return false;
+  k_sg_products<<<grid_for(n, kBlock, 4096), kBlock, 0, st>>>(A.rp, A.ci, B.rp, n, u);
+  s.check(hipGetLastError());
+  std::vector<int> hv(n);
+  s.check(hipMemcpyAsync(hv.data(), u, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  s.check(hipStreamSynchronize(st));
+  if (!s.ok) return false;
+  std::vector<int> big;
+  int64_t products = 0;
+  for (int i = 0; i < n; ++i) {
+    products += hv[i];
+    if (hv[i] > kSmallProducts) big.push_back(i);
   }
-  if (ok) {
-    const int g = (int)std::min<int64_t>(n, 65535);
-    // row-major A read column-major is A^T; row-major P (ld nc) read column-major is P^T (nc x n)
-    k_densify<<<g, kBlock, 0, st>>>(arp, aci, av, (int)n, n, dA, sA);
-    k_densify<<<g, kBlock, 0, st>>>(prp, pci, pv, (int)n, nc, dPt, sPt);
-    hip_ok(hipGetLastError());
+  const int nbig = (int)big.size();
+  if (log) std::fprintf(stderr, "[setup]   product: %lld partial products, %d big rows\n", (long long)products, nbig);
+  // big rows: a column bitmap in LDS when C has at most kDenseCols columns, else mark arrays of
+  // p ints per block (at most 4 GiB together)
+  // (dense accumulators of p doubles per block, at most 2 GiB together)
+  const bool dense = p <= kDenseCols;
+  const int gbig = !nbig ? 0
+                   : dense ? (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nbig, 2048, (1LL << 28) / std::max(1, p)}))
+                           : (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)nbig, 1024, (1LL << 30) / std::max(1, p)}));
+  int* dbig = nbig ? s.alloc<int>(nbig) : nullptr;
+  int* marks = nbig && !dense ? s.alloc<int>((int64_t)gbig * p) : nullptr;
+  double* accg = nbig && dense ? s.alloc<double>((int64_t)gbig * p) : nullptr;
+  if (!s.ok) return false;
+  if (nbig) s.check(hipMemcpyAsync(dbig, big.data(), sizeof(int) * nbig, hipMemcpyHostToDevice, st));
+  if (marks) s.check(hipMemsetAsync(marks, 0xff, sizeof(int) * (size_t)gbig * p, st));  // -1
+  if (accg) s.check(hipMemsetAsync(accg, 0, sizeof(double) * (size_t)gbig * p, st));
+  const int gsmall = grid_for(n, 1, 65536);
+  k_sg_small<0><<<gsmall, kSmallBlock, 0, st>>>(A.rp, A.ci, B.rp, B.ci, u, n, cnt, nullptr, nullptr);
+  if (nbig && dense) k_sg_dense_sym<0><<<gbig, kBigBlock, 0, st>>>(A.rp, A.ci, B.rp, B.ci, dbig, nbig, p, cnt, nullptr, nullptr);
+  if (nbig && !dense) k_sg_big<0><<<gbig, kBigBlock, 0, st>>>(A.rp, A.ci, B.rp, B.ci, dbig, nbig, n, p, marks, cnt, nullptr, nullptr);
+  s.check(hipGetLastError());
+  lap("counted");
+  s.check(hipMemcpyAsync(hv.data(), cnt, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+  s.check(hipStreamSynchronize(st));
+  if (!s.ok) return false;
+  std::vector<int> rp(n + 1, 0);
+  int64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    total += hv[i];
+    if (total > INT32_MAX) return false;
+    rp[i + 1] = (int)total;
   }
-  const double one = 1.0, zero = 0.0;
-  const float onef = 1.0f, zerof = 0.0f;
-  const rocblas_int N = (rocblas_int)n, NC = (rocblas_int)nc;
-  if (ok) {
-    // A P = (A^T)^T (P^T)^T: n x nc
-    blas_ok(rocblas_dgemm(hb, rocblas_operation_transpose, rocblas_operation_transpose, N, NC, N, &one, dA, N, dPt, NC,
-                          &zero, dAP, N));
-    blas_ok(rocblas_sgemm(hb, rocblas_operation_transpose, rocblas_operation_transpose, N, NC, N, &onef, sA, N, sPt, NC,
-                          &zerof, sAP, N));
+  C.n = n;
+  C.ncols = p;
+  C.nnz = total;
+  C.rp = s.alloc<int>(n + 1);
+  C.ci = s.alloc<int>(total);
+  C.v = s.alloc<double>(total);
+  if (!s.ok) return false;
+  s.check(hipMemcpyAsync(C.rp, rp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st));
+  k_sg_small<1><<<gsmall, kSmallBlock, 0, st>>>(A.rp, A.ci, B.rp, B.ci, u, n, nullptr, C.rp, C.ci);
+  if (nbig && dense) k_sg_dense_sym<1><<<gbig, kBigBlock, 0, st>>>(A.rp, A.ci, B.rp, B.ci, dbig, nbig, p, nullptr, C.rp, C.ci);
+  if (nbig && !dense) k_sg_big<1><<<gbig, kBigBlock, 0, st>>>(A.rp, A.ci, B.rp, B.ci, dbig, nbig, n, p, marks, nullptr, C.rp, C.ci);
+  lap("columns");
+  k_sg_num_small<<<gsmall, kSmallBlock, 0, st>>>(A.rp, A.ci, A.v, B.rp, B.ci, B.v, u, n, C.rp, C.ci, C.v);
+  if (nbig && dense) k_sg_dense_num<<<gbig, kBigBlock, 0, st>>>(A.rp, A.ci, A.v, B.rp, B.ci, B.v, dbig, nbig, p, accg, C.rp, C.ci, C.v);
+  if (nbig && !dense) k_sg_num_big<<<gbig, kBigBlock, 0, st>>>(A.rp, A.ci, A.v, B.rp, B.ci, B.v, dbig, nbig, C.rp, C.ci, C.v);
+  s.check(hipGetLastError());
+  s.check(hipStreamSynchronize(st));
+  lap("values");
+  return s.ok;
+}
+
+// A_c = sym(R (A P)) as block-sparse MFMA products of dense expansions (galerkin_dense.hpp), the
+// pattern from row bitmaps; fills Ac on the host.  false when memory is refused or a call fails.
+bool dense_galerkin_dev(DevScratch& s, const DevCsr& A, const DevCsr& P, const DevCsr& R, Csr& Ac, hipStream_t st,
+                        bool log) {
+  using namespace gd;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int n = A.n, nc = P.ncols;
+  const int64_t np = (n + kTile - 1) / kTile * kTile, ncp = (nc + kTile - 1) / kTile * kTile;
+  const int W = (nc + 31) / 32;
+  double* dA = s.alloc<double>(np * np);
+  double* dP = s.alloc<double>(np * ncp);
+  double* dR = s.alloc<double>(ncp * np);
+  double* dAP = s.alloc<double>(np * ncp);
+  double* dRAP = s.alloc<double>(ncp * ncp);
+  const int nkt = (int)(np / kKStep);
+  uint8_t* occA = s.alloc<uint8_t>(np / kTile * nkt);
+  uint8_t* occR = s.alloc<uint8_t>(ncp / kTile * nkt);
+  uint32_t* bP = s.alloc<uint32_t>((int64_t)n * W);
+  uint32_t* bAP = s.alloc<uint32_t>((int64_t)n * W);
+  uint32_t* bRAP = s.alloc<uint32_t>((int64_t)nc * W);
+  int* cnt = s.alloc<int>(nc);
+  if (!s.ok) return false;
+  s.check(hipMemsetAsync(dA, 0, sizeof(double) * np * np, st));
+  s.check(hipMemsetAsync(dP, 0, sizeof(double) * np * ncp, st));
+  s.check(hipMemsetAsync(dR, 0, sizeof(double) * ncp * np, st));
+  s.check(hipMemsetAsync(occA, 0, np / kTile * nkt, st));
+  s.check(hipMemsetAsync(occR, 0, ncp / kTile * nkt, st));
+  s.check(hipMemsetAsync(bP, 0, sizeof(uint32_t) * n * W, st));
+  const int g = grid_for(std::max(n, nc), 1, 65536);
+  k_gd_densify<<<g, kBlock, 0, st>>>(A.rp, A.ci, A.v, n, np, dA);
+  k_gd_densify<<<g, kBlock, 0, st>>>(P.rp, P.ci, P.v, n, ncp, dP);
+  k_gd_densify<<<g, kBlock, 0, st>>>(R.rp, R.ci, R.v, nc, np, dR);
+  k_gd_occupancy<<<g, kBlock, 0, st>>>(A.rp, A.ci, n, nkt, occA);
+  k_gd_occupancy<<<g, kBlock, 0, st>>>(R.rp, R.ci, nc, nkt, occR);
+  k_gd_row_bits<<<g, kBlock, 0, st>>>(P.rp, P.ci, n, W, bP);
+  k_gd_or_rows<<<g, kBlock, 0, st>>>(A.rp, A.ci, n, W, bP, bAP);
+  k_gd_or_rows<<<g, kBlock, 0, st>>>(R.rp, R.ci, nc, W, bAP, bRAP);
+  k_gd_count<<<g, kBlock, 0, st>>>(bRAP, nc, W, cnt);
+  k_gd_gemm<<<dim3((unsigned)(ncp / kTile), (unsigned)(np / kTile)), 256, 0, st>>>(dA, np, dP, ncp, dAP, ncp, nkt, occA);
+  k_gd_gemm<<<dim3((unsigned)(ncp / kTile), (unsigned)(ncp / kTile)), 256, 0, st>>>(dR, np, dAP, ncp, dRAP, ncp, nkt, occR);
+  s.check(hipGetLastError());
+  std::vector<int> hc(nc);
+  s.check(hipMemcpyAsync(hc.data(), cnt, sizeof(int) * nc, hipMemcpyDeviceToHost, st));
+  s.check(hipStreamSynchronize(st));
+  if (!s.ok) return false;
+  Ac = Csr();
+  Ac.nrows = Ac.ncols = nc;
+  Ac.rp.assign(nc + 1, 0);
+  for (int i = 0; i < nc; ++i) {
+    if ((int64_t)Ac.rp[i] + hc[i] > INT32_MAX) return false;
+    Ac.rp[i + 1] = Ac.rp[i] + hc[i];
   }
-  if (ok) {
-    k_binarize<<<2048, kBlock, 0, st>>>(sAP, n * nc);
-    hip_ok(hipGetLastError());
-    // R (A P) = P^T (A P): nc x nc
-    blas_ok(rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, NC, NC, N, &one, dPt, NC, dAP, N, &zero,
-                          dRAP, NC));
-    blas_ok(rocblas_sgemm(hb, rocblas_operation_none, rocblas_operation_none, NC, NC, N, &onef, sPt, NC, sAP, N, &zerof,
-                          sRAP, NC));
+  const int64_t nnz = Ac.rp[nc];
+  int* crp = s.alloc<int>(nc + 1);
+  int* cci = s.alloc<int>(nnz);
+  double* cv = s.alloc<double>(nnz);
+  if (!s.ok) return false;
+  s.check(hipMemcpyAsync(crp, Ac.rp.data(), sizeof(int) * (nc + 1), hipMemcpyHostToDevice, st));
+  k_gd_extract<<<grid_for(nc, 1, 65536), 256, 0, st>>>(bRAP, nc, W, crp, cci);
+  k_gd_values<<<grid_for(nc, kBlock / 64, 8192), kBlock, 0, st>>>(crp, cci, nc, dRAP, ncp, cv);
+  s.check(hipGetLastError());
+  Ac.ci.resize(nnz);
+  Ac.v.resize(nnz);
+  if (nnz) {
+    s.check(hipMemcpyAsync(Ac.ci.data(), cci, sizeof(int) * nnz, hipMemcpyDeviceToHost, st));
+    s.check(hipMemcpyAsync(Ac.v.data(), cv, sizeof(double) * nnz, hipMemcpyDeviceToHost, st));
   }
-  if (ok) {
-    // C = (R A P + (R A P)^T) / 2 (a structurally absent mirror is an exact zero, as the host's
-    // symmetrisation assumes) into the A P buffer; the pattern transposed into sAP, so that row
-    // a of the pattern is contiguous.  0.5 a + 0.5 b rounds exactly as 0.5 (a + b).
-    const double half = 0.5;
-    blas_ok(rocblas_dgeam(hb, rocblas_operation_none, rocblas_operation_transpose, NC, NC, &half, dRAP, NC, &half, dRAP,
-                          NC, dAP, NC));
-    blas_ok(rocblas_sgeam(hb, rocblas_operation_transpose, rocblas_operation_none, NC, NC, &onef, sRAP, NC, &zerof, sRAP,
-                          NC, sAP, NC));
-  }
-  if (ok) {
-    rap.resize((size_t)nc * nc);
-    pat.resize((size_t)nc * nc);
-    hip_ok(hipMemcpyAsync(rap.data(), dAP, 8 * nc * nc, hipMemcpyDeviceToHost, st));
-    hip_ok(hipMemcpyAsync(pat.data(), sAP, 4 * nc * nc, hipMemcpyDeviceToHost, st));
-    hip_ok(hipStreamSynchronize(st));
-  }
-  if (hb) (void)rocblas_destroy_handle(hb);
-  if (st) (void)hipStreamDestroy(st);
-  for (void* p : bufs) (void)hipFree(p);
-  if (!ok) {
+  s.check(hipStreamSynchronize(st));
+  if (log)
+    std::fprintf(stderr, "[setup]   dense product %d x %d -> %d: %.3f s\n", n, n, nc,
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  return s.ok;
+}
+
+}  // namespace
+
+// Galerkin product A_c = sym(R (A P)) on the device.  mode 0: never.  1: levels with at least 5e7
+// partial products in A P (smaller ones are as fast on the host); those of at most 65,536 rows
+// and columns whose dense contraction is within 1000 times the partial products of A P (the
+// filled coarse levels) as MFMA products (equal to the host's up to rounding order), the others
+// as sparse products (equal bit for bit).  2: every level, sparse.  3: every level of at most
+// 65,536 rows and columns dense, the others sparse.  Returns false (the host computes the
+// product) when the device memory or the budget is not available.
+bool sparse_galerkin(const Csr& A, const Csr& P, const Csr& R, int64_t sparse_flops, int mode, bool log, Csr& Ac,
+                     const TransientBudget* tb) {
+  if (mode == 0 || A.nrows == 0 || P.ncols == 0) return false;
+  if (mode == 1 && sparse_flops < 50000000LL) return false;
+  const double n = A.nrows, nc = P.ncols;
+  const bool fits = n <= sg::kDenseCols && nc <= sg::kDenseCols;
+  const bool dense = fits && (mode == 3 || (mode == 1 && 2.0 * n * n * nc + 2.0 * nc * n * nc <= 1000.0 * (double)sparse_flops));
+  std::lock_guard<std::mutex> lock(g_galerkin_mu);
+  hipStream_t st = nullptr;
+  if (hipStreamCreate(&st) != hipSuccess) {
     (void)hipGetLastError();
-    if (log) std::fprintf(stderr, "[setup] device Galerkin product unavailable, using the host\n");
     return false;
   }
-  // CSR on R A P's pattern: pattern(a, b) at pat[b + a nc], C(a, b) = C(b, a) at rap[b + a nc]
-  Ac = Csr();
-  Ac.nrows = Ac.ncols = (int32_t)nc;
-  Ac.rp.assign(nc + 1, 0);
-#pragma omp parallel for schedule(static, 64)
-  for (int64_t a = 0; a < nc; ++a) {
-    int32_t cnt = 0;
-    for (int64_t b = 0; b < nc; ++b) cnt += pat[b + a * nc] > 0.5f;
-    Ac.rp[a + 1] = cnt;
-  }
-  for (int64_t a = 0; a < nc; ++a) Ac.rp[a + 1] += Ac.rp[a];
-  Ac.ci.resize(Ac.rp[nc]);
-  Ac.v.resize(Ac.rp[nc]);
-#pragma omp parallel for schedule(static, 64)
-  for (int64_t a = 0; a < nc; ++a) {
-    int32_t pos = Ac.rp[a];
-    for (int64_t b = 0; b < nc; ++b)
-      if (pat[b + a * nc] > 0.5f) {
-        Ac.ci[pos] = (int32_t)b;
-        Ac.v[pos] = rap[b + a * nc];
-        ++pos;
+  bool ok = false;
+  for (int attempt = dense ? 0 : 1; attempt < 2 && !ok; ++attempt) {
+    DevScratch s;
+    s.tb = tb;
+    const DevCsr dA = upload_csr(s, A, st), dP = upload_csr(s, P, st), dR = upload_csr(s, R, st);
+    if (!s.ok) continue;
+    if (attempt == 0) {
+      ok = dense_galerkin_dev(s, dA, dP, dR, Ac, st, log);
+      if (!ok && log) std::fprintf(stderr, "[setup] dense device Galerkin product unavailable, trying the sparse one\n");
+      continue;
+    }
+    DevCsr AP, RAP;
+    if (device_spgemm(s, dA, dP, AP, st, log) && device_spgemm(s, dR, AP, RAP, st, log)) {
+      double* sym = s.alloc<double>(RAP.nnz);
+      if (s.ok) {
+        sg::k_sg_symmetrize<<<grid_for(RAP.n, kBlock / 64, 8192), kBlock, 0, st>>>(RAP.rp, RAP.ci, RAP.v, RAP.n, sym);
+        s.check(hipGetLastError());
+        Ac = Csr();
+        Ac.nrows = RAP.n;
+        Ac.ncols = RAP.ncols;
+        Ac.rp.resize(RAP.n + 1);
+        Ac.ci.resize(RAP.nnz);
+        Ac.v.resize(RAP.nnz);
+        s.check(hipMemcpyAsync(Ac.rp.data(), RAP.rp, sizeof(int) * (RAP.n + 1), hipMemcpyDeviceToHost, st));
+        if (RAP.nnz) {
+          s.check(hipMemcpyAsync(Ac.ci.data(), RAP.ci, sizeof(int) * RAP.nnz, hipMemcpyDeviceToHost, st));
+          s.check(hipMemcpyAsync(Ac.v.data(), sym, sizeof(double) * RAP.nnz, hipMemcpyDeviceToHost, st));
+        }
+        s.check(hipStreamSynchronize(st));
+        ok = s.ok;
       }
+    }
   }
-  return true;
+  (void)hipStreamDestroy(st);
+  if (!ok && log) std::fprintf(stderr, "[setup] device Galerkin product unavailable, using the host\n");
+  return ok;
 }
 
 // host_only: build the hierarchy but do not upload it; use_device: the setup may run its
@@ -1306,7 +1442,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   if (o.smoother_degree < 1 || o.coarse_eq_limit < 1 || o.max_levels < 1 || !(o.cheb_hi > o.cheb_lo) ||
       !(o.cheb_lo >= 0.0) || o.esteig_iters < 1 || !(o.threshold >= 0.0) || !(o.stagnation_ratio > 0.0) ||
       o.coarse_dense_max < 1 || (o.coarsening != BD_SA && o.coarsening != BD_RS && o.coarsening != BD_PMIS) ||
-      o.galerkin_device < 0 || o.galerkin_device > 2 || o.diag_form < 0 || o.diag_form > 1 ||
+      o.galerkin_device < 0 || o.galerkin_device > 3 || o.diag_form < 0 || o.diag_form > 1 ||
       o.preconditioner < BD_PC_AMG || o.preconditioner > BD_PC_NONE ||
       (o.preconditioner != BD_PC_AMG && o.vcycle_precision != BD_F64) ||
       (o.smoother != BD_CHEBYSHEV && o.smoother != BD_JACOBI) ||
@@ -1333,8 +1469,8 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   h->mixed = o.vcycle_precision == BD_F32;
   std::string err;
   const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
-  const GalerkinOffload offload = [&](const Csr& Ak, const Csr& Pk, int64_t flops, Csr& Ac) {
-    return dense_galerkin(Ak, Pk, flops, o.galerkin_device, log, Ac, tb);
+  const GalerkinOffload offload = [&](const Csr& Ak, const Csr& Pk, const Csr& Rk, int64_t flops, Csr& Ac) {
+    return sparse_galerkin(Ak, Pk, Rk, flops, o.galerkin_device, log, Ac, tb);
   };
   const auto t0 = std::chrono::steady_clock::now();
   const int rc = build_hierarchy(std::move(H), o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr);
@@ -1589,6 +1725,53 @@ int bidomain_amg_export(const bd_amg* h, int level, int which, int32_t* rows, in
     if (row_ptr) std::copy(M.rp.begin(), M.rp.end(), row_ptr);
     if (col_idx) std::copy(M.ci.begin(), M.ci.end(), col_idx);
     if (val) std::copy(M.v.begin(), M.v.end(), val);
+    return BD_OK;
+  });
+}
+
+int bidomain_galerkin(int32_t n, int32_t nc, const int32_t* a_row_ptr, const int32_t* a_col_idx, const double* a_val,
+                      const int32_t* p_row_ptr, const int32_t* p_col_idx, const double* p_val, int on_device,
+                      int64_t capacity, int32_t* c_row_ptr, int32_t* c_col_idx, double* c_val, int64_t* c_nnz) {
+  return guarded([&] {
+    if (n <= 0 || nc <= 0 || !a_row_ptr || !a_col_idx || !a_val || !p_row_ptr || !p_col_idx || !p_val || !c_nnz ||
+        on_device < 0 || on_device > 2 || (on_device == 2 && (n > sg::kDenseCols || nc > sg::kDenseCols)))
+      throw Failure{BD_E_INVALID, "invalid Galerkin arguments"};
+    Csr A, P;
+    A.nrows = A.ncols = n;
+    A.rp.assign(a_row_ptr, a_row_ptr + n + 1);
+    if (A.rp[0] != 0 || A.rp[n] < 0) throw Failure{BD_E_INVALID, "A: row_ptr must start at 0"};
+    A.ci.assign(a_col_idx, a_col_idx + A.rp[n]);
+    A.v.assign(a_val, a_val + A.rp[n]);
+    const std::string err = validate(A);
+    if (!err.empty()) throw Failure{BD_E_INVALID, "A: " + err};
+    P.nrows = n;
+    P.ncols = nc;
+    P.rp.assign(p_row_ptr, p_row_ptr + n + 1);
+    if (P.rp[0] != 0) throw Failure{BD_E_INVALID, "P: row_ptr must start at 0"};
+    for (int32_t i = 0; i < n; ++i)
+      if (P.rp[i + 1] < P.rp[i]) throw Failure{BD_E_INVALID, "P: row_ptr must be non-decreasing"};
+    P.ci.assign(p_col_idx, p_col_idx + P.rp[n]);
+    P.v.assign(p_val, p_val + P.rp[n]);
+    for (int32_t c : P.ci)
+      if (c < 0 || c >= nc) throw Failure{BD_E_INVALID, "P: column index out of range"};
+    const Csr R = transpose(P);
+    int64_t flops = 0;
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) flops += P.rp[A.ci[k] + 1] - P.rp[A.ci[k]];
+    Csr Ac;
+    if (on_device) {
+      if (!sparse_galerkin(A, P, R, flops, on_device == 1 ? 2 : 3, false, Ac, nullptr))
+        throw Failure{BD_E_NOMEM, "device Galerkin product: device memory not available"};
+    } else {
+      Ac = symmetrized(spgemm(R, spgemm(A, P)));
+    }
+    *c_nnz = Ac.nnz();
+    if (c_row_ptr) std::copy(Ac.rp.begin(), Ac.rp.end(), c_row_ptr);
+    if (c_col_idx || c_val) {
+      if (capacity < Ac.nnz()) throw Failure{BD_E_INVALID, "output capacity below the product's nonzeros"};
+      if (c_col_idx) std::copy(Ac.ci.begin(), Ac.ci.end(), c_col_idx);
+      if (c_val) std::copy(Ac.v.begin(), Ac.v.end(), c_val);
+    }
     return BD_OK;
   });
 }

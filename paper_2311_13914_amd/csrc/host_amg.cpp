@@ -786,6 +786,8 @@ int coarse_operator(const HostLevel& L, bool nullspace, std::vector<double>& G, 
 
 }  // namespace
 
+Csr symmetrized(const Csr& A) { return symmetrize(A); }
+
 // ------------------------------------------------------------------------------------------
 // With BIDOMAIN_SETUP_LOG set in the environment, one line per level goes to stderr as the
 // setup proceeds (large hierarchies take minutes on the host).
@@ -863,7 +865,7 @@ int build_hierarchy(Csr A0, const bd_amg_opts& o, HostHierarchy& H, std::string&
 #pragma omp parallel for reduction(+ : flops) schedule(static, 4096)
       for (int32_t i = 0; i < n; ++i)
         for (int32_t ka = cur.A.rp[i]; ka < cur.A.rp[i + 1]; ++ka) flops += P.rp[cur.A.ci[ka] + 1] - P.rp[cur.A.ci[ka]];
-      done = (*offload)(cur.A, P, flops, Ac);
+      done = (*offload)(cur.A, P, R, flops, Ac);
       if (done && log) std::fprintf(stderr, "[setup] level %d: Galerkin product on the device (%.1f s)\n", k, elapsed());
     }
     if (!done) {

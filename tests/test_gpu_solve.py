@@ -457,25 +457,104 @@ def test_diag_form_selection(torch, case):
         lib.bidomain_amg_destroy(h)
 
 
-@pytest.mark.parametrize("dims", [(16, 16, 8), (37, 29, 13), (32, 32, 16)])
-def test_device_galerkin_equals_host(torch, dims):
-    """Galerkin products as dense device GEMMs (forced on every level) give the host's sparse
-    hierarchy: the same levels, patterns and nonzero counts, and values equal up to rounding order."""
+@pytest.mark.parametrize("dims,coarsening", [((16, 16, 8), "sa"), ((37, 29, 13), "sa"), ((32, 32, 16), "sa"),
+                                              ((32, 32, 16), "rs"), ((37, 29, 13), "pmis")])
+def test_device_galerkin_equals_host(torch, dims, coarsening):
+    """Galerkin products as sparse device products (forced on every level) give the host's
+    hierarchy bit for bit: the same levels, patterns and values."""
     c = bc.make_case(*dims, seed=9)
     ops = fem.assemble_operators(c)
     A = ops["Aell"]
-    hd = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, galerkin_device=2), ops["m"])
-    hh = lib.bidomain_amg_build_host(A, lib.bidomain_default_opts(nullspace=1))
+    kw = dict(nullspace=1, coarsening={"sa": lib.BD_SA, "rs": lib.BD_RS, "pmis": lib.BD_PMIS}[coarsening])
+    if coarsening != "sa":
+        kw["threshold"] = 0.5
+    hd = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(galerkin_device=2, **kw), ops["m"])
+    hh = lib.bidomain_amg_build_host(A, lib.bidomain_default_opts(**kw))
     try:
         idd, ih = lib.bidomain_amg_info(hd), lib.bidomain_amg_info(hh)
-        print(f"[gpu] device Galerkin dims={dims} levels={idd['n']}", flush=True)
+        print(f"[gpu] device Galerkin dims={dims} {coarsening} levels={idd['n']}", flush=True)
         assert idd["n"] == ih["n"] and idd["nnz"] == ih["nnz"] and idd["p_nnz"] == ih["p_nnz"]
         for k in range(idd["nlevels"]):
             for which in ([0, 1] if k + 1 < idd["nlevels"] else [0]):
                 rd, cd, vd, _ = lib.bidomain_amg_export(hd, k, which)
                 rh, ch, vh, _ = lib.bidomain_amg_export(hh, k, which)
                 assert np.array_equal(rd, rh) and np.array_equal(cd, ch), (k, which)
-                assert np.max(np.abs(vd - vh)) <= 1e-12 * np.max(np.abs(vh)), (k, which)
+                assert np.array_equal(vd, vh), (k, which, np.max(np.abs(vd - vh)))
     finally:
         lib.bidomain_amg_destroy(hd)
         lib.bidomain_amg_destroy(hh)
+
+
+def _long_row_operands(n, nc, a_per_row, p_per_row, spread, seed, hub=0):
+    """A symmetric n x n matrix with about a_per_row entries a row in a band, and a random
+    n x nc interpolation with p_per_row entries a row within nc / spread of the diagonal; with
+    hub > 0, that many random rows also interpolate from column 0 (so row 0 of the product is
+    far longer than the rest)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n), a_per_row // 2)
+    cols = np.clip(rows + rng.integers(-4 * a_per_row, 4 * a_per_row, rows.size), 0, n - 1)
+    B = sp.csr_matrix((rng.uniform(-1, 1, rows.size), (rows, cols)), shape=(n, n))
+    A = (B + B.T + sp.diags(np.full(n, 4.0 * a_per_row))).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    pr = np.repeat(np.arange(n), p_per_row)
+    pc = (pr * nc // n + rng.integers(-nc // spread, nc // spread, pr.size)) % nc
+    if hub:
+        hr = rng.choice(n, hub, replace=False)
+        pr, pc = np.concatenate([pr, hr]), np.concatenate([pc, np.zeros(hub, pc.dtype)])
+    P = sp.csr_matrix((rng.uniform(0.1, 1, pr.size), (pr, pc)), shape=(n, nc))
+    P.sum_duplicates()
+    P.sort_indices()
+    return A, P
+
+
+@pytest.mark.parametrize("n,nc,a_per_row,p_per_row,spread,hub", [(3000, 700, 20, 4, 8, 0), (10000, 9000, 60, 16, 2, 0),
+                                                                   (100000, 70000, 20, 2, 1, 5000)])
+def test_galerkin_product_device_equals_host(torch, n, nc, a_per_row, p_per_row, spread, hub):
+    """The device product on rows of every kind: few partial products (LDS hash); many, with at
+    most 65,536 product columns (LDS bitmap, dense accumulation windows, rows longer than one
+    window) or more (mark arrays; sorted in LDS, or with more than 8192 distinct columns by an
+    ordered scan of the marks, the hub row); equal to the host product bit for bit and to sparse
+    algebra within rounding."""
+    A, P = _long_row_operands(n, nc, a_per_row, p_per_row, spread, seed=1, hub=hub)
+    Cd = lib.bidomain_galerkin(A, P, on_device=True)
+    Ch = lib.bidomain_galerkin(A, P, on_device=False)
+    longest = int(np.diff(Cd.indptr).max())
+    print(f"[gpu] Galerkin n={n} nc={nc}: nnz {Cd.nnz}, longest row {longest}", flush=True)
+    assert np.array_equal(Cd.indptr, Ch.indptr) and np.array_equal(Cd.indices, Ch.indices)
+    assert np.array_equal(Cd.data, Ch.data)
+    R = (P.T @ A @ P).tocsr()
+    ref = 0.5 * (R + R.T)
+    assert abs(Cd - ref).max() <= 1e-12 * abs(ref).max()
+    if n >= 10000:
+        assert longest > 8192
+    if n <= 65536 and nc <= 65536:
+        Cm = lib.bidomain_galerkin(A, P, on_device=2)     # dense MFMA form: same pattern
+        assert np.array_equal(Cm.indptr, Ch.indptr) and np.array_equal(Cm.indices, Ch.indices)
+        assert np.max(np.abs(Cm.data - Ch.data)) <= 1e-12 * np.max(np.abs(Ch.data))
+
+
+@pytest.mark.parametrize("dims", [(24, 24, 12), (40, 36, 20)])
+def test_dense_device_galerkin_hierarchy(torch, dims):
+    """Every level's Galerkin product in the dense MFMA form (galerkin_device = 3): the host's
+    levels and patterns, values within rounding of the host's, and a solve that converges like
+    the host hierarchy's."""
+    c = bc.make_case(*dims, seed=9)
+    ops = fem.assemble_operators(c)
+    A = ops["Aell"]
+    hd = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, galerkin_device=3), ops["m"])
+    hh = lib.bidomain_amg_build_host(A, lib.bidomain_default_opts(nullspace=1))
+    try:
+        idd, ih = lib.bidomain_amg_info(hd), lib.bidomain_amg_info(hh)
+        print(f"[gpu] dense device Galerkin dims={dims} levels={idd['n']}", flush=True)
+        assert idd["n"] == ih["n"] and idd["nnz"] == ih["nnz"]
+        for k in range(1, idd["nlevels"]):
+            rd, cd, vd, _ = lib.bidomain_amg_export(hd, k, 0)
+            rh, ch, vh, _ = lib.bidomain_amg_export(hh, k, 0)
+            assert np.array_equal(rd, rh) and np.array_equal(cd, ch), k
+            assert np.max(np.abs(vd - vh)) <= 1e-11 * np.max(np.abs(vh)), k
+    finally:
+        lib.bidomain_amg_destroy(hd)
+        lib.bidomain_amg_destroy(hh)
+

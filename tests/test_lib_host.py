@@ -196,3 +196,26 @@ def test_invalid_ellipsoids_are_rejected(change):
     with pytest.raises(lib.BidomainError) as e:
         lib.bidomain_ellipsoid_assemble(c, lib.BD_MAT_AELL)
     assert e.value.status == lib.BD_E_INVALID
+
+
+def test_host_galerkin_product_matches_sparse_algebra():
+    """bidomain_galerkin on the host: (R A P + (R A P)^T) / 2 with R = P^T on the full structural
+    pattern of the product, against scipy's sparse products."""
+    import scipy.sparse as sp
+    c = bc.make_case(9, 7, 5, seed=2)
+    A = fem.assemble_operators(c)["Aell"]
+    h = amg.setup(A, amg.AMGOptions(nullspace=True))
+    P = h.levels[0].P
+    C = lib.bidomain_galerkin(A, P, on_device=False)
+    R = (P.T @ A @ P).tocsr()
+    ref = 0.5 * (R + R.T)
+    assert abs(C - ref).max() <= 1e-13 * abs(ref).max()
+    pat = (abs(P.T) @ abs(A) @ abs(P)).tocsr()
+    pat.sort_indices()
+    assert np.array_equal(C.indptr, pat.indptr) and np.array_equal(C.indices, pat.indices)
+    bad = A.copy()
+    bad.data = bad.data.copy()
+    bad.data[bad.indptr[0]] = -1.0      # row 0's diagonal
+    with pytest.raises(lib.BidomainError):
+        lib.bidomain_galerkin(bad, P, on_device=False)
+    assert lib.bidomain_galerkin(A, sp.csr_matrix(P.shape), on_device=False).nnz == 0
