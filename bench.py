@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
-PMC_FILES = [os.path.join(ROOT, "profiles", f) for f in ("pmc_outer_spmv_c5.json", "pmc_outer_spmv_c2.json")]
+PMC_FILES = [os.path.join(ROOT, "profiles", "pmc_outer_spmv_c5.json")]
 # the kernels and their block -> tile mapping; a counter summary stays valid while these are unchanged
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2311_13914_amd", "csrc", "kernels.hpp")]
 
