@@ -52,6 +52,7 @@ enum { BD_CHEBYSHEV = 0, BD_JACOBI = 1 };      /* level smoother                
 enum { BD_F64 = 0, BD_F32 = 1 };               /* V-cycle precision                          */
 enum { BD_NULL_NONE = 0, BD_NULL_CONSTANT = 1 };/* kernel of the operator                    */
 enum { BD_PC_AMG = 0, BD_PC_JACOBI = 1, BD_PC_NONE = 2 }; /* preconditioner of the CG solve    */
+enum { BD_MIS_GREEDY = 0, BD_MIS_LUBY = 1 };   /* SA independent set                         */
 
 /*
  * AMG options.  Defaults (bidomain_default_opts) follow App. A of the paper: smoothed
@@ -98,6 +99,15 @@ typedef struct {
    * With JACOBI or NONE the setup keeps the fine level only and vcycle_precision must be
    * BD_F64; the serving API takes BD_PC_AMG only. */
   int32_t preconditioner;
+  /* Independent set of the SA levels (Sec. 4: greedy, or its parallel form after Luby):
+   * BD_MIS_GREEDY visits the nodes in index order (default); BD_MIS_LUBY takes them in
+   * decreasing random priority (the top 32 bits of SplitMix64 draws from seed + 0x4C554259 +
+   * level, above the node index), the set the parallel rounds reach. */
+  int32_t independent_set;
+  /* 1: with BD_MIS_LUBY, build each SA level's strength graph, independent set (parallel
+   * rounds), aggregates and tentative and smoothed prolongators on the device with this
+   * library's kernels -- the host's result bit for bit; 0 (default): on the host. */
+  int32_t aggregate_device;
 } bd_amg_opts;
 
 void bidomain_default_opts(bd_amg_opts* opts);

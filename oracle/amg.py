@@ -64,6 +64,8 @@ class AMGOptions:
     nullspace: bool = False         # True: pure Neumann operator with constant kernel
     stagnation_ratio: float = 0.9   # stop coarsening when n_c > ratio * n_k
     coarse_dense_max: int = 2048    # larger coarsest levels are relaxed by their smoother
+    mis: str = "greedy"             # SA independent set: "greedy" (index order) or "luby"
+                                    # (random priorities, the parallel algorithm's outcome)
 
 
 @dataclass
@@ -174,12 +176,29 @@ def sa_strength(A: sp.csr_matrix, theta: float) -> sp.csr_matrix:
     return G
 
 
-def greedy_mis(G: sp.csr_matrix, square: bool) -> np.ndarray:
-    """Greedy maximal independent set in index order on G (or on G^2, distance <= 2)."""
+LUBY_SEED_OFFSET = 0x4C554259   # keeps these draws apart from the other SplitMix64 streams
+
+
+def luby_keys(seed: int, level: int, n: int) -> np.ndarray:
+    """Priorities of the parallel independent set of a level: the top 32 bits of the SplitMix64
+    stream seeded with seed + LUBY_SEED_OFFSET + level, above the node index (so all differ)."""
+    z = splitmix64(seed + LUBY_SEED_OFFSET + level, n)
+    return ((z >> np.uint64(32)) << np.uint64(32)) | np.arange(n, dtype=np.uint64)
+
+
+def greedy_mis(G: sp.csr_matrix, square: bool, order=None) -> np.ndarray:
+    """Greedy maximal independent set on G (or on G^2, distance <= 2), visiting the nodes in
+    index order, or in the given order.
+
+    Sec. 4 allows the greedy MIS or its parallel form (Luby): in rounds, every free node whose
+    priority exceeds that of every free node within reach (distance 1, or 2 on a squared level)
+    becomes a root and the free nodes within its reach are taken.  With fixed priorities that
+    parallel process ends in the greedy set taken in decreasing priority order, which is how the
+    "luby" variant is computed here (order = nodes by decreasing luby_keys)."""
     n = G.shape[0]
     indptr, indices = G.indptr, G.indices
     state = bytearray(n)  # 0 free, 1 root, 2 taken by a root
-    for i in range(n):
+    for i in (range(n) if order is None else (int(v) for v in order)):
         if state[i]:
             continue
         state[i] = 1
@@ -418,7 +437,10 @@ def setup(A: sp.csr_matrix, opts: AMGOptions) -> Hierarchy:
         lvl.lam = estimate_lambda_max(A, lvl.Dinv, opts.esteig_iters, opts.seed + k)
         if opts.coarsening == "sa":
             G = sa_strength(A, opts.threshold)
-            roots = greedy_mis(G, square=k < opts.square_graph_levels)
+            order = None
+            if opts.mis == "luby":
+                order = np.argsort(luby_keys(opts.seed, k, n))[::-1]
+            roots = greedy_mis(G, square=k < opts.square_graph_levels, order=order)
             agg = sa_aggregate(G, roots)
             nc = int(roots.sum())
             Pt, Bc = tentative_prolongator(agg, B, nc)

@@ -23,6 +23,7 @@ BD_CHEBYSHEV, BD_JACOBI = 0, 1
 BD_F64, BD_F32 = 0, 1
 BD_NULL_NONE, BD_NULL_CONSTANT = 0, 1
 BD_PC_AMG, BD_PC_JACOBI, BD_PC_NONE = 0, 1, 2
+BD_MIS_GREEDY, BD_MIS_LUBY = 0, 1
 BD_OP_A, BD_OP_P, BD_OP_R, BD_OP_PRESMOOTH, BD_OP_VCYCLE, BD_OP_COARSE = range(6)
 BD_MAT_AI, BD_MAT_AE, BD_MAT_AELL, BD_MAT_APAR = range(4)
 BD_V, BD_UE, BD_W = range(3)
@@ -39,7 +40,8 @@ class bd_amg_opts(C.Structure):
                 ("cheb_hi", C.c_double), ("esteig_iters", C.c_int32), ("seed", C.c_uint64),
                 ("vcycle_precision", C.c_int32), ("nullspace", C.c_int32), ("stagnation_ratio", C.c_double),
                 ("coarse_dense_max", C.c_int32), ("galerkin_device", C.c_int32),
-                ("diag_form", C.c_int32), ("preconditioner", C.c_int32)]
+                ("diag_form", C.c_int32), ("preconditioner", C.c_int32), ("independent_set", C.c_int32),
+                ("aggregate_device", C.c_int32)]
 
 
 class bd_csr(C.Structure):

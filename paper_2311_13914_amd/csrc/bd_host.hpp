@@ -57,9 +57,20 @@ struct HostHierarchy {
 // and returns true, or returns false and the host computes it.
 using GalerkinOffload = std::function<bool(const Csr& A, const Csr& P, const Csr& R, int64_t sparse_flops, Csr& Ac)>;
 
+// The SA prolongator of a level on another engine (independent set BD_MIS_LUBY): given A_k, its
+// diagonal d and D^{-1}, the near-null vector B_k, lambda and the level index, either fills P_k,
+// B_{k+1} and the number of aggregates exactly as the host would and returns true, or returns
+// false and the host builds them.
+using AggregateOffload = std::function<bool(const Csr& A, const std::vector<double>& d, const std::vector<double>& Dinv,
+                                            const std::vector<double>& B, double lam, int level, Csr& P,
+                                            std::vector<double>& Bc, int32_t& nc)>;
+
+// SplitMix64 stream offset of the parallel independent set's priorities (seed + offset + level).
+constexpr uint64_t kLubySeedOffset = 0x4C554259;
+
 // Setup phase: returns BD_OK or a BD_E_* code with a message in err.
 int build_hierarchy(Csr A, const bd_amg_opts& o, HostHierarchy& H, std::string& err,
-                    const GalerkinOffload* offload = nullptr);
+                    const GalerkinOffload* offload = nullptr, const AggregateOffload* agg_offload = nullptr);
 
 // Largest Ritz value of D^{-1} A after `iters` Jacobi-CG steps from a SplitMix64 vector.
 double lambda_estimate(const Csr& A, const std::vector<double>& Dinv, int iters, uint64_t seed);

@@ -1444,6 +1444,8 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
       o.coarse_dense_max < 1 || (o.coarsening != BD_SA && o.coarsening != BD_RS && o.coarsening != BD_PMIS) ||
       o.galerkin_device < 0 || o.galerkin_device > 3 || o.diag_form < 0 || o.diag_form > 1 ||
       o.preconditioner < BD_PC_AMG || o.preconditioner > BD_PC_NONE ||
+      (o.independent_set != BD_MIS_GREEDY && o.independent_set != BD_MIS_LUBY) || o.aggregate_device < 0 ||
+      o.aggregate_device > 1 ||
       (o.preconditioner != BD_PC_AMG && o.vcycle_precision != BD_F64) ||
       (o.smoother != BD_CHEBYSHEV && o.smoother != BD_JACOBI) ||
       (o.vcycle_precision != BD_F64 && o.vcycle_precision != BD_F32))

@@ -10,6 +10,7 @@
 // singular).  Tie and threshold rules are spelled out where they are applied; they make the
 // hierarchy independent of the rounding of the matrix entries.
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -264,6 +265,12 @@ uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
   return z ^ (z >> 31);
 }
 
+// Priority of node i in the parallel independent set of level k: the top 32 bits of the level's
+// SplitMix64 draw above the node index (all distinct).
+uint64_t luby_key(uint64_t seed, int level, int32_t i) {
+  return ((splitmix64_at(seed + kLubySeedOffset + (uint64_t)level, (uint64_t)i) >> 32) << 32) | (uint64_t)(uint32_t)i;
+}
+
 // Largest eigenvalue of the symmetric tridiagonal (diag a, off-diagonal b) by bisection on
 // the Sturm sequence count.
 double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
@@ -410,10 +417,12 @@ Graph sa_strength(const Csr& A, const std::vector<double>& d, double theta) {
   return G;
 }
 
-// Greedy MIS in index order; with `square`, a new root also takes its distance-2 nodes.
-std::vector<uint8_t> greedy_mis(const Graph& G, int32_t n, bool square) {
+// Greedy MIS in index order, or in the order `order` (a permutation); with `square`, a new root
+// also takes its distance-2 nodes.
+std::vector<uint8_t> greedy_mis(const Graph& G, int32_t n, bool square, const std::vector<int32_t>* order = nullptr) {
   std::vector<uint8_t> st(n, 0);  // 0 free, 1 root, 2 taken
-  for (int32_t i = 0; i < n; ++i) {
+  for (int32_t q = 0; q < n; ++q) {
+    const int32_t i = order ? (*order)[q] : q;
     if (st[i]) continue;
     st[i] = 1;
     for (int32_t k = G.rp[i]; k < G.rp[i + 1]; ++k) {
@@ -792,7 +801,7 @@ Csr symmetrized(const Csr& A) { return symmetrize(A); }
 // With BIDOMAIN_SETUP_LOG set in the environment, one line per level goes to stderr as the
 // setup proceeds (large hierarchies take minutes on the host).
 int build_hierarchy(Csr A0, const bd_amg_opts& o, HostHierarchy& H, std::string& err,
-                    const GalerkinOffload* offload) {
+                    const GalerkinOffload* offload, const AggregateOffload* agg_offload) {
   const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
   const auto t_start = std::chrono::steady_clock::now();
   auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count(); };
@@ -833,18 +842,35 @@ int build_hierarchy(Csr A0, const bd_amg_opts& o, HostHierarchy& H, std::string&
     std::vector<double> Bc;
     int32_t nc = 0;
     if (o.coarsening == BD_SA) {
-      const Graph G = sa_strength(cur.A, d, o.threshold);
-      stamp(k, "strength graph");
-      const std::vector<uint8_t> st = greedy_mis(G, n, k < o.square_graph_levels);
-      stamp(k, "independent set");
-      std::vector<int32_t> agg;
-      nc = sa_aggregate(G, st, agg);
-      if (nc < 0) {
-        err = "aggregation left nodes unassigned";
-        return BD_E_INVALID;
+      bool done = false;
+      if (agg_offload && o.independent_set == BD_MIS_LUBY) {
+        done = (*agg_offload)(cur.A, d, cur.Dinv, cur.B, cur.lam, k, P, Bc, nc);
+        if (done) stamp(k, "strength, independent set, aggregates and prolongator on the device");
       }
-      P = sa_prolongator(cur.A, cur.Dinv, cur.B, agg, nc, cur.lam, o.prolong_smooths, Bc);
-      stamp(k, "aggregates and smoothed prolongator");
+      if (!done) {
+        const Graph G = sa_strength(cur.A, d, o.threshold);
+        stamp(k, "strength graph");
+        std::vector<int32_t> order;
+        if (o.independent_set == BD_MIS_LUBY) {  // decreasing priority (the index in the low bits)
+          std::vector<uint64_t> key(n);
+#pragma omp parallel for schedule(static, 4096)
+          for (int32_t i = 0; i < n; ++i) key[i] = luby_key(o.seed, k, i);
+          std::sort(key.begin(), key.end(), std::greater<uint64_t>());
+          order.resize(n);
+          for (int32_t q = 0; q < n; ++q) order[q] = (int32_t)(key[q] & 0xFFFFFFFFu);
+        }
+        const std::vector<uint8_t> st =
+            greedy_mis(G, n, k < o.square_graph_levels, o.independent_set == BD_MIS_LUBY ? &order : nullptr);
+        stamp(k, "independent set");
+        std::vector<int32_t> agg;
+        nc = sa_aggregate(G, st, agg);
+        if (nc < 0) {
+          err = "aggregation left nodes unassigned";
+          return BD_E_INVALID;
+        }
+        P = sa_prolongator(cur.A, cur.Dinv, cur.B, agg, nc, cur.lam, o.prolong_smooths, Bc);
+        stamp(k, "aggregates and smoothed prolongator");
+      }
     } else {
       const Csr S = rs_strength(cur.A, o.threshold);
       const std::vector<uint8_t> st =
@@ -923,4 +949,6 @@ extern "C" void bidomain_default_opts(bd_amg_opts* o) {
   o->galerkin_device = 1;
   o->diag_form = 1;
   o->preconditioner = BD_PC_AMG;
+  o->independent_set = BD_MIS_GREEDY;
+  o->aggregate_device = 0;
 }

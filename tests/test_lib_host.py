@@ -73,7 +73,7 @@ def _compare_hierarchies(h_lib, h_or, tol=1e-11):
             assert abs(Rl - lv.R).max() <= tol * abs(lv.R).max(), f"R_{k}"
 
 
-@pytest.mark.parametrize("variant", ["sa_ell", "sa_par", "rs_ell", "pmis_ell"])
+@pytest.mark.parametrize("variant", ["sa_ell", "sa_par", "rs_ell", "pmis_ell", "luby_ell", "luby_par"])
 @pytest.mark.parametrize("dims", [(16, 16, 8), (24, 20, 10)])
 def test_host_setup_matches_oracle(variant, dims):
     c = bc.make_case(*dims, seed=1)
@@ -85,9 +85,15 @@ def test_host_setup_matches_oracle(variant, dims):
     elif variant == "rs_ell":
         A, oo, lo = ops["Aell"], amg.AMGOptions(coarsening="rs", threshold=0.5, nullspace=True), \
             dict(coarsening=lib.BD_RS, threshold=0.5, nullspace=1)
-    else:
+    elif variant == "pmis_ell":
         A, oo, lo = ops["Aell"], amg.AMGOptions(coarsening="pmis", threshold=0.5, nullspace=True, seed=3), \
             dict(coarsening=lib.BD_PMIS, threshold=0.5, nullspace=1, seed=3)
+    elif variant == "luby_ell":
+        A, oo, lo = ops["Aell"], amg.AMGOptions(nullspace=True, mis="luby", seed=5), \
+            dict(nullspace=1, independent_set=lib.BD_MIS_LUBY, seed=5)
+    else:
+        A, oo, lo = ops["Apar"], amg.AMGOptions(mis="luby", seed=6, threshold=0.0), \
+            dict(independent_set=lib.BD_MIS_LUBY, seed=6, threshold=0.0)
     h_or = amg.setup(A, oo)
     h = lib.bidomain_amg_build_host(A, lib.bidomain_default_opts(**lo))
     try:

@@ -312,3 +312,93 @@ def test_pmis_invariants_on_c1():
         r = amg.pmis_random(0, k, lv.A.shape[0])
         assert 0.0 <= r.min() and r.max() < 1.0
         assert np.array_equal(amg.pmis_split(S, r), lv.cpts)
+
+
+def test_luby_order_on_a_path_by_hand():
+    """Path 0 - 1 - 2 - 3 - 4, priorities (5, 9, 1, 7, 3): unsquared, 1 (9) takes 0 and 2, then 3
+    (7) takes 4 -> roots {1, 3}; squared, 1 takes 0, 2 and 3, and 4 (distance 3 from 1) becomes
+    a root -> roots {1, 4}."""
+    A = _path_laplacian(5)
+    G = amg.sa_strength(A, 0.06)
+    keys = np.array([5, 9, 1, 7, 3], dtype=np.uint64)
+    order = np.argsort(keys)[::-1]
+    assert np.flatnonzero(amg.greedy_mis(G, square=False, order=order)).tolist() == [1, 3]
+    assert np.flatnonzero(amg.greedy_mis(G, square=True, order=order)).tolist() == [1, 4]
+
+
+def _parallel_rounds(G, keys, square):
+    """The parallel (Luby-type) independent set written as its rounds: every free node whose key
+    beats all free nodes within reach becomes a root; the free nodes within reach of a new root
+    are taken.  Reach = neighbours in G, or nodes within distance 2 when squared."""
+    n = G.shape[0]
+    R = (G + sp.eye(n)).tocsr()
+    if square:
+        R = (R @ R).tocsr()
+    R = (R != 0).astype(np.int8).tocsr()
+    rows = np.repeat(np.arange(n), np.diff(R.indptr))
+    cols = R.indices
+    FREE, ROOT, TAKEN = 0, 1, 2
+    st = np.zeros(n, dtype=np.int8)
+    kf = keys.astype(object)
+    while np.any(st == FREE):
+        free = st == FREE
+        best = np.zeros(n, dtype=object)
+        for r, c in zip(rows.tolist(), cols.tolist()):
+            if free[c] and kf[c] > best[r]:
+                best[r] = kf[c]
+        new = free & np.array([best[i] == kf[i] for i in range(n)])
+        assert new.any()
+        st[new] = ROOT
+        reach = (R @ new.astype(np.int64)) > 0
+        st[(st == FREE) & reach] = TAKEN
+    return st == ROOT
+
+
+@pytest.mark.parametrize("square", [False, True])
+def test_luby_order_equals_the_parallel_rounds(square):
+    """With fixed priorities the parallel rounds end in the greedy set taken in decreasing
+    priority order (the oracle's 'luby' variant): checked on random graphs and on a slab's
+    strength graph, against the rounds written out above."""
+    rng = np.random.default_rng(11)
+    graphs = []
+    for n in (30, 60):
+        M = sp.random(n, n, density=0.08, random_state=rng, format="csr")
+        M = ((M + M.T) != 0).astype(np.float64)
+        M.setdiag(0)
+        M.eliminate_zeros()
+        graphs.append(M.tocsr())
+    A = fem.assemble_operators(bc.make_case(5, 4, 3, seed=1))["Aell"]
+    graphs.append(amg.sa_strength(A, 0.06))
+    for G in graphs:
+        n = G.shape[0]
+        keys = amg.luby_keys(7, 2, n)
+        mis = amg.greedy_mis(G, square=square, order=np.argsort(keys)[::-1])
+        assert np.array_equal(mis, _parallel_rounds(G, keys, square))
+
+
+def test_luby_keys_are_distinct_and_follow_the_stream():
+    keys = amg.luby_keys(5, 3, 1000)
+    assert len(set(keys.tolist())) == 1000
+    z = amg.splitmix64(5 + amg.LUBY_SEED_OFFSET + 3, 1000)
+    assert np.array_equal(keys >> np.uint64(32), z >> np.uint64(32))
+    assert np.array_equal(keys & np.uint64(0xFFFFFFFF), np.arange(1000, dtype=np.uint64))
+
+
+def test_luby_hierarchy_invariants_on_c1():
+    """The SA hierarchy with the parallel independent set keeps the SA invariants: roots
+    independent within distance 2 on the first level, every node aggregated, P B_c = B."""
+    c = bc.config_case("C1")
+    A = fem.assemble_operators(c)["Aell"]
+    h = amg.setup(A, amg.AMGOptions(nullspace=True, mis="luby", seed=4))
+    hg = amg.setup(A, amg.AMGOptions(nullspace=True))
+    lv = h.levels[0]
+    G = amg.sa_strength(A, 0.06)
+    roots = amg.greedy_mis(G, square=True, order=np.argsort(amg.luby_keys(4, 0, A.shape[0]))[::-1])
+    R2 = ((G + sp.eye(A.shape[0])) @ (G + sp.eye(A.shape[0]))).tocsr()
+    ri = np.flatnonzero(roots)
+    sub = R2[ri][:, ri]
+    assert sub.nnz == ri.size                      # only the diagonal: no two roots within reach
+    assert np.all((R2 @ roots.astype(float)) > 0)  # maximal
+    assert lv.P.shape[1] == ri.size
+    assert np.allclose(lv.P @ h.levels[1].B, lv.B)
+    assert h.levels[1].A.shape != hg.levels[1].A.shape or not np.array_equal(lv.agg, hg.levels[0].agg)
