@@ -29,6 +29,16 @@ Csr transpose(const Csr& A);
 Csr spgemm(const Csr& A, const Csr& B);
 // (A + A^T) / 2 on A's pattern (a mirror entry that does not exist counts as zero).
 Csr symmetrized(const Csr& A);
+// Tentative SA prolongator: P(i, agg[i]) = B_i / |B restricted to the aggregate| (norms summed in
+// index order); Bc receives the norms (the coarse near-null vector).
+Csr tentative_prolongator(const std::vector<double>& B, const std::vector<int32_t>& agg, int32_t nc,
+                          std::vector<double>& Bc);
+// Damping of the prolongator smoothing, 4 / (3 lambda).
+double prolongator_damping(double lam);
+// SA strength: a coupling is strong when its weight is >= strength_cut(theta); weights >=
+// tie_keep() times the largest tie in the aggregation passes.
+double strength_cut(double theta);
+double tie_keep();
 std::vector<double> diagonal(const Csr& A);
 // Checks the boundary's CSR contract; returns an empty string when valid.
 std::string validate(const Csr& A);

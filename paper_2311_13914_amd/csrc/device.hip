@@ -22,6 +22,7 @@
 #include "kernels.hpp"
 #include "spgemm.hpp"
 #include "galerkin_dense.hpp"
+#include "aggregate.hpp"
 
 namespace bd {
 
@@ -1429,6 +1430,131 @@ bool sparse_galerkin(const Csr& A, const Csr& P, const Csr& R, int64_t sparse_fl
   return ok;
 }
 
+// SA coarsening of a level on the device (aggregate.hpp): strength graph, parallel independent
+// set, aggregation passes and the prolongator smoothing's product and combination; the O(n)
+// bookkeeping between them (aggregate ranks, the tentative prolongator's norms in index order)
+// on the host with the host's own routine.  The result is the host setup's bit for bit (tests
+// compare whole hierarchies).  false (the host builds the level) when memory is refused or a
+// call fails.
+bool device_sa_level(const Csr& A, const std::vector<double>& d, const std::vector<double>& Dinv,
+                     const std::vector<double>& B, double lam, int level, const bd_amg_opts& o, bool log, Csr& P,
+                     std::vector<double>& Bc, int32_t& nc, const TransientBudget* tb) {
+  using namespace ag;
+  const int n = A.nrows;
+  const bool square = level < o.square_graph_levels;
+  std::lock_guard<std::mutex> lock(g_galerkin_mu);
+  hipStream_t st = nullptr;
+  if (hipStreamCreate(&st) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  bool ok = false;
+  {
+    DevScratch s;
+    s.tb = tb;
+    const auto t0 = std::chrono::steady_clock::now();
+    const DevCsr dA = upload_csr(s, A, st);
+    double* dd = s.alloc<double>(n);
+    double* ddinv = s.alloc<double>(n);
+    int* cnt = s.alloc<int>(n);
+    if (!s.ok) goto done;
+    s.check(hipMemcpyAsync(dd, d.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    s.check(hipMemcpyAsync(ddinv, Dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    {
+      const int g = grid_for(n, kBlock, 8192);
+      const double cut = strength_cut(o.threshold), keep = tie_keep();
+      k_ag_strength<0><<<g, kBlock, 0, st>>>(dA.rp, dA.ci, dA.v, dd, n, cut, cnt, nullptr, nullptr, nullptr);
+      std::vector<int> hv(n), srp(n + 1, 0);
+      s.check(hipMemcpyAsync(hv.data(), cnt, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+      s.check(hipStreamSynchronize(st));
+      if (!s.ok) goto done;
+      for (int i = 0; i < n; ++i) srp[i + 1] = srp[i] + hv[i];
+      int* dsrp = s.alloc<int>(n + 1);
+      int* dsci = s.alloc<int>(srp[n]);
+      double* dsw = s.alloc<double>(srp[n]);
+      uint64_t* key = s.alloc<uint64_t>(n);
+      uint64_t* m1 = s.alloc<uint64_t>(n);
+      uint64_t* m2 = s.alloc<uint64_t>(n);
+      uint8_t* stt = s.alloc<uint8_t>(n);
+      uint8_t* mark = s.alloc<uint8_t>(n);
+      uint8_t* r1 = s.alloc<uint8_t>(n);
+      uint8_t* r2 = s.alloc<uint8_t>(n);
+      int* nfree = s.alloc<int>(1);
+      int* root1 = s.alloc<int>(n);
+      int* root2 = s.alloc<int>(n);
+      if (!s.ok) goto done;
+      s.check(hipMemcpyAsync(dsrp, srp.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, st));
+      k_ag_strength<1><<<g, kBlock, 0, st>>>(dA.rp, dA.ci, dA.v, dd, n, cut, nullptr, dsrp, dsci, dsw);
+      k_ag_keys<<<g, kBlock, 0, st>>>(n, o.seed + kLubySeedOffset + (uint64_t)level, key, stt);
+      int rounds = 0, free_left = n;
+      while (free_left > 0 && s.ok) {
+        // every round makes at least the largest free key a root, and random priorities finish
+        // in O(log n) rounds; a run past 1000 rounds is handed to the host
+        if (++rounds > 1000) goto done;
+        s.check(hipMemsetAsync(nfree, 0, sizeof(int), st));
+        k_ag_max<true><<<g, kBlock, 0, st>>>(dsrp, dsci, n, key, stt, m1);
+        if (square) k_ag_max<false><<<g, kBlock, 0, st>>>(dsrp, dsci, n, m1, stt, m2);
+        k_ag_select<<<g, kBlock, 0, st>>>(n, square ? m2 : m1, key, stt, mark);
+        k_ag_reach<<<g, kBlock, 0, st>>>(dsrp, dsci, n, mark, r1);
+        if (square) k_ag_reach<<<g, kBlock, 0, st>>>(dsrp, dsci, n, r1, r2);
+        k_ag_take<<<g, kBlock, 0, st>>>(n, square ? r2 : r1, stt, nfree);
+        s.check(hipGetLastError());
+        s.check(hipMemcpyAsync(&free_left, nfree, sizeof(int), hipMemcpyDeviceToHost, st));
+        s.check(hipStreamSynchronize(st));
+      }
+      k_ag_pass1<<<g, kBlock, 0, st>>>(dsrp, dsci, dsw, n, stt, keep, root1);
+      k_ag_pass2<<<g, kBlock, 0, st>>>(dsrp, dsci, dsw, n, root1, keep, root2);
+      s.check(hipGetLastError());
+      s.check(hipMemcpyAsync(hv.data(), root2, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+      s.check(hipStreamSynchronize(st));
+      if (!s.ok) goto done;
+      // aggregate = rank of the root (index order)
+      std::vector<int32_t> rank(n, -1), agg(n);
+      nc = 0;
+      for (int i = 0; i < n; ++i)
+        if (hv[i] == i) rank[i] = nc++;
+      for (int i = 0; i < n; ++i) {
+        if (hv[i] < 0 || rank[hv[i]] < 0) goto done;  // left out (the host reports it)
+        agg[i] = rank[hv[i]];
+      }
+      if (log)
+        std::fprintf(stderr, "[setup]   level %d on the device: %d rounds, %d aggregates (%.3f s)\n", level, rounds, nc,
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+      P = tentative_prolongator(B, agg, nc, Bc);
+      const double omega = prolongator_damping(lam);
+      for (int sm = 0; sm < o.prolong_smooths; ++sm) {
+        DevScratch s2;
+        s2.tb = tb;
+        const DevCsr dP = upload_csr(s2, P, st);
+        DevCsr AP;
+        if (!s2.ok || !device_spgemm(s2, dA, dP, AP, st, false)) goto done;
+        k_ag_smooth<<<grid_for(n, kBlock, 8192), kBlock, 0, st>>>(dP.rp, dP.ci, dP.v, AP.rp, AP.ci, AP.v, ddinv,
+                                                                  omega, n);
+        s2.check(hipGetLastError());
+        Csr Q;
+        Q.nrows = n;
+        Q.ncols = nc;
+        Q.rp.resize(n + 1);
+        Q.ci.resize(AP.nnz);
+        Q.v.resize(AP.nnz);
+        s2.check(hipMemcpyAsync(Q.rp.data(), AP.rp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, st));
+        if (AP.nnz) {
+          s2.check(hipMemcpyAsync(Q.ci.data(), AP.ci, sizeof(int) * AP.nnz, hipMemcpyDeviceToHost, st));
+          s2.check(hipMemcpyAsync(Q.v.data(), AP.v, sizeof(double) * AP.nnz, hipMemcpyDeviceToHost, st));
+        }
+        s2.check(hipStreamSynchronize(st));
+        if (!s2.ok) goto done;
+        P = std::move(Q);
+      }
+      ok = s.ok;
+    }
+  done:;
+  }
+  (void)hipStreamDestroy(st);
+  if (!ok && log) std::fprintf(stderr, "[setup] device coarsening of level %d unavailable, using the host\n", level);
+  return ok;
+}
+
 // host_only: build the hierarchy but do not upload it; use_device: the setup may run its
 // Galerkin products on the device (option galerkin_device); plan: build the launch plans (for a
 // hierarchy that will be uploaded).
@@ -1471,11 +1597,17 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   h->mixed = o.vcycle_precision == BD_F32;
   std::string err;
   const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
+  const AggregateOffload agg_offload = [&](const Csr& Ak, const std::vector<double>& dk, const std::vector<double>& Dk,
+                                           const std::vector<double>& Bk, double lam, int level, Csr& Pk,
+                                           std::vector<double>& Bc, int32_t& nc) {
+    return device_sa_level(Ak, dk, Dk, Bk, lam, level, o, log, Pk, Bc, nc, tb);
+  };
   const GalerkinOffload offload = [&](const Csr& Ak, const Csr& Pk, const Csr& Rk, int64_t flops, Csr& Ac) {
     return sparse_galerkin(Ak, Pk, Rk, flops, o.galerkin_device, log, Ac, tb);
   };
   const auto t0 = std::chrono::steady_clock::now();
-  const int rc = build_hierarchy(std::move(H), o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr);
+  const int rc = build_hierarchy(std::move(H), o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr,
+                                 use_device && o.aggregate_device == 1 ? &agg_offload : nullptr);
   if (rc != BD_OK) throw Failure{rc, err};
   if (plan) plan_hierarchy(h->H, o.diag_form != 0);  // launch plans, on this (possibly worker) thread
   if (log)

@@ -479,22 +479,8 @@ Csr sa_prolongator(const Csr& A, const std::vector<double>& Dinv, const std::vec
                    const std::vector<int32_t>& agg, int32_t nc, double lam, int nsmooth,
                    std::vector<double>& Bc) {
   const int32_t n = A.nrows;
-  std::vector<double> norm2(nc, 0.0);
-  for (int32_t i = 0; i < n; ++i) norm2[agg[i]] += B[i] * B[i];
-  Bc.resize(nc);
-  for (int32_t c = 0; c < nc; ++c) Bc[c] = std::sqrt(norm2[c]);
-  Csr P;
-  P.nrows = n;
-  P.ncols = nc;
-  P.rp.resize(n + 1);
-  P.ci.resize(n);
-  P.v.resize(n);
-  for (int32_t i = 0; i <= n; ++i) P.rp[i] = i;
-  for (int32_t i = 0; i < n; ++i) {
-    P.ci[i] = agg[i];
-    P.v[i] = B[i] / Bc[agg[i]];
-  }
-  const double omega = 4.0 / (3.0 * lam);
+  Csr P = tentative_prolongator(B, agg, nc, Bc);
+  const double omega = prolongator_damping(lam);
   for (int s = 0; s < nsmooth; ++s) {
     Csr AP = spgemm(A, P);  // pattern(AP) contains pattern(P): every diagonal a_ii is stored
 #pragma omp parallel for schedule(static)
@@ -796,6 +782,32 @@ int coarse_operator(const HostLevel& L, bool nullspace, std::vector<double>& G, 
 }  // namespace
 
 Csr symmetrized(const Csr& A) { return symmetrize(A); }
+
+Csr tentative_prolongator(const std::vector<double>& B, const std::vector<int32_t>& agg, int32_t nc,
+                          std::vector<double>& Bc) {
+  const int32_t n = (int32_t)agg.size();
+  std::vector<double> norm2(nc, 0.0);
+  for (int32_t i = 0; i < n; ++i) norm2[agg[i]] += B[i] * B[i];
+  Bc.resize(nc);
+  for (int32_t c = 0; c < nc; ++c) Bc[c] = std::sqrt(norm2[c]);
+  Csr P;
+  P.nrows = n;
+  P.ncols = nc;
+  P.rp.resize(n + 1);
+  P.ci.resize(n);
+  P.v.resize(n);
+  for (int32_t i = 0; i <= n; ++i) P.rp[i] = i;
+  for (int32_t i = 0; i < n; ++i) {
+    P.ci[i] = agg[i];
+    P.v[i] = B[i] / Bc[agg[i]];
+  }
+  return P;
+}
+
+double prolongator_damping(double lam) { return 4.0 / (3.0 * lam); }
+
+double strength_cut(double theta) { return theta * (1.0 - kTie); }
+double tie_keep() { return 1.0 - kTie; }
 
 // ------------------------------------------------------------------------------------------
 // With BIDOMAIN_SETUP_LOG set in the environment, one line per level goes to stderr as the

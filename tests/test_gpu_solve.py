@@ -558,3 +558,35 @@ def test_dense_device_galerkin_hierarchy(torch, dims):
         lib.bidomain_amg_destroy(hd)
         lib.bidomain_amg_destroy(hh)
 
+
+
+@pytest.mark.parametrize("case,kw", [("slab", dict(nullspace=1)), ("ragged", dict(nullspace=1, square_graph_levels=2)),
+                                     ("parabolic", dict(threshold=0.0)), ("ellipsoid", dict(nullspace=1))])
+def test_device_coarsening_equals_host(torch, case, kw):
+    """Strength graph, parallel independent set, aggregation and prolongator smoothing on the
+    device (aggregate_device = 1, with the sparse device Galerkin products) give the host
+    setup's hierarchy with the same independent set bit for bit: every level's A, P and R."""
+    from oracle import ellipsoid
+    if case == "ellipsoid":
+        ops = ellipsoid.assemble_operators(bc.EllipsoidCase(24, 16, 8))
+    else:
+        dims = {"slab": (24, 24, 12), "ragged": (37, 29, 13), "parabolic": (32, 32, 16)}[case]
+        ops = fem.assemble_operators(bc.make_case(*dims, seed=9))
+    A = ops["Apar"] if case == "parabolic" else ops["Aell"]
+    base = dict(independent_set=lib.BD_MIS_LUBY, seed=3, **kw)
+    hd = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(aggregate_device=1, galerkin_device=2, **base))
+    hh = lib.bidomain_amg_build_host(A, lib.bidomain_default_opts(**base))
+    try:
+        idd, ih = lib.bidomain_amg_info(hd), lib.bidomain_amg_info(hh)
+        print(f"[gpu] device coarsening {case}: levels {idd['n']} (host {ih['n']})", flush=True)
+        assert idd["n"] == ih["n"] and idd["nnz"] == ih["nnz"] and idd["p_nnz"] == ih["p_nnz"]
+        for k in range(idd["nlevels"]):
+            for which in ([0, 1, 2] if k + 1 < idd["nlevels"] else [0]):
+                rd, cd, vd, _ = lib.bidomain_amg_export(hd, k, which)
+                rh, ch, vh, _ = lib.bidomain_amg_export(hh, k, which)
+                assert np.array_equal(rd, rh) and np.array_equal(cd, ch), (k, which)
+                assert np.array_equal(vd, vh), (k, which, np.max(np.abs(vd - vh)))
+        assert np.array_equal(idd["lam"], ih["lam"], equal_nan=True)
+    finally:
+        lib.bidomain_amg_destroy(hd)
+        lib.bidomain_amg_destroy(hh)
