@@ -58,7 +58,8 @@ enum { BD_MIS_GREEDY = 0, BD_MIS_LUBY = 1 };   /* SA independent set            
  * AMG options.  Defaults (bidomain_default_opts) follow App. A of the paper: smoothed
  * aggregation with threshold 0.06, one prolongator smoothing, graph squaring on the first
  * level, coarse-equation limit 100, Chebyshev smoother of degree 2 on D^{-1}A over
- * [0.05, 1.05] x lambda with lambda from 10 Jacobi-CG steps.  For BD_RS, `threshold` is the
+ * [0.05, 1.05] x lambda with lambda from 10 Jacobi-CG steps; the independent set in its
+ * parallel form (Sec. 4).  For BD_RS, `threshold` is the
  * strong threshold alpha of eq. (10) (0.5 is the paper's CPU optimum).
  */
 typedef struct {
@@ -100,13 +101,14 @@ typedef struct {
    * BD_F64; the serving API takes BD_PC_AMG only. */
   int32_t preconditioner;
   /* Independent set of the SA levels (Sec. 4: greedy, or its parallel form after Luby):
-   * BD_MIS_GREEDY visits the nodes in index order (default); BD_MIS_LUBY takes them in
-   * decreasing random priority (the top 32 bits of SplitMix64 draws from seed + 0x4C554259 +
-   * level, above the node index), the set the parallel rounds reach. */
+   * BD_MIS_LUBY (default) takes the nodes in decreasing random priority (the top 32 bits of
+   * SplitMix64 draws from seed + 0x4C554259 + level, above the node index), the set the
+   * parallel rounds reach; BD_MIS_GREEDY visits them in index order. */
   int32_t independent_set;
-  /* 1: with BD_MIS_LUBY, build each SA level's strength graph, independent set (parallel
-   * rounds), aggregates and tentative and smoothed prolongators on the device with this
-   * library's kernels -- the host's result bit for bit; 0 (default): on the host. */
+  /* 1 (default): with BD_MIS_LUBY, each SA level's eigenvalue estimate, strength graph,
+   * independent set (parallel rounds), aggregates and smoothed prolongator are computed on the
+   * device with this library's kernels -- the host's result bit for bit; 0: on the host.
+   * bidomain_amg_build_host never uses the device. */
   int32_t aggregate_device;
 } bd_amg_opts;
 

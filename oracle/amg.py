@@ -64,8 +64,8 @@ class AMGOptions:
     nullspace: bool = False         # True: pure Neumann operator with constant kernel
     stagnation_ratio: float = 0.9   # stop coarsening when n_c > ratio * n_k
     coarse_dense_max: int = 2048    # larger coarsest levels are relaxed by their smoother
-    mis: str = "greedy"             # SA independent set: "greedy" (index order) or "luby"
-                                    # (random priorities, the parallel algorithm's outcome)
+    mis: str = "luby"               # SA independent set: "luby" (random priorities, the
+                                    # parallel algorithm's outcome) or "greedy" (index order)
 
 
 @dataclass

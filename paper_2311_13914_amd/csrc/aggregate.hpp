@@ -177,5 +177,69 @@ __global__ void k_ag_smooth(const int* __restrict__ prp, const int* __restrict__
   }
 }
 
+// ---- eigenvalue estimate: Jacobi-CG on D^{-1} A in the host's operation order -------------
+
+// r = the start vector (uniform in [-1, 1) from the stream `seed`), z = D^{-1} r, p = z.
+__global__ void k_lam_init(int n, uint64_t seed, const double* __restrict__ dinv, double* __restrict__ r,
+                           double* __restrict__ z, double* __restrict__ p) {
+#pragma clang fp contract(off)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double ri = 2.0 * ((double)(splitmix64_at(seed, (uint64_t)i) >> 11) * 0x1.0p-53) - 1.0;
+    r[i] = ri;
+    z[i] = dinv[i] * ri;
+    p[i] = z[i];
+  }
+}
+
+// q = A p, each row summed in order.
+__global__ void k_lam_spmv(const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                           const double* __restrict__ p, int n, double* __restrict__ q) {
+#pragma clang fp contract(off)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) s = s + v[k] * p[ci[k]];
+    q[i] = s;
+  }
+}
+
+// part[b] = sum of a[i] b[i] over block b of DB consecutive entries, in order: the block's
+// products are staged in LDS by 64 lanes, then added one by one.
+template <int DB>
+__global__ __launch_bounds__(64) void k_lam_dot_blocks(const double* __restrict__ a, const double* __restrict__ b,
+                                                       int64_t n, double* __restrict__ part) {
+#pragma clang fp contract(off)
+  __shared__ double prod[DB];
+  const int64_t nb = (n + DB - 1) / DB;
+  for (int64_t blk = blockIdx.x; blk < nb; blk += gridDim.x) {
+    const int64_t i0 = blk * DB;
+    const int len = (int)(n - i0 < DB ? n - i0 : DB);
+    for (int t = threadIdx.x; t < len; t += 64) prod[t] = a[i0 + t] * b[i0 + t];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = 0.0;
+      for (int t = 0; t < len; ++t) s = s + prod[t];
+      part[blk] = s;
+    }
+    __syncthreads();
+  }
+}
+
+// r -= alpha q; z = D^{-1} r.
+__global__ void k_lam_update_r(int n, double alpha, const double* __restrict__ q, const double* __restrict__ dinv,
+                               double* __restrict__ r, double* __restrict__ z) {
+#pragma clang fp contract(off)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    z[i] = dinv[i] * ri;
+  }
+}
+
+// p = z + beta p.
+__global__ void k_lam_update_p(int n, double beta, const double* __restrict__ z, double* __restrict__ p) {
+#pragma clang fp contract(off)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = z[i] + beta * p[i];
+}
+
 }  // namespace ag
 }  // namespace bd

@@ -67,12 +67,12 @@ struct HostHierarchy {
 // and returns true, or returns false and the host computes it.
 using GalerkinOffload = std::function<bool(const Csr& A, const Csr& P, const Csr& R, int64_t sparse_flops, Csr& Ac)>;
 
-// The SA prolongator of a level on another engine (independent set BD_MIS_LUBY): given A_k, its
-// diagonal d and D^{-1}, the near-null vector B_k, lambda and the level index, either fills P_k,
+// The SA coarsening of a level on another engine (independent set BD_MIS_LUBY): given A_k, its
+// diagonal d and D^{-1}, the near-null vector B_k and the level index, either fills lambda, P_k,
 // B_{k+1} and the number of aggregates exactly as the host would and returns true, or returns
 // false and the host builds them.
 using AggregateOffload = std::function<bool(const Csr& A, const std::vector<double>& d, const std::vector<double>& Dinv,
-                                            const std::vector<double>& B, double lam, int level, Csr& P,
+                                            const std::vector<double>& B, int level, double& lam, Csr& P,
                                             std::vector<double>& Bc, int32_t& nc)>;
 
 // SplitMix64 stream offset of the parallel independent set's priorities (seed + offset + level).
@@ -82,8 +82,14 @@ constexpr uint64_t kLubySeedOffset = 0x4C554259;
 int build_hierarchy(Csr A, const bd_amg_opts& o, HostHierarchy& H, std::string& err,
                     const GalerkinOffload* offload = nullptr, const AggregateOffload* agg_offload = nullptr);
 
-// Largest Ritz value of D^{-1} A after `iters` Jacobi-CG steps from a SplitMix64 vector.
+// Largest Ritz value of D^{-1} A after `iters` Jacobi-CG steps from a SplitMix64 vector.  Dot
+// products: blocks of kDotBlock entries summed in order, then the block sums in order.
 double lambda_estimate(const Csr& A, const std::vector<double>& Dinv, int iters, uint64_t seed);
+// The same from the CG coefficients (alpha, beta) such a run produced (the CG/Lanczos relation);
+// without any step, the largest diagonal entry of D^{-1} A.
+double ritz_from_cg(const Csr& A, const std::vector<double>& Dinv, const std::vector<double>& alpha,
+                    const std::vector<double>& beta);
+constexpr int kDotBlock = 4096;
 
 // Q1 slab operators (27-point pattern, structural zeros kept).
 void assemble_slab_stiffness(const bd_slab& s, double sig_l, double sig_t, Csr& A);

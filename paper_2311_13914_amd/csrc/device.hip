@@ -1430,14 +1430,15 @@ bool sparse_galerkin(const Csr& A, const Csr& P, const Csr& R, int64_t sparse_fl
   return ok;
 }
 
-// SA coarsening of a level on the device (aggregate.hpp): strength graph, parallel independent
-// set, aggregation passes and the prolongator smoothing's product and combination; the O(n)
+// SA coarsening of a level on the device (aggregate.hpp): eigenvalue estimate, strength graph,
+// parallel independent set, aggregation passes and the prolongator smoothing's product and
+// combination; the O(n)
 // bookkeeping between them (aggregate ranks, the tentative prolongator's norms in index order)
 // on the host with the host's own routine.  The result is the host setup's bit for bit (tests
 // compare whole hierarchies).  false (the host builds the level) when memory is refused or a
 // call fails.
 bool device_sa_level(const Csr& A, const std::vector<double>& d, const std::vector<double>& Dinv,
-                     const std::vector<double>& B, double lam, int level, const bd_amg_opts& o, bool log, Csr& P,
+                     const std::vector<double>& B, int level, const bd_amg_opts& o, bool log, double& lam, Csr& P,
                      std::vector<double>& Bc, int32_t& nc, const TransientBudget* tb) {
   using namespace ag;
   const int n = A.nrows;
@@ -1460,6 +1461,44 @@ bool device_sa_level(const Csr& A, const std::vector<double>& d, const std::vect
     if (!s.ok) goto done;
     s.check(hipMemcpyAsync(dd, d.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
     s.check(hipMemcpyAsync(ddinv, Dinv.data(), sizeof(double) * n, hipMemcpyHostToDevice, st));
+    {  // eigenvalue estimate: the host's Jacobi-CG steps and dot-product order
+      const int g = grid_for(n, kBlock, 8192);
+      double *r = s.alloc<double>(n), *z = s.alloc<double>(n), *p = s.alloc<double>(n), *q = s.alloc<double>(n);
+      const int64_t nb = (n + kDotBlock - 1) / kDotBlock;
+      double* part = s.alloc<double>(nb);
+      if (!s.ok) goto done;
+      std::vector<double> hp(nb);
+      auto dot = [&](const double* a, const double* b) {
+        k_lam_dot_blocks<kDotBlock><<<(int)std::min<int64_t>(nb, 65536), 64, 0, st>>>(a, b, n, part);
+        s.check(hipMemcpyAsync(hp.data(), part, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+        s.check(hipStreamSynchronize(st));
+        double acc = 0.0;
+        for (double v : hp) acc += v;
+        return acc;
+      };
+      k_lam_init<<<g, kBlock, 0, st>>>(n, o.seed + (uint64_t)level, ddinv, r, z, p);
+      double rho = dot(r, z);
+      const double rho0 = rho;
+      std::vector<double> alpha, beta;
+      for (int j = 0; j < o.esteig_iters && s.ok; ++j) {
+        k_lam_spmv<<<g, kBlock, 0, st>>>(dA.rp, dA.ci, dA.v, p, n, q);
+        const double pq = dot(p, q);
+        if (!(pq > 0.0)) break;
+        const double al = rho / pq;
+        alpha.push_back(al);
+        if (j == o.esteig_iters - 1) break;
+        k_lam_update_r<<<g, kBlock, 0, st>>>(n, al, q, ddinv, r, z);
+        const double rn = dot(r, z);
+        if (!(rn > 1e-28 * rho0)) break;
+        const double be = rn / rho;
+        beta.push_back(be);
+        k_lam_update_p<<<g, kBlock, 0, st>>>(n, be, z, p);
+        rho = rn;
+      }
+      s.check(hipGetLastError());
+      if (!s.ok) goto done;
+      lam = ritz_from_cg(A, Dinv, alpha, beta);
+    }
     {
       const int g = grid_for(n, kBlock, 8192);
       const double cut = strength_cut(o.threshold), keep = tie_keep();
@@ -1598,9 +1637,9 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   std::string err;
   const bool log = std::getenv("BIDOMAIN_SETUP_LOG") != nullptr;
   const AggregateOffload agg_offload = [&](const Csr& Ak, const std::vector<double>& dk, const std::vector<double>& Dk,
-                                           const std::vector<double>& Bk, double lam, int level, Csr& Pk,
+                                           const std::vector<double>& Bk, int level, double& lam, Csr& Pk,
                                            std::vector<double>& Bc, int32_t& nc) {
-    return device_sa_level(Ak, dk, Dk, Bk, lam, level, o, log, Pk, Bc, nc, tb);
+    return device_sa_level(Ak, dk, Dk, Bk, level, o, log, lam, Pk, Bc, nc, tb);
   };
   const GalerkinOffload offload = [&](const Csr& Ak, const Csr& Pk, const Csr& Rk, int64_t flops, Csr& Ac) {
     return sparse_galerkin(Ak, Pk, Rk, flops, o.galerkin_device, log, Ac, tb);

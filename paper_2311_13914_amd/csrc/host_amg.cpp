@@ -305,12 +305,12 @@ namespace {
 // Dot product in a fixed order independent of the thread count: 4096-entry blocks summed in
 // parallel, then the block sums in index order.
 double fixed_dot(const std::vector<double>& a, const std::vector<double>& b) {
-  const int64_t n = (int64_t)a.size(), nb = (n + 4095) / 4096;
+  const int64_t n = (int64_t)a.size(), nb = (n + kDotBlock - 1) / kDotBlock;
   std::vector<double> part(nb, 0.0);
 #pragma omp parallel for schedule(static)
   for (int64_t blk = 0; blk < nb; ++blk) {
     double s = 0.0;
-    for (int64_t i = blk * 4096; i < std::min(n, (blk + 1) * 4096); ++i) s += a[i] * b[i];
+    for (int64_t i = blk * kDotBlock; i < std::min(n, (blk + 1) * kDotBlock); ++i) s += a[i] * b[i];
     part[blk] = s;
   }
   double s = 0.0;
@@ -356,6 +356,12 @@ double lambda_estimate(const Csr& A, const std::vector<double>& Dinv, int iters,
     for (int32_t i = 0; i < n; ++i) p[i] = z[i] + be * p[i];
     rho = rn;
   }
+  return ritz_from_cg(A, Dinv, alpha, beta);
+}
+
+double ritz_from_cg(const Csr& A, const std::vector<double>& Dinv, const std::vector<double>& alpha,
+                    const std::vector<double>& beta) {
+  const int32_t n = A.nrows;
   const int m = (int)alpha.size();
   if (m == 0) {
     double mx = 0.0;
@@ -848,18 +854,20 @@ int build_hierarchy(Csr A0, const bd_amg_opts& o, HostHierarchy& H, std::string&
       err = bad_diag;
       return BD_E_INVALID;
     }
-    cur.lam = lambda_estimate(cur.A, cur.Dinv, o.esteig_iters, o.seed + (uint64_t)k);
-    stamp(k, "eigenvalue estimate");
     Csr P;
     std::vector<double> Bc;
     int32_t nc = 0;
+    bool on_device = false;
+    if (o.coarsening == BD_SA && agg_offload && o.independent_set == BD_MIS_LUBY) {
+      on_device = (*agg_offload)(cur.A, d, cur.Dinv, cur.B, k, cur.lam, P, Bc, nc);
+      if (on_device) stamp(k, "eigenvalue estimate, strength, independent set, aggregates and prolongator on the device");
+    }
+    if (!on_device) {
+      cur.lam = lambda_estimate(cur.A, cur.Dinv, o.esteig_iters, o.seed + (uint64_t)k);
+      stamp(k, "eigenvalue estimate");
+    }
     if (o.coarsening == BD_SA) {
-      bool done = false;
-      if (agg_offload && o.independent_set == BD_MIS_LUBY) {
-        done = (*agg_offload)(cur.A, d, cur.Dinv, cur.B, cur.lam, k, P, Bc, nc);
-        if (done) stamp(k, "strength, independent set, aggregates and prolongator on the device");
-      }
-      if (!done) {
+      if (!on_device) {
         const Graph G = sa_strength(cur.A, d, o.threshold);
         stamp(k, "strength graph");
         std::vector<int32_t> order;
@@ -961,6 +969,6 @@ extern "C" void bidomain_default_opts(bd_amg_opts* o) {
   o->galerkin_device = 1;
   o->diag_form = 1;
   o->preconditioner = BD_PC_AMG;
-  o->independent_set = BD_MIS_GREEDY;
-  o->aggregate_device = 0;
+  o->independent_set = BD_MIS_LUBY;
+  o->aggregate_device = 1;
 }

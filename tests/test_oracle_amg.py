@@ -177,11 +177,12 @@ def test_smoothed_prolongator_in_setup_dirichlet_path():
     A = tridiag(-1, 2, -1) on four nodes (SPD), D = 2 I.  D^-1 A has eigenvalues 1 - cos(k pi/5),
     k = 1..4, so after a complete Krylov space lambda = 1 + cos(pi/5) = (5 + 5^1/2)/4 and
     omega = 4/(3 lambda) = 4 (5 - 5^1/2)/15.  All couplings have weight 1/2; node 1 ties between
-    roots 0 and 2 and joins 0, so the aggregates are {0, 1}, {2, 3}.  D^-1 A P_t =
+    roots 0 and 2 and joins 0 (greedy independent set in index order), so the aggregates are
+    {0, 1}, {2, 3}.  D^-1 A P_t =
     (s/2) [[1,0],[1,-1],[-1,1],[0,1]], hence P = s [[1-w,0],[1-w,w],[w,1-w],[0,1-w]], w = omega/2.
     """
     A = sp.csr_matrix(np.array([[2., -1, 0, 0], [-1, 2, -1, 0], [0, -1, 2, -1], [0, 0, -1, 2]]))
-    h = amg.setup(A, amg.AMGOptions(coarse_eq_limit=2, square_graph_levels=0))
+    h = amg.setup(A, amg.AMGOptions(coarse_eq_limit=2, square_graph_levels=0, mis="greedy"))
     lv = h.levels[0]
     assert lv.agg.tolist() == [0, 0, 1, 1]
     assert lv.lam == pytest.approx((5 + 5 ** 0.5) / 4, rel=1e-14)
@@ -390,7 +391,7 @@ def test_luby_hierarchy_invariants_on_c1():
     c = bc.config_case("C1")
     A = fem.assemble_operators(c)["Aell"]
     h = amg.setup(A, amg.AMGOptions(nullspace=True, mis="luby", seed=4))
-    hg = amg.setup(A, amg.AMGOptions(nullspace=True))
+    hg = amg.setup(A, amg.AMGOptions(nullspace=True, mis="greedy"))
     lv = h.levels[0]
     G = amg.sa_strength(A, 0.06)
     roots = amg.greedy_mis(G, square=True, order=np.argsort(amg.luby_keys(4, 0, A.shape[0]))[::-1])

@@ -87,7 +87,7 @@ def test_two_grid_matches_dense_closed_form():
 
 
 def test_vcycle_symmetric_positive():
-    c, ops, A, h = _small_hierarchy(5, 5, 3, coarse_eq_limit=10)
+    c, ops, A, h = _small_hierarchy(5, 5, 3, coarse_eq_limit=10, mis="greedy")
     assert h.nlevels >= 3
     n = A.shape[0]
     B = _vcycle_matrix(h, n)
