@@ -170,8 +170,11 @@ typedef struct {
 } bd_amg_stats;
 
 /*
- * Setup phase (Alg. 1): build the hierarchy of A on the host and copy it to the device.
- * A: host CSR (copied).  opts: NULL for defaults.  null_weights: NULL, or n host doubles w;
+ * Setup phase (Alg. 1): build the hierarchy of A and keep it on the device.  The host drives
+ * the level loop; with the default options each SA level's eigenvalue estimate, strength graph,
+ * independent set, aggregation, prolongator smoothing and Galerkin product run on the device
+ * (aggregate_device, galerkin_device), and the host keeps a copy of every level (for
+ * bidomain_amg_export and the launch plans).  A: host CSR (copied).  opts: NULL for defaults.  null_weights: NULL, or n host doubles w;
  * with BD_NULL_CONSTANT the solution is normalised to w^T x = 0 (w = lumped mass gives the
  * integral-zero normalisation of the extracellular potential, Sec. 2.1), else to 1^T x = 0.
  * Errors: BD_E_INVALID (malformed CSR, bad options), BD_E_NOMEM, BD_E_DEVICE.

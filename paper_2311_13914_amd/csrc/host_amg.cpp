@@ -1,7 +1,9 @@
 // AMG setup phase on the host (Alg. 1 of the paper; Sec. 4 and App. A for the components).
 //
-// Smoothed aggregation: strength graph from w_ij = |a_ij| / sqrt(a_ii a_jj) >= theta, greedy
-// maximal independent set (on the squared graph for the first `square_graph_levels` levels),
+// Smoothed aggregation: strength graph from w_ij = |a_ij| / sqrt(a_ii a_jj) >= theta, maximal
+// independent set taken greedily in decreasing random priority (the set the parallel Luby-type
+// rounds reach; option independent_set) or in index order, on the squared graph for the first
+// `square_graph_levels` levels,
 // clusters formed around the MIS roots by largest weight, tentative prolongator normalised
 // per cluster (|C_j|^{-1/2} for the constant near-null vector), one Jacobi smoothing of the
 // prolongator, Galerkin coarse operator R A P with R = P^T.  Classical coarsening: strong
