@@ -195,7 +195,9 @@ def bench_solve(args):
         lib.bidomain_amg_destroy(h)
         results[prec] = dict(x=x, its=its, secs=secs, setup_s=setup_s, levels=hinfo["n"],
                              opc=hinfo["operator_complexity"], res=info["rel_residual_true"],
-                             bytes=hinfo["device_bytes"])
+                             bytes=hinfo["device_bytes"],
+                             hierarchy={k: hinfo[k] for k in ("n", "nnz", "p_nnz", "tiles", "col_bytes",
+                                                              "col_bytes_p", "col_bytes_r", "diags")})
         print(f"[bench] {'f32' if prec else 'f64'} {args.coarsening}: setup {setup_s:.1f} s, levels "
               f"{hinfo['n']}, {its / args.steps:.1f} it/solve, {secs / args.steps * 1e3:.2f} ms/solve",
               file=sys.stderr, flush=True)
@@ -214,6 +216,7 @@ def bench_solve(args):
                                f"slab, n={n}, {args.coarsening.upper()} hierarchy, rtol {args.rtol:g}",
                    "levels": r["levels"], "operator_complexity": round(r["opc"], 3),
                    "device_bytes": r["bytes"]},
+        "hierarchy": r["hierarchy"],
         "iters_per_solve": r["its"] / args.steps, "rel_residual_true": r["res"],
         "rel_error_vs_f64": err, "setup_s": round(r["setup_s"], 1),
     }
@@ -416,7 +419,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-block", default="128,128,32", help="elements of the oracle's sample block")
     ap.add_argument("--no-serve", action="store_true", help="skip the bounded serving stream")
-    ap.add_argument("--workload", default="C5", choices=["C2", "C3", "C5"])
+    ap.add_argument("--workload", default="C5", choices=["C1", "C2", "C3", "C5"])
     ap.add_argument("--mode", default="step", choices=["step", "solve", "serve", "sweep"],
                     help="step: Bidomain time steps (default); solve: repeated single elliptic solves; "
                          "serve: a stream of cases through the batching server; sweep: AMG threshold "
