@@ -44,8 +44,9 @@ def kernel_source_hash() -> str:
 
 
 def spmv_bytes(n: int, nnz: int, s: int = 8, col_bytes: int = 4, tiles: int = 0, diags: int = 0) -> int:
-    """Algorithmic bytes of y = A x in CSR: values + column indices (4 bytes, 2-byte offsets
-    from a per-tile base, or 1-byte offset-dictionary indices) + row offsets, x read once, y
+    """Algorithmic bytes of y = A x in CSR: values + column indices (4 bytes, 3-byte packed
+    indices, 2-byte offsets from a per-tile base, or 1-byte offset-dictionary indices) + row
+    offsets, x read once, y
     written once, the tile table (and the per-tile column bases with 2-byte offsets); in the
     symmetric diagonal form the `diags` stored diagonals of n values, x once and y once.  The
     p^T q partials are negligible."""

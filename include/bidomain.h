@@ -145,11 +145,12 @@ typedef struct {
   double grid_complexity;
   int64_t device_bytes;           /* device memory owned by the handle                    */
   /* The level operator's product on the device (0 on a host-only handle): bytes per column
-   * index it reads (4; 2 for 16-bit offsets from a per-tile column base, or for 16-bit column
-   * indices where rows are too long for the staging buffer and there are at most 65,536
-   * columns; 1 for an index into
-   * the matrix's dictionary of at most 256 distinct column - row offsets; 0 in the symmetric
-   * diagonal form below) and its row tiles (0 when rows are too long for the staging buffer
+   * index it reads (4; 3 for 24-bit column indices where row tiles span more than 65,536
+   * columns and there are at most 2^24 columns; 2 for 16-bit offsets from a per-tile column
+   * base, or for 16-bit column indices where rows are too long for the staging buffer and
+   * there are at most 65,536 columns; 1 for an index into the matrix's dictionary of at most
+   * 256 distinct column - row offsets; 0 in the symmetric diagonal form below) and its row
+   * tiles (0 when rows are too long for the staging buffer
    * and a lane-group kernel runs, or in the diagonal form). */
   int32_t col_bytes[BD_MAX_LEVELS];
   int64_t tiles[BD_MAX_LEVELS];

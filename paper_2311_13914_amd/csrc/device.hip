@@ -86,6 +86,7 @@ struct DPat {
   const int* ci = nullptr;        // 32-bit column indices, or null when only cs is kept
   const uint16_t* cs = nullptr;   // column - cbase[tile] (stream) or the column (lane group) in 16 bits, or null
   const int* cbase = nullptr;     // CSR-stream: per-tile column base, with cs
+  const uint32_t* c24 = nullptr;  // CSR-stream: 24-bit column indices, four in three words, or null
   const uint8_t* cd = nullptr;    // CSR-stream: index into dict of column - row, or null
   const int* dict = nullptr;      // the distinct column - row offsets, with cd
   int ndict = 0;
@@ -96,8 +97,8 @@ struct DPat {
   int nd = 0;                // symmetric diagonal form: stored diagonals (kDiagK), or 0
   int64_t ds = 0;            // with nd: stride between the diagonals
   int doff[kDiagK] = {};     // with nd: their column - row offsets (>= 0)
-  int col_bytes() const { return nd ? 0 : (cd ? 1 : (cs ? 2 : 4)); }
-  int form() const { return nd ? SDIA : (cd ? IXD8 : (cs ? IX16 : IX32)); }
+  int col_bytes() const { return nd ? 0 : (cd ? 1 : (cs ? 2 : (c24 ? 3 : 4))); }
+  int form() const { return nd ? SDIA : (cd ? IXD8 : (cs ? IX16 : (c24 ? IX24 : IX32))); }
 };
 
 template <typename T>
@@ -212,6 +213,21 @@ bool compact_columns(const Csr& H, const std::vector<int>& blk, std::vector<uint
   return true;
 }
 
+// 24-bit column indices for a CSR-stream matrix of at most 2^24 columns: entries 4q .. 4q + 3
+// (zero past nnz) in words 3q .. 3q + 2, entry j in bits 24 j .. 24 j + 23 of the 96 bits.
+void pack_columns24(const Csr& H, std::vector<uint32_t>& c24) {
+  const int64_t nnz = H.nnz(), nq = (nnz + 3) / 4;
+  c24.assign((size_t)(3 * nq), 0u);
+#pragma omp parallel for schedule(static, 65536)
+  for (int64_t q = 0; q < nq; ++q) {
+    uint32_t c[4];
+    for (int j = 0; j < 4; ++j) c[j] = 4 * q + j < nnz ? (uint32_t)H.ci[4 * q + j] : 0u;
+    c24[3 * q] = c[0] | c[1] << 24;
+    c24[3 * q + 1] = c[1] >> 8 | c[2] << 16;
+    c24[3 * q + 2] = c[2] >> 16 | c[3] << 8;
+  }
+}
+
 // Host values in the device precision: the vector itself for float64, a copy converted in
 // parallel for float32.
 template <typename T>
@@ -252,6 +268,7 @@ struct StreamPlan {
   std::vector<int> dict;
   std::vector<uint16_t> cs;     // 16-bit per-tile offsets (stream) or column indices (lane group), or empty
   std::vector<int> cbase;
+  std::vector<uint32_t> c24;    // 24-bit column indices (stream), or empty
 };
 
 namespace bd {
@@ -355,6 +372,7 @@ StreamPlan plan_stream(const Csr& H, bool diag_form) {
     if (!P.blk.empty() && !compact_columns(H, P.blk, P.cs, P.cbase)) {
       P.cs.clear();
       P.cbase.clear();
+      if (H.ncols <= kMaxCols24) pack_columns24(H, P.c24);
     }
     // rows too long for a stream tile, 64 lanes a row: 16-bit column indices where they fit
     if (P.blk.empty() && H.nrows > 0 && H.ncols <= 65536 && lanes_for((double)H.nnz() / H.nrows) == 64)
@@ -424,7 +442,8 @@ DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, const StreamPlan* pla
       M.cs = upload_padded<uint16_t>(ar, plan->cs.data(), plan->cs.size(), st);
       if (!plan->cbase.empty()) M.cbase = upload_small<int>(ar, plan->cbase, st);
     }
-    if ((!M.nd && !M.cd && !M.cs) || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
+    if (!plan->c24.empty()) M.c24 = upload_padded<uint32_t>(ar, plan->c24.data(), plan->c24.size(), st);
+    if ((!M.nd && !M.cd && !M.cs && !M.c24) || need_ci) M.ci = upload_padded<int>(ar, H.ci.data(), H.ci.size(), st);
   }
   if (M.nd && !(plan && plan->nd == M.nd)) {
     // a matrix sharing a diagonal-form pattern without diagonals of its own (a simulation's
@@ -527,6 +546,7 @@ void bind(SpArgs<T>& a, const DCsr<T>& M) {
   a.ci = M.ci;
   a.cs = M.cs;
   a.cbase = M.cbase;
+  a.c24 = M.c24;
   a.cd = M.cd;
   a.dict = M.dict;
   a.ndict = M.ndict;
@@ -552,6 +572,7 @@ void launch_spmv(const DCsr<T>& M, SpArgs<T> a, hipStream_t st) {
     switch (M.form()) {
       case IXD8: k_spmv_stream<T, OP, IXD8><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
       case IX16: k_spmv_stream<T, OP, IX16><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
+      case IX24: k_spmv_stream<T, OP, IX24><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
       default: k_spmv_stream<T, OP, IX32><<<M.nb, kBlock, 0, st>>>(a, M.blk); break;
     }
     HIPCHK(hipGetLastError());
@@ -2342,6 +2363,9 @@ struct Batch {
   launch_tasks(sp[IXD8][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                          \
     k_spmv_stream_multi<T, OPV, IXD8><<<nb, kBlock, 0, st>>>(d, n);                                      \
   });                                                                                                    \
+  launch_tasks(sp[IX24][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                          \
+    k_spmv_stream_multi<T, OPV, IX24><<<nb, kBlock, 0, st>>>(d, n);                                      \
+  });                                                                                                    \
   launch_tasks(sp[SDIA][OPV], st, stg, [&](const SpTask<T>* d, int n, int nb) {                          \
     k_spmv_sdia_multi<T, OPV><<<nb, kBlock, 0, st>>>(d, n);                                              \
   });
@@ -2361,6 +2385,9 @@ struct Batch {
     });
     launch_tasks(cgq[IXD8], st, stg, [&](const SpTask<double>* d, int n, int nb) {
       k_spmv_stream_multi<double, OP_CG_Q, IXD8><<<nb, kBlock, 0, st>>>(d, n);
+    });
+    launch_tasks(cgq[IX24], st, stg, [&](const SpTask<double>* d, int n, int nb) {
+      k_spmv_stream_multi<double, OP_CG_Q, IX24><<<nb, kBlock, 0, st>>>(d, n);
     });
     launch_tasks(cgq[SDIA], st, stg, [&](const SpTask<double>* d, int n, int nb) {
       k_spmv_sdia_multi<double, OP_CG_Q><<<nb, kBlock, 0, st>>>(d, n);

@@ -262,6 +262,7 @@ struct SpArgs {
   const int* ci;          // 32-bit column indices (null when cs is used)
   const uint16_t* cs;     // CSR-stream only: column - cbase[tile], or null
   const int* cbase;       // CSR-stream only: per-tile column base, with cs
+  const uint32_t* c24;    // CSR-stream only: 24-bit column indices (entries 4q.. in words 3q..), or null
   const uint8_t* cd;      // CSR-stream only: index into dict of column - row, or null
   const int* dict;        // the distinct column - row offsets (at most 256), with cd
   int ndict;
@@ -491,7 +492,8 @@ struct Tile {
 };
 
 // Matrix entries of one tile held in registers between phase 1's loads and its gathers:
-// four 32-bit column indices per chunk, or (16-bit offsets) two words of two offsets each.
+// four 32-bit column indices per chunk, (16-bit offsets) two words of two offsets each, or
+// (24-bit indices) the three words that pack the chunk's four indices.
 template <typename T>
 struct TileRegs {
   int c[kStreamChunks][4];
@@ -504,10 +506,19 @@ constexpr int kStageLen = 4 * ((kStreamCap + 2) / 4 + 1);
 static_assert(kStageLen <= kStreamChunks * 4 * kBlock, "every spanned chunk has a thread");
 
 // Column index forms of a CSR-stream matrix: 32-bit indices; 16-bit offsets from a per-tile
-// base; or, for matrices whose column - row offsets take at most 256 distinct values (the
-// stencil operators of a structured mesh), an 8-bit index into that offset dictionary.
+// base; for matrices whose column - row offsets take at most 256 distinct values (the
+// stencil operators of a structured mesh), an 8-bit index into that offset dictionary; or,
+// where tiles span too many columns for 16-bit offsets and the matrix has at most 2^24
+// columns, 24-bit column indices (four entries in three 32-bit words).
 // SDIA: the symmetric diagonal form (k_spmv_sdia), no column indices at all.
-enum IdxForm : int { IX32 = 0, IX16 = 1, IXD8 = 2, SDIA = 3, kForms = 4 };
+enum IdxForm : int { IX32 = 0, IX16 = 1, IXD8 = 2, IX24 = 3, SDIA = 4, kForms = 5 };
+constexpr int kMaxCols24 = 1 << 24;
+
+// Three 32-bit words at 4-byte alignment (one load of 12 bytes): the 24-bit indices of four
+// consecutive entries, entry j in bits 24 j .. 24 j + 23 of the 96-bit little-endian word.
+struct __attribute__((aligned(4))) Words3 {
+  uint32_t w0, w1, w2;
+};
 // Dictionary tiles stage values, index bytes and the dictionary in LDS: a smaller cap keeps
 // the float64 total within the other forms' staging buffer.
 constexpr int kStreamCapD = 3450;
@@ -558,6 +569,9 @@ __device__ __forceinline__ void tile_load(const SpArgs<T>& a, const Tile& t, Til
     if constexpr (IX == IX16) {
       const uint2 cc = *reinterpret_cast<const uint2*>(a.cs + k);
       R.c[c][0] = (int)cc.x; R.c[c][1] = (int)cc.y;
+    } else if constexpr (IX == IX24) {
+      const Words3 cc = *reinterpret_cast<const Words3*>(a.c24 + 3 * (k >> 2));
+      R.c[c][0] = (int)cc.w0; R.c[c][1] = (int)cc.w1; R.c[c][2] = (int)cc.w2;
     } else {
       const int4 cc = *reinterpret_cast<const int4*>(a.ci + k);
       R.c[c][0] = cc.x; R.c[c][1] = cc.y; R.c[c][2] = cc.z; R.c[c][3] = cc.w;
@@ -579,6 +593,16 @@ __device__ __forceinline__ void tile_gather(const SpArgs<T>& a, const Tile& t, c
       xv[c][1] = a.x[min(t.cb + (int)(w0 >> 16), cmax)];
       xv[c][2] = a.x[min(t.cb + (int)(w1 & 0xffffu), cmax)];
       xv[c][3] = a.x[min(t.cb + (int)(w1 >> 16), cmax)];
+    }
+  } else if constexpr (IX == IX24) {
+    // every packed index is a column of the matrix (neighbouring rows' or the zero padding)
+#pragma unroll
+    for (int c = 0; c < kStreamChunks; ++c) {
+      const unsigned w0 = (unsigned)R.c[c][0], w1 = (unsigned)R.c[c][1], w2 = (unsigned)R.c[c][2];
+      xv[c][0] = a.x[w0 & 0xffffffu];
+      xv[c][1] = a.x[(w0 >> 24) | ((w1 & 0xffffu) << 8)];
+      xv[c][2] = a.x[(w1 >> 16) | ((w2 & 0xffu) << 16)];
+      xv[c][3] = a.x[w2 >> 8];
     }
   } else {
 #pragma unroll

@@ -18,11 +18,11 @@ def test_spmv_bytes_diagonal_form():
     assert bench.spmv_bytes(n, 28607425, 4, 0, 0, 14) == 16 * n * 4
 
 
-@pytest.mark.parametrize("col_bytes,tiles,extra", [(4, 0, 0), (4, 100, 4 * 101), (2, 100, 4 * 101 + 4 * 100),
-                                                   (1, 100, 4 * 101)])
+@pytest.mark.parametrize("col_bytes,tiles,extra", [(4, 0, 0), (4, 100, 4 * 101), (3, 100, 4 * 101),
+                                                   (2, 100, 4 * 101 + 4 * 100), (1, 100, 4 * 101)])
 def test_spmv_bytes_csr_forms(col_bytes, tiles, extra):
-    # values and column indices per entry, row offsets, x and y once, the tile table (and the
-    # per-tile column bases of the 16-bit form)
+    # values and column indices per entry (4, 3, 2 or 1 bytes), row offsets, x and y once, the
+    # tile table (and the per-tile column bases of the 16-bit form)
     n, nnz = 1000, 27000
     assert bench.spmv_bytes(n, nnz, 8, col_bytes, tiles) == nnz * (8 + col_bytes) + n * (4 + 16) + extra
 

@@ -345,21 +345,23 @@ def _far_matrix(n, far, jitter):
     return sp.csr_matrix((v, (r, c)), shape=(n, n))
 
 
-@pytest.mark.parametrize("far,jitter,col_bytes", [((60000,), 1, 1), ((60000,), 600, 2), ((60000, 120000), 600, 4)])
-def test_product_index_forms(torch, far, jitter, col_bytes):
+@pytest.mark.parametrize("n,far,jitter,col_bytes", [(131072, (60000,), 1, 1), (131072, (60000,), 600, 2),
+                                                     (131072, (60000, 120000), 600, 3),
+                                                     ((1 << 24) + (1 << 16), (60000, 120000), 600, 4)])
+def test_product_index_forms(torch, n, far, jitter, col_bytes):
     """The product in each column-index form: an offset dictionary (two distinct column - row
-    offsets), 16-bit per-tile offsets (~400 distinct offsets, tiles spanning < 65,536 columns)
-    and 32-bit indices.  In the 16-bit case the 256-row tiles alternate between column bases
+    offsets), 16-bit per-tile offsets (~400 distinct offsets, tiles spanning < 65,536 columns),
+    24-bit indices (tiles spanning more, at most 2^24 columns) and 32-bit indices (more than
+    2^24 columns).  In the 16-bit case the 256-row tiles alternate between column bases
     ~60,000 apart, so near the end of the matrix the previous tile's entries that an aligned
     chunk picks up decode past the last column unless they are clamped; every result must
     still be exact."""
-    n = 131072
     A = _far_matrix(n, far, jitter)
     A.sort_indices()
     h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(max_levels=1, nullspace=0))
     try:
         info = lib.bidomain_amg_info(h)
-        print(f"[gpu] product index forms far={far} jitter={jitter} col_bytes={info['col_bytes'][0]} "
+        print(f"[gpu] product index forms n={n} far={far} jitter={jitter} col_bytes={info['col_bytes'][0]} "
               f"tiles={info['tiles'][0]}", flush=True)
         assert info["col_bytes"][0] == col_bytes and info["tiles"][0] > 0
         x = np.random.default_rng(5).standard_normal(n)
