@@ -435,10 +435,11 @@ __device__ __forceinline__ void block_tail(const SpArgs<T>& a, double (&acc)[3],
 
 // Row-group kernel: G lanes per row, TPB consecutive 256/G-row tiles per block.  Used for
 // matrices with a row longer than the CSR-stream staging buffer (kStreamCap entries); IX16:
-// 16-bit column indices (cs) for a matrix of at most 65,536 columns.  Rows averaging more than
-// 256 entries (G = 64: the filled coarse levels, thousands of entries a row) keep 16 loads a
-// lane in flight per trip; measured at 11,408 rows of 8,000 entries: 128 us a product against
-// 142 us with 4 and 136 us with 8.
+// 16-bit column indices (cs) for a matrix of at most 65,536 columns.  In float32, rows averaging
+// more than 256 entries (G = 64: the filled coarse levels, thousands of entries a row) keep 16
+// entries a lane in flight per trip; measured at 11,408 rows of 8,000 entries: 128 us a product
+// against 142 us with 4 and 136 us with 8.  Float64 products gained nothing from it (within
+// +-3 %) and keep 4.
 template <typename T, int G, int OP, int IX = 0>
 __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
   if (solve_done(a.sv)) return;
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
     const int row = (tile0 + t) * RPT + grp;
     if (row >= a.nrows) break;
     T s;
-    constexpr int U = G == 64 ? 16 : 4;
+    constexpr int U = G == 64 && sizeof(T) == 4 ? 16 : 4;
     if constexpr (IX == 1) s = row_product<T, G, uint16_t, U>(a.rp, a.cs, a.av, a.x, row, lane);
     else s = row_product<T, G, int, U>(a.rp, a.ci, a.av, a.x, row, lane);
     if (lane == 0) row_epilogue<T, OP>(a, row, s, acc, vc);
