@@ -110,6 +110,14 @@ typedef struct {
    * device with this library's kernels -- the host's result bit for bit; 0: on the host.
    * bidomain_amg_build_host never uses the device. */
   int32_t aggregate_device;
+  /* Renumbering of coarse levels on the device: the unknowns of an intermediate level (not the
+   * fine one, not the coarsest; over 256 rows, at most 10 % dense) are put in reverse
+   * Cuthill-McKee order, so that a row's columns -- and the gathers of the level's products --
+   * fall on fewer cache lines and 16-bit column offsets become possible.  1 (default): levels of
+   * at least 2^24 stored entries (the renumbering costs setup time that small hierarchies do not
+   * earn back); 2: every such level; 0: none.  The host hierarchy, bidomain_amg_export and the
+   * vectors of bidomain_amg_apply keep the aggregate numbering. */
+  int32_t reorder;
 } bd_amg_opts;
 
 void bidomain_default_opts(bd_amg_opts* opts);
@@ -168,6 +176,8 @@ typedef struct {
   /* The hierarchy's V-cycle precision (BD_F64 | BD_F32): the element type of the vectors
    * bidomain_amg_apply reads and writes. */
   int32_t vcycle_precision;
+  /* 1 where the level's unknowns are renumbered on the device (option reorder), else 0. */
+  int32_t renumbered[BD_MAX_LEVELS];
 } bd_amg_stats;
 
 /*

@@ -41,7 +41,7 @@ class bd_amg_opts(C.Structure):
                 ("vcycle_precision", C.c_int32), ("nullspace", C.c_int32), ("stagnation_ratio", C.c_double),
                 ("coarse_dense_max", C.c_int32), ("galerkin_device", C.c_int32),
                 ("diag_form", C.c_int32), ("preconditioner", C.c_int32), ("independent_set", C.c_int32),
-                ("aggregate_device", C.c_int32)]
+                ("aggregate_device", C.c_int32), ("reorder", C.c_int32)]
 
 
 class bd_csr(C.Structure):
@@ -61,7 +61,7 @@ class bd_amg_stats(C.Structure):
                 ("device_bytes", C.c_int64), ("col_bytes", C.c_int32 * BD_MAX_LEVELS),
                 ("tiles", C.c_int64 * BD_MAX_LEVELS), ("col_bytes_p", C.c_int32 * BD_MAX_LEVELS),
                 ("col_bytes_r", C.c_int32 * BD_MAX_LEVELS), ("diags", C.c_int32 * BD_MAX_LEVELS),
-                ("vcycle_precision", C.c_int32)]
+                ("vcycle_precision", C.c_int32), ("renumbered", C.c_int32 * BD_MAX_LEVELS)]
 
 
 class bd_slab(C.Structure):
@@ -282,7 +282,7 @@ def bidomain_amg_info(h) -> dict:
                 lam=list(s.lambda_[:L]), coarse_mode=s.coarse_mode, operator_complexity=s.operator_complexity,
                 grid_complexity=s.grid_complexity, device_bytes=s.device_bytes, col_bytes=list(s.col_bytes[:L]),
                 tiles=list(s.tiles[:L]), col_bytes_p=list(s.col_bytes_p[:L]), col_bytes_r=list(s.col_bytes_r[:L]),
-                diags=list(s.diags[:L]), vcycle_precision=s.vcycle_precision)
+                diags=list(s.diags[:L]), vcycle_precision=s.vcycle_precision, renumbered=list(s.renumbered[:L]))
 
 
 def bidomain_galerkin(A, P, on_device):

@@ -29,6 +29,16 @@ Csr transpose(const Csr& A);
 Csr spgemm(const Csr& A, const Csr& B);
 // (A + A^T) / 2 on A's pattern (a mirror entry that does not exist counts as zero).
 Csr symmetrized(const Csr& A);
+// Reverse Cuthill-McKee numbering of the graph of a square matrix with a symmetric pattern
+// (Cuthill & McKee, 1969; reversed after George, 1971): each connected component is walked
+// breadth-first from a node of least degree (ties: lowest index), the unvisited neighbours of a
+// node queued by increasing degree (ties: index); the visit order, reversed, is returned as
+// new -> old.
+std::vector<int32_t> rcm_order(const Csr& A);
+// Row- and column-renumbered copy of M: row i of the result is row rows[i] of M (rows: new ->
+// old, or null to keep the order), column c becomes cols[c] (cols: old -> new, or null); each row
+// sorted by its new column.
+Csr renumbered(const Csr& M, const int32_t* rows, const int32_t* cols);
 // Tentative SA prolongator: P(i, agg[i]) = B_i / |B restricted to the aggregate| (norms summed in
 // index order); Bc receives the norms (the coarse near-null vector).
 Csr tentative_prolongator(const std::vector<double>& B, const std::vector<int32_t>& agg, int32_t nc,
@@ -54,6 +64,9 @@ struct HostLevel {
   std::vector<double> B;        // near-null vector on this level
   std::vector<double> Dinv;     // 1 / diag(A)
   double lam = std::numeric_limits<double>::quiet_NaN();  // lambda_max(D^{-1} A) estimate
+  // Numbering of this level's unknowns on the device, new -> old (empty: the host's); set with
+  // the launch plans, which then hold the renumbered matrices.
+  std::vector<int32_t> perm;
 };
 
 struct HostHierarchy {

@@ -269,6 +269,8 @@ struct StreamPlan {
   std::vector<uint16_t> cs;     // 16-bit per-tile offsets (stream) or column indices (lane group), or empty
   std::vector<int> cbase;
   std::vector<uint32_t> c24;    // 24-bit column indices (stream), or empty
+  std::shared_ptr<bd::Csr> mat;  // the renumbered matrix the plan is for (uploaded instead of the
+                                // host's; released after the upload), or null
 };
 
 namespace bd {
@@ -381,13 +383,57 @@ StreamPlan plan_stream(const Csr& H, bool diag_form) {
   return P;
 }
 
-// Launch plans of every matrix of a host hierarchy (levels' A, P, R).
-void plan_hierarchy(HostHierarchy& H, bool diag_form) {
-  for (HostLevel& L : H.lv) {
-    L.plan_a = std::make_shared<StreamPlan>(plan_stream(L.A, diag_form));
-    if (L.P.nrows) L.plan_p = std::make_shared<StreamPlan>(plan_stream(L.P, false));
-    if (L.R.nrows) L.plan_r = std::make_shared<StreamPlan>(plan_stream(L.R, false));
+// Levels renumbered on the device (option reorder): the intermediate ones -- not the fine
+// level, whose numbering is the caller's, nor the coarsest, solved through its dense inverse --
+// of more than 256 rows and at most 10 % dense, and (reorder = 1) with at least 2^24 stored
+// entries.  Reverse Cuthill-McKee order clusters a row's columns: on the 384 x 384 x 96 slab the
+// 128-byte lines of x a row of level 2 touches fall from 261 to 95 and its product from 431 to
+// 302 us (level 1: 64 -> 24 lines, 177 -> 148 us), both levels' tiles then fit 16-bit offsets,
+// and level 3 (8 % dense) gains too.  The renumbering costs the setup ~10 ns an entry on the
+// host, which small hierarchies -- short solves, often only a few of them -- do not earn back.
+bool renumber_level(const HostHierarchy& H, int k, int reorder) {
+  const int M = (int)H.lv.size() - 1;
+  const Csr& A = H.lv[k].A;
+  return reorder > 0 && k >= 1 && k < M && A.nrows > 256 &&
+         (double)A.nnz() <= 0.1 * (double)A.nrows * (double)A.nrows && (reorder == 2 || A.nnz() >= (int64_t(1) << 24));
+}
+// Launch plans of every matrix of a host hierarchy (levels' A, P, R), with the renumbered
+// copies where a level is renumbered (reorder).
+void plan_hierarchy(HostHierarchy& H, bool diag_form, int reorder) {
+  const int nl = (int)H.lv.size();
+  std::vector<std::vector<int32_t>> inv(nl);  // old -> new, per renumbered level
+  for (int k = 0; k < nl; ++k) {
+    HostLevel& L = H.lv[k];
+    L.perm.clear();
+    if (renumber_level(H, k, reorder)) {
+      L.perm = rcm_order(L.A);
+      inv[k].resize(L.perm.size());
+      for (int32_t i = 0; i < (int32_t)L.perm.size(); ++i) inv[k][L.perm[i]] = i;
+    }
   }
+  auto plan = [&](const Csr& M, const std::vector<int32_t>& rows, const std::vector<int32_t>& cols, bool diag) {
+    if (rows.empty() && cols.empty()) return std::make_shared<StreamPlan>(plan_stream(M, diag));
+    auto mat = std::make_shared<Csr>(renumbered(M, rows.empty() ? nullptr : rows.data(),
+                                                cols.empty() ? nullptr : cols.data()));
+    auto P = std::make_shared<StreamPlan>(plan_stream(*mat, diag));
+    P->mat = std::move(mat);
+    return P;
+  };
+  const std::vector<int32_t> none;
+  for (int k = 0; k < nl; ++k) {
+    HostLevel& L = H.lv[k];
+    L.plan_a = plan(L.A, L.perm, inv[k], diag_form);
+    // P_k: rows on level k, columns on level k + 1; R_k the other way round
+    if (L.P.nrows) L.plan_p = plan(L.P, L.perm, k + 1 < nl ? inv[k + 1] : none, false);
+    if (L.R.nrows) L.plan_r = plan(L.R, k + 1 < nl ? H.lv[k + 1].perm : none, inv[k], false);
+  }
+}
+
+// Host copies of the renumbered matrices are needed only until they are on the device.
+void release_plan_matrices(HostHierarchy& H) {
+  for (HostLevel& L : H.lv)
+    for (auto* p : {&L.plan_a, &L.plan_p, &L.plan_r})
+      if (*p) (*p)->mat.reset();
 }
 
 template <typename U>
@@ -403,8 +449,9 @@ const U* upload_small(Arena& ar, const std::vector<U>& h, hipStream_t st) {
 // 32-bit column indices even where the product reads a compressed form (for kernels outside
 // the product that read them).
 template <typename T>
-DCsr<T> upload(Arena& ar, const Csr& H, const DPat* share, const StreamPlan* plan, bool need_ci, hipStream_t st,
+DCsr<T> upload(Arena& ar, const Csr& H0, const DPat* share, const StreamPlan* plan, bool need_ci, hipStream_t st,
                int max_blocks) {
+  const Csr& H = plan && plan->mat ? *plan->mat : H0;  // a renumbered level's matrix
   DCsr<T> M;
   if (share) {
     static_cast<DPat&>(M) = *share;
@@ -476,6 +523,7 @@ template <typename T>
 struct DLevel {
   int n = 0;
   DCsr<T> A, P, R;
+  const int* perm = nullptr;  // device numbering of the level's unknowns, new -> old (null: the host's)
   T* dinv = nullptr;
   T* f = nullptr;  // right-hand side (level 0: set per call)
   T *x = nullptr, *r = nullptr, *da = nullptr, *db = nullptr;
@@ -810,7 +858,14 @@ void build_levels(bd_amg* h, hipStream_t st) {
       D.P = upload<T>(h->ar, HL[k].P, nullptr, HL[k].plan_p.get(), false, st, kMaxBlocksSpmv);
       D.R = upload<T>(h->ar, HL[k].R, nullptr, HL[k].plan_r.get(), false, st, kMaxBlocksSpmv);
     }
-    D.dinv = upload_vec<T>(h->ar, HL[k].Dinv, st);
+    if (HL[k].perm.empty()) {
+      D.dinv = upload_vec<T>(h->ar, HL[k].Dinv, st);
+    } else {
+      std::vector<double> dp(HL[k].perm.size());
+      for (size_t i = 0; i < dp.size(); ++i) dp[i] = HL[k].Dinv[HL[k].perm[i]];
+      D.dinv = upload_vec<T>(h->ar, dp, st);
+      D.perm = upload_small<int>(h->ar, HL[k].perm, st);
+    }
     if (k > 0) D.f = h->ar.alloc<T>(D.n);
     D.x = h->ar.alloc<T>(D.n);
     D.r = h->ar.alloc<T>(D.n);
@@ -834,6 +889,16 @@ void build_levels(bd_amg* h, hipStream_t st) {
         }
       }
     }
+  }
+}
+
+// dst[i] = src[perm[i]] (into a renumbered level's device numbering, TO_DEVICE) or
+// dst[perm[i]] = src[i] (back to the host's numbering).
+template <typename T, bool TO_DEVICE>
+__global__ void k_renumber(const T* __restrict__ src, T* __restrict__ dst, const int* __restrict__ perm, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (TO_DEVICE) dst[i] = src[perm[i]];
+    else dst[perm[i]] = src[i];
   }
 }
 
@@ -1144,6 +1209,7 @@ void device_upload(bd_amg* h, const double* weights, bool need_ci, hipStream_t s
     h->w = upload_vec<double>(h->ar, wv, st);
   }
   alloc_solve_state(h, st);
+  release_plan_matrices(h->H);
   h->host_only = false;
 }
 
@@ -1631,7 +1697,7 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
       o.galerkin_device < 0 || o.galerkin_device > 3 || o.diag_form < 0 || o.diag_form > 1 ||
       o.preconditioner < BD_PC_AMG || o.preconditioner > BD_PC_NONE ||
       (o.independent_set != BD_MIS_GREEDY && o.independent_set != BD_MIS_LUBY) || o.aggregate_device < 0 ||
-      o.aggregate_device > 1 ||
+      o.aggregate_device > 1 || o.reorder < 0 || o.reorder > 2 ||
       (o.preconditioner != BD_PC_AMG && o.vcycle_precision != BD_F64) ||
       (o.smoother != BD_CHEBYSHEV && o.smoother != BD_JACOBI) ||
       (o.vcycle_precision != BD_F64 && o.vcycle_precision != BD_F32))
@@ -1669,10 +1735,12 @@ int setup_impl(const bd_csr* A, const bd_amg_opts* opts, const double* weights, 
   const int rc = build_hierarchy(std::move(H), o, h->H, err, use_device && o.galerkin_device != 0 ? &offload : nullptr,
                                  use_device && o.aggregate_device == 1 ? &agg_offload : nullptr);
   if (rc != BD_OK) throw Failure{rc, err};
-  if (plan) plan_hierarchy(h->H, o.diag_form != 0);  // launch plans, on this (possibly worker) thread
+  const auto t1 = std::chrono::steady_clock::now();
+  if (plan) plan_hierarchy(h->H, o.diag_form != 0, o.reorder);  // launch plans, on this (possibly worker) thread
   if (log)
-    std::fprintf(stderr, "[setup] hierarchy and launch plans: %.2f s\n",
-                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    std::fprintf(stderr, "[setup] hierarchy %.2f s, launch plans (with renumbered levels) %.2f s\n",
+                 std::chrono::duration<double>(t1 - t0).count(),
+                 std::chrono::duration<double>(std::chrono::steady_clock::now() - t1).count());
   h->M = (int)h->H.lv.size() - 1;
   h->host_only = true;
   if (!host_only) device_upload(h.get(), weights, false, st);
@@ -1887,6 +1955,7 @@ int bidomain_amg_info(const bd_amg* h, bd_amg_stats* s) {
         s->col_bytes[k] = M.col_bytes();
         s->tiles[k] = M.blk ? M.nb : 0;
         s->diags[k] = M.nd;
+        s->renumbered[k] = L[k].perm.empty() ? 0 : 1;
         if (k + 1 < L.size()) {
           const DPat& P = h->mixed ? static_cast<const DPat&>(h->L32[k].P) : static_cast<const DPat&>(h->L64[k].P);
           const DPat& R = h->mixed ? static_cast<const DPat&>(h->L32[k].R) : static_cast<const DPat&>(h->L64[k].R);
@@ -1982,17 +2051,32 @@ int bidomain_amg_apply(bd_amg* h, int op, int level, const void* in_dev, void* o
       const T* in = (const T*)in_dev;
       T* out = (T*)out_dev;
       DLevel<T>& Lk = L[level];
+      // the caller's vectors are in the host numbering; a renumbered level's input goes through
+      // its work vector da and its output through db
+      auto to_device = [&](const DLevel<T>& Lv, const T* src) -> const T* {
+        if (!Lv.perm) return src;
+        k_renumber<T, true><<<vec_blocks(Lv.n), kBlock, 0, st>>>(src, Lv.da, Lv.perm, Lv.n);
+        return Lv.da;
+      };
+      auto from_device = [&](const DLevel<T>& Lv, const T* src, T* dst) {
+        if (Lv.perm) k_renumber<T, false><<<vec_blocks(Lv.n), kBlock, 0, st>>>(src, dst, Lv.perm, Lv.n);
+        else HIPCHK(hipMemcpyAsync(dst, src, sizeof(T) * Lv.n, hipMemcpyDeviceToDevice, st));
+      };
       switch (op) {
         case BD_OP_A: {
-          SpArgs<T> a = args<T>(sv); a.x = in; a.y = out;
+          SpArgs<T> a = args<T>(sv); a.x = to_device(Lk, in); a.y = Lk.perm ? Lk.db : out;
           launch_spmv<T, OP_Y>(Lk.A, a, st);
+          if (Lk.perm) from_device(Lk, Lk.db, out);
           break;
         }
         case BD_OP_P:
         case BD_OP_R: {
           if (level >= h->M) throw Failure{BD_E_INVALID, "the coarsest level has no transfer operators"};
-          SpArgs<T> a = args<T>(sv); a.x = in; a.y = out;
+          const DLevel<T>& Lin = op == BD_OP_P ? L[level + 1] : Lk;
+          const DLevel<T>& Lout = op == BD_OP_P ? Lk : L[level + 1];
+          SpArgs<T> a = args<T>(sv); a.x = to_device(Lin, in); a.y = Lout.perm ? Lout.db : out;
           launch_spmv<T, OP_Y>(op == BD_OP_P ? Lk.P : Lk.R, a, st);
+          if (Lout.perm) from_device(Lout, Lout.db, out);
           break;
         }
         case BD_OP_PRESMOOTH:
@@ -2003,6 +2087,8 @@ int bidomain_amg_apply(bd_amg* h, int op, int level, const void* in_dev, void* o
           T* saved = Lx.f;
           if (k == 0) {
             Lx.f = (T*)in;
+          } else if (Lx.perm) {
+            k_renumber<T, true><<<vec_blocks(Lx.n), kBlock, 0, st>>>(in, Lx.f, Lx.perm, Lx.n);
           } else {
             HIPCHK(hipMemcpyAsync(Lx.f, in, sizeof(T) * Lx.n, hipMemcpyDeviceToDevice, st));
           }
@@ -2014,7 +2100,7 @@ int bidomain_amg_apply(bd_amg* h, int op, int level, const void* in_dev, void* o
           } else {
             vcycle<T>(h, k, sv, false, RedSpec{}, st);
           }
-          HIPCHK(hipMemcpyAsync(out, Lx.x, sizeof(T) * Lx.n, hipMemcpyDeviceToDevice, st));
+          from_device(Lx, Lx.x, out);
           if (k == 0) Lx.f = saved;
           break;
         }

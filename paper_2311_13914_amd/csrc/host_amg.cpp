@@ -814,6 +814,78 @@ Csr tentative_prolongator(const std::vector<double>& B, const std::vector<int32_
 
 double prolongator_damping(double lam) { return 4.0 / (3.0 * lam); }
 
+std::vector<int32_t> rcm_order(const Csr& A) {
+  const int32_t n = A.nrows;
+  std::vector<int32_t> deg(n);
+  for (int32_t i = 0; i < n; ++i) deg[i] = A.rp[i + 1] - A.rp[i];
+  auto lighter = [&](int32_t a, int32_t b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; };
+  // component starts: nodes by increasing degree, the first unvisited one each time
+  std::vector<int32_t> starts(n);
+  for (int32_t i = 0; i < n; ++i) starts[i] = i;
+  std::sort(starts.begin(), starts.end(), lighter);
+  std::vector<uint8_t> seen(n, 0);
+  std::vector<int32_t> order;
+  order.reserve(n);
+  std::vector<int32_t> nb;
+  size_t next_start = 0;
+  while ((int32_t)order.size() < n) {
+    while (seen[starts[next_start]]) ++next_start;
+    const int32_t s0 = starts[next_start];
+    seen[s0] = 1;
+    order.push_back(s0);
+    for (size_t head = order.size() - 1; head < order.size(); ++head) {
+      const int32_t u = order[head];
+      nb.clear();
+      for (int32_t k = A.rp[u]; k < A.rp[u + 1]; ++k) {
+        const int32_t c = A.ci[k];
+        if (!seen[c]) {
+          seen[c] = 1;
+          nb.push_back(c);
+        }
+      }
+      std::sort(nb.begin(), nb.end(), lighter);
+      order.insert(order.end(), nb.begin(), nb.end());
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+Csr renumbered(const Csr& M, const int32_t* rows, const int32_t* cols) {
+  Csr R;
+  R.nrows = M.nrows;
+  R.ncols = M.ncols;
+  R.rp.assign(M.nrows + 1, 0);
+  for (int32_t i = 0; i < M.nrows; ++i) {
+    const int32_t o = rows ? rows[i] : i;
+    R.rp[i + 1] = R.rp[i] + (M.rp[o + 1] - M.rp[o]);
+  }
+  R.ci.resize(M.ci.size());
+  R.v.resize(M.v.size());
+#pragma omp parallel
+  {
+    std::vector<uint64_t> key;  // new column in the high word, position in the row in the low
+#pragma omp for schedule(dynamic, 256)
+    for (int32_t i = 0; i < M.nrows; ++i) {
+      const int32_t o = rows ? rows[i] : i, b = M.rp[o], len = M.rp[o + 1] - b;
+      key.resize(len);
+      bool sorted = true;
+      for (int32_t j = 0; j < len; ++j) {
+        const uint32_t c = (uint32_t)(cols ? cols[M.ci[b + j]] : M.ci[b + j]);
+        key[j] = (uint64_t)c << 32 | (uint32_t)j;
+        sorted = sorted && (j == 0 || key[j] > key[j - 1]);
+      }
+      if (!sorted) std::sort(key.begin(), key.end());
+      const int32_t q = R.rp[i];
+      for (int32_t j = 0; j < len; ++j) {
+        R.ci[q + j] = (int32_t)(key[j] >> 32);
+        R.v[q + j] = M.v[b + (int32_t)(key[j] & 0xffffffffu)];
+      }
+    }
+  }
+  return R;
+}
+
 double strength_cut(double theta) { return theta * (1.0 - kTie); }
 double tie_keep() { return 1.0 - kTie; }
 
@@ -973,4 +1045,5 @@ extern "C" void bidomain_default_opts(bd_amg_opts* o) {
   o->preconditioner = BD_PC_AMG;
   o->independent_set = BD_MIS_LUBY;
   o->aggregate_device = 1;
+  o->reorder = 1;
 }

@@ -179,6 +179,93 @@ int main() {
     CHECK(rc == BD_OK, "ellipsoid %dx%dx%d: setup failed: %s", d[0], d[1], d[2], err.c_str());
     if (rc == BD_OK) check_hierarchy(H, o, "ellipsoid sa");
   }
+  // reverse Cuthill-McKee numbering: a permutation; a shuffled path (and a graph of several
+  // paths and isolated nodes) gets bandwidth 1 back; renumbered() is the permuted matrix
+  {
+    auto bandwidth = [](const Csr& A) {
+      int32_t b = 0;
+      for (int32_t i = 0; i < A.nrows; ++i)
+        for (int32_t k = A.rp[i]; k < A.rp[i + 1]; ++k) b = std::max(b, std::abs(A.ci[k] - i));
+      return b;
+    };
+    auto is_perm = [](const std::vector<int32_t>& q, int32_t n) {
+      std::vector<int> hit(n, 0);
+      if ((int32_t)q.size() != n) return false;
+      for (int32_t v : q) {
+        if (v < 0 || v >= n || hit[v]) return false;
+        hit[v] = 1;
+      }
+      return true;
+    };
+    for (int comps = 1; comps <= 3; ++comps) {
+      const int32_t n = 997;
+      std::vector<int32_t> lab(n);  // node at path position i
+      for (int32_t i = 0; i < n; ++i) lab[i] = i;
+      uint64_t z = 12345 + comps;
+      for (int32_t i = n - 1; i > 0; --i) {  // Fisher-Yates with a fixed LCG
+        z = z * 6364136223846793005ull + 1442695040888963407ull;
+        std::swap(lab[i], lab[(int32_t)((z >> 33) % (uint64_t)(i + 1))]);
+      }
+      std::vector<std::vector<int32_t>> adj(n);
+      for (int32_t i = 0; i + 1 < n; ++i) {
+        if (comps > 1 && (i % (n / comps) == n / comps - 1)) continue;  // cut into components
+        if (comps == 3 && i % 97 == 0) continue;                         // and a few isolated pieces
+        adj[lab[i]].push_back(lab[i + 1]);
+        adj[lab[i + 1]].push_back(lab[i]);
+      }
+      Csr A;
+      A.nrows = A.ncols = n;
+      A.rp.assign(n + 1, 0);
+      for (int32_t i = 0; i < n; ++i) {
+        adj[i].push_back(i);
+        std::sort(adj[i].begin(), adj[i].end());
+        A.rp[i + 1] = A.rp[i] + (int32_t)adj[i].size();
+        for (int32_t c : adj[i]) {
+          A.ci.push_back(c);
+          A.v.push_back(c == i ? 2.0 + 0.001 * i : -1.0 - 0.001 * (i + c));
+        }
+      }
+      const std::vector<int32_t> q = rcm_order(A);
+      CHECK(is_perm(q, n), "rcm (%d components): not a permutation", comps);
+      if (!is_perm(q, n)) continue;
+      std::vector<int32_t> inv(n);
+      for (int32_t i = 0; i < n; ++i) inv[q[i]] = i;
+      const Csr B = renumbered(A, q.data(), inv.data());
+      CHECK(validate(B).empty(), "rcm (%d components): renumbered CSR: %s", comps, validate(B).c_str());
+      CHECK(bandwidth(B) == 1, "rcm (%d components): bandwidth %d, not 1", comps, bandwidth(B));
+      std::vector<double> x(n);
+      for (int32_t i = 0; i < n; ++i) x[i] = std::sin(0.37 * i);
+      std::vector<double> xb(n);
+      for (int32_t i = 0; i < n; ++i) xb[i] = x[q[i]];
+      const std::vector<double> y = matvec(A, x), yb = matvec(B, xb);
+      for (int32_t i = 0; i < n; ++i)
+        CHECK(std::fabs(yb[i] - y[q[i]]) <= 1e-14 * (1.0 + std::fabs(y[q[i]])), "rcm: renumbered product row %d", i);
+    }
+    // on a coarse SA level of a slab: a permutation, and no wider than the aggregate numbering
+    const bd_slab s = slab(23, 19, 9);
+    Csr Ai;
+    assemble_slab_stiffness(s, s.sig_il, s.sig_it, Ai);
+    bd_amg_opts o;
+    bidomain_default_opts(&o);
+    o.coarse_eq_limit = 100;
+    o.galerkin_device = 0;
+    o.nullspace = BD_NULL_CONSTANT;
+    HostHierarchy H;
+    std::string err;
+    CHECK(build_hierarchy(Ai, o, H, err) == BD_OK && H.lv.size() > 2, "rcm: slab hierarchy: %s", err.c_str());
+    if (H.lv.size() > 2) {
+      const Csr& A1 = H.lv[1].A;
+      const std::vector<int32_t> q = rcm_order(A1);
+      CHECK(is_perm(q, A1.nrows), "rcm: level 1 not a permutation");
+      if (is_perm(q, A1.nrows)) {
+        std::vector<int32_t> inv(A1.nrows);
+        for (int32_t i = 0; i < A1.nrows; ++i) inv[q[i]] = i;
+        const Csr B = renumbered(A1, q.data(), inv.data());
+        CHECK(B.nnz() == A1.nnz() && validate(B).empty(), "rcm: level 1 renumbered CSR");
+        CHECK(bandwidth(B) <= bandwidth(A1), "rcm: level 1 bandwidth %d > %d", bandwidth(B), bandwidth(A1));
+      }
+    }
+  }
   // malformed input is rejected, not read out of bounds
   Csr bad;
   bad.nrows = bad.ncols = 3;
