@@ -23,10 +23,10 @@ def _mix():
 _LAST_STATS = {}   # bidomain_serve_stats of the last _serve call, read after all cases finished
 
 
-def _serve(cases, nsteps, budget=1 << 34, slots=8, prec=None, timeout=150, budget_fn=None):
+def _serve(cases, nsteps, budget=1 << 34, slots=8, prec=None, timeout=150, budget_fn=None, reorder=1):
     prec = lib.BD_F32 if prec is None else prec
-    oe = lib.bidomain_default_opts(vcycle_precision=prec)
-    op = lib.bidomain_default_opts(vcycle_precision=prec, threshold=0.0)  # the parabolic default
+    oe = lib.bidomain_default_opts(vcycle_precision=prec, reorder=reorder)
+    op = lib.bidomain_default_opts(vcycle_precision=prec, threshold=0.0, reorder=reorder)  # the parabolic default
     if budget_fn is not None:  # size the budget from the server's own admission estimate
         probe = lib.bidomain_serve_create(1 << 40, 1, oe, op, 1e-8)
         try:
@@ -80,6 +80,34 @@ def test_each_result_is_the_same_alone_and_in_the_mix(torch, prec):
         v_one, ue_one = states1[tk1[0]]
         assert np.array_equal(v_mix, v_one) and np.array_equal(ue_mix, ue_one)
         assert (done1[tk1[0]]["it_par"], done1[tk1[0]]["it_ell"]) == (done[t]["it_par"], done[t]["it_ell"])
+
+
+def test_renumbered_levels_alone_and_in_the_mix(torch):
+    """With every eligible coarse level renumbered on the device (reorder = 2: these cases' levels
+    are below the default's 2^24 entries), served results are the same alone and in the mix,
+    and the first case matches the oracle."""
+    cases = [bc.make_case(40, 40, 20, seed=21), bc.make_case(36, 30, 16, seed=22)]
+    oe = lib.bidomain_default_opts(reorder=2)
+    op = lib.bidomain_default_opts(threshold=0.0, reorder=2)
+    v0 = torch.tensor(bc.nodal_v0(cases[0]), dtype=torch.float64, device="cuda")
+    sim = lib.bidomain_sim_create(cases[0], v0, ell_opts=oe, par_opts=op)
+    try:
+        ren = lib.bidomain_amg_info(lib.bidomain_sim_hierarchy(sim, 0))["renumbered"]
+    finally:
+        lib.bidomain_sim_destroy(sim)
+    print(f"[gpu] serve with renumbered levels {ren}", flush=True)
+    assert any(ren)
+    tk, done, states, _, _, _ = _serve(cases, 2, prec=lib.BD_F64, reorder=2)
+    for c, t in zip(cases, tk):
+        assert done[t]["status"] == lib.BD_OK and done[t]["max_rel_residual"] <= 1e-8
+        tk1, done1, states1, _, _, _ = _serve([c], 2, prec=lib.BD_F64, reorder=2)
+        assert np.array_equal(states[t][0], states1[tk1[0]][0]) and np.array_equal(states[t][1], states1[tk1[0]][1])
+    ref = bidomain.create(cases[0], bc.nodal_v0(cases[0]), rtol=1e-12)
+    for _ in range(2):
+        bidomain.step(ref)
+    v, ue = states[tk[0]]
+    assert np.linalg.norm(v - ref.v) <= 1e-6 * np.linalg.norm(ref.v)
+    assert np.linalg.norm(ue - ref.ue) <= 1e-6 * np.linalg.norm(ref.ue)
 
 
 def test_served_case_equals_standalone_simulation(torch):
