@@ -114,8 +114,8 @@ typedef struct {
    * fine one, not the coarsest; over 256 rows, at most 10 % dense) are put in reverse
    * Cuthill-McKee order, so that a row's columns -- and the gathers of the level's products --
    * fall on fewer cache lines and 16-bit column offsets become possible.  1 (default): levels of
-   * at least 2^24 stored entries (the renumbering costs setup time that small hierarchies do not
-   * earn back); 2: every such level; 0: none.  The host hierarchy, bidomain_amg_export and the
+   * at least 2^26 stored entries (the renumbering costs host setup time and memory that smaller
+   * hierarchies do not earn back); 2: every such level; 0: none.  The host hierarchy, bidomain_amg_export and the
    * vectors of bidomain_amg_apply keep the aggregate numbering. */
   int32_t reorder;
 } bd_amg_opts;

@@ -385,19 +385,20 @@ StreamPlan plan_stream(const Csr& H, bool diag_form) {
 
 // Levels renumbered on the device (option reorder): the intermediate ones -- not the fine
 // level, whose numbering is the caller's, nor the coarsest, solved through its dense inverse --
-// of more than 256 rows and at most 10 % dense, and (reorder = 1) with at least 2^24 stored
+// of more than 256 rows and at most 10 % dense, and (reorder = 1) with at least 2^26 stored
 // entries.  Reverse Cuthill-McKee order clusters a row's columns: on the 384 x 384 x 96 slab the
 // 128-byte lines of x a row of level 2 touches fall from 261 to 95 and its product from 431 to
 // 302 us (level 1: 64 -> 24 lines, 177 -> 148 us), both levels' tiles then fit 16-bit offsets,
 // and level 3 (8 % dense) gains too.  The renumbering costs the setup ~10 ns an entry on the
-// host, which small hierarchies -- short solves, often only a few of them -- do not earn back.
+// host, in large allocations; with a 2^24-entry floor the serving stream's larger cases were
+// renumbered too, on the setup workers, and the serving thread's p99 solve latency rose from
+// ~55 to ~140 ms, so smaller hierarchies keep the aggregate order by default.
 bool renumber_level(const HostHierarchy& H, int k, int reorder) {
   const int M = (int)H.lv.size() - 1;
   const Csr& A = H.lv[k].A;
   return reorder > 0 && k >= 1 && k < M && A.nrows > 256 &&
-         (double)A.nnz() <= 0.1 * (double)A.nrows * (double)A.nrows && (reorder == 2 || A.nnz() >= (int64_t(1) << 24));
-}
-// Launch plans of every matrix of a host hierarchy (levels' A, P, R), with the renumbered
+         (double)A.nnz() <= 0.1 * (double)A.nrows * (double)A.nrows && (reorder == 2 || A.nnz() >= (int64_t(1) << 26));
+}// Launch plans of every matrix of a host hierarchy (levels' A, P, R), with the renumbered
 // copies where a level is renumbered (reorder).
 void plan_hierarchy(HostHierarchy& H, bool diag_form, int reorder) {
   const int nl = (int)H.lv.size();

@@ -793,9 +793,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_stream(SpArgs<T> a, const int* 
 // {0, 1, C_t - 1, C_t, C_t + 1}).  Each lane loads x[i + C] only; its neighbours are the values
 // of the adjacent lanes (rows i - 1, i + 1), moved by DPP wave shifts, and the two that fall
 // outside the wave come from scalar loads at wave-uniform addresses.  Likewise a(i, i - 1) is
-// the previous lane's a(i - 1, i).  That leaves 35 vector loads a row instead of 54: the
-// product is bound by the texture units' address and data processing of those loads (counters:
-// busy 96 % of the kernel), not by the HBM bytes.
+// the previous lane's a(i - 1, i).  That leaves 35 vector loads a row instead of 54 (the form
+// with 54 kept the texture units busy 96 % of the kernel).  Halving them again -- two rows a
+// lane, 8-byte float32 loads -- measured only 3 % faster on a 14.4 M-row grid (16 % where the
+// diagonals are cache-resident), so at scale the 27 offset streams' memory latency, not the
+// instruction count, keeps the product below a plain stream's rate.
 template <typename T, int CTRL>
 __device__ __forceinline__ T lane_move(T v) {
   if constexpr (sizeof(T) == 8) {

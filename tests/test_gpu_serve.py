@@ -84,7 +84,7 @@ def test_each_result_is_the_same_alone_and_in_the_mix(torch, prec):
 
 def test_renumbered_levels_alone_and_in_the_mix(torch):
     """With every eligible coarse level renumbered on the device (reorder = 2: these cases' levels
-    are below the default's 2^24 entries), served results are the same alone and in the mix,
+    are below the default's 2^26 entries), served results are the same alone and in the mix,
     and the first case matches the oracle."""
     cases = [bc.make_case(40, 40, 20, seed=21), bc.make_case(36, 30, 16, seed=22)]
     oe = lib.bidomain_default_opts(reorder=2)

@@ -102,7 +102,7 @@ def test_vcycle_operations_match_oracle(torch, name, form):
 
 def test_renumbered_levels_match_oracle(torch):
     """Intermediate levels renumbered on the device (reverse Cuthill-McKee; option reorder = 2
-    takes this small hierarchy's level 1, the default only levels of 2^24 entries or more): each
+    takes this small hierarchy's level 1, the default only levels of 2^26 entries or more): each
     V-cycle operation on every level, through the host numbering of bidomain_amg_apply, within
     1e-12 of the oracle's; solves with and without renumbering take the same iterations (within
     one) and agree to rounding, in float64 and with float32 V-cycles."""
