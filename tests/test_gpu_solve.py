@@ -399,10 +399,27 @@ def _far_matrix(n, far, jitter):
     return sp.csr_matrix((v, (r, c)), shape=(n, n))
 
 
+def _product_check(torch, h, A, x, prec):
+    """A x through BD_OP_A on level 0 in the handle's precision: float64 within 1e-13 of the
+    product; float32 within 2e-5 (max norm, relative) of the float64 product of the float32
+    matrix and vector."""
+    if prec == lib.BD_F64:
+        out = torch.empty(A.shape[0], dtype=torch.float64, device="cuda")
+        lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, dev(torch, x), out)
+        assert _relerr(host(out), A @ x) <= 1e-13
+    else:
+        x32 = x.astype(np.float32)
+        out = torch.empty(A.shape[0], dtype=torch.float32, device="cuda")
+        lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, dev(torch, x32, torch.float32), out)
+        A32 = A.astype(np.float32).astype(np.float64)
+        assert _relerr(host(out).astype(np.float64), A32 @ x32.astype(np.float64)) <= 2e-5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n,far,jitter,col_bytes", [(131072, (60000,), 1, 1), (131072, (60000,), 600, 2),
                                                      (131072, (60000, 120000), 600, 3),
                                                      ((1 << 24) + (1 << 16), (60000, 120000), 600, 4)])
-def test_product_index_forms(torch, n, far, jitter, col_bytes):
+def test_product_index_forms(torch, n, far, jitter, col_bytes, prec):
     """The product in each column-index form: an offset dictionary (two distinct column - row
     offsets), 16-bit per-tile offsets (~400 distinct offsets, tiles spanning < 65,536 columns),
     24-bit indices (tiles spanning more, at most 2^24 columns) and 32-bit indices (more than
@@ -412,17 +429,14 @@ def test_product_index_forms(torch, n, far, jitter, col_bytes):
     still be exact."""
     A = _far_matrix(n, far, jitter)
     A.sort_indices()
-    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(max_levels=1, nullspace=0))
+    p = lib.BD_F64 if prec == "f64" else lib.BD_F32
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(max_levels=1, nullspace=0, vcycle_precision=p))
     try:
         info = lib.bidomain_amg_info(h)
-        print(f"[gpu] product index forms n={n} far={far} jitter={jitter} col_bytes={info['col_bytes'][0]} "
+        print(f"[gpu] product index forms n={n} far={far} jitter={jitter} {prec} col_bytes={info['col_bytes'][0]} "
               f"tiles={info['tiles'][0]}", flush=True)
         assert info["col_bytes"][0] == col_bytes and info["tiles"][0] > 0
-        x = np.random.default_rng(5).standard_normal(n)
-        out = torch.empty(n, dtype=torch.float64, device="cuda")
-        lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, dev(torch, x), out)
-        ref = A @ x
-        assert _relerr(host(out), ref) <= 1e-13
+        _product_check(torch, h, A, np.random.default_rng(5).standard_normal(n), p)
     finally:
         lib.bidomain_amg_destroy(h)
 
@@ -430,7 +444,7 @@ def test_product_index_forms(torch, n, far, jitter, col_bytes):
 def _long_row_matrix(n, base, long_rows, seed):
     """Rows of 0..base-1 entries plus `long_rows` rows of 4,029..12,000 entries (longer than a
     stream tile holds, so the lane-group kernel takes the matrix), row lengths ragged around
-    the kernel's 1,024-entry trips; columns (7 i + k s_i) mod n with odd s_i, distinct within a
+    the kernel's trips (256 entries a 64-lane group in float64, 1,024 in float32); columns (7 i + k s_i) mod n with odd s_i, distinct within a
     row since n is a power of two; a diagonal added to every row."""
     import scipy.sparse as sp
     rng = np.random.default_rng(seed)
@@ -448,25 +462,24 @@ def _long_row_matrix(n, base, long_rows, seed):
                           (np.concatenate([r, d]), np.concatenate([c, d]))), shape=(n, n))
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("n,base,long_rows,col_bytes", [(16384, 400, 64, 2), (16384, 100, 3, 4)])
-def test_long_rows_lane_group(torch, n, base, long_rows, col_bytes):
+def test_long_rows_lane_group(torch, n, base, long_rows, col_bytes, prec):
     """Rows longer than a stream tile (coarse levels of the largest slabs reach ~12,000 entries)
     go to the lane-group kernel: 64 lanes a row, with 16-bit column indices, when the mean row
     is long (and there are at most 65,536 columns), fewer lanes and 32-bit indices otherwise;
-    the product must still be exact to rounding."""
+    the product must still be exact to rounding, in float64 and in float32 (16 entries a lane
+    a trip there)."""
     A = _long_row_matrix(n, base, long_rows, seed=23)
     A.sort_indices()
-    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(max_levels=1, nullspace=0))
+    p = lib.BD_F64 if prec == "f64" else lib.BD_F32
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(max_levels=1, nullspace=0, vcycle_precision=p))
     try:
         info = lib.bidomain_amg_info(h)
-        print(f"[gpu] long rows n={n} base={base} long={long_rows} nnz={A.nnz} "
+        print(f"[gpu] long rows n={n} base={base} long={long_rows} {prec} nnz={A.nnz} "
               f"tiles={info['tiles'][0]}", flush=True)
         assert info["tiles"][0] == 0 and info["col_bytes"][0] == col_bytes
-        x = np.random.default_rng(6).standard_normal(n)
-        out = torch.empty(n, dtype=torch.float64, device="cuda")
-        lib.bidomain_amg_apply(h, lib.BD_OP_A, 0, dev(torch, x), out)
-        ref = A @ x
-        assert _relerr(host(out), ref) <= 1e-13
+        _product_check(torch, h, A, np.random.default_rng(6).standard_normal(n), p)
     finally:
         lib.bidomain_amg_destroy(h)
 
