@@ -157,11 +157,13 @@ def test_c5_fine_product_sampled():
         lib.bidomain_amg_destroy(h)
 
 
+@pytest.mark.parametrize("reorder", [1, 2])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-def test_c2_elliptic_solution_matches_oracle(c2, precision):
+def test_c2_elliptic_solution_matches_oracle(c2, precision, reorder):
     """The 128 x 128 x 64 elliptic solve (f = -A_i v0, zero guess) against the oracle's solution
     at rtol 1e-12 on the oracle's own hierarchy: relative error <= 1e-6, true relative residual
-    <= 1e-8, iteration count within 1 (float64) or 2 (float32 V-cycles) of the oracle's."""
+    <= 1e-8, iteration count within 1 (float64) or 2 (float32 V-cycles) of the oracle's; with
+    the default options and with levels 1 and 2 renumbered on the device (reorder = 2)."""
     import torch
     from oracle import amg, krylov
     case, ops = c2
@@ -175,8 +177,10 @@ def test_c2_elliptic_solution_matches_oracle(c2, precision):
         _C2_REF["f32"] = krylov.amg_fcg_mixed(A, f, h_or, rtol=1e-8, m=m).iterations
     ref = _C2_REF["ref"]
     prec = lib.BD_F32 if precision == "f32" else lib.BD_F64
-    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, vcycle_precision=prec), m)
+    h = lib.bidomain_amg_setup(A, lib.bidomain_default_opts(nullspace=1, vcycle_precision=prec, reorder=reorder), m)
     try:
+        ren = lib.bidomain_amg_info(h)["renumbered"]
+        assert (sum(ren) >= 2) if reorder == 2 else not any(ren), ren
         x = torch.zeros(case.n, dtype=torch.float64, device="cuda")
         rc, info = lib.bidomain_pcg_solve(h, _dev(f), x, False, 1e-8, 500)
         assert rc == lib.BD_OK, info
@@ -184,7 +188,7 @@ def test_c2_elliptic_solution_matches_oracle(c2, precision):
         fh = f - f.mean()
         assert np.linalg.norm(fh - A @ xs) <= 1e-8 * np.linalg.norm(fh) * (1 + 1e-6)
         err = np.linalg.norm(xs - ref) / np.linalg.norm(ref)
-        print(f"[gpu] C2 {precision}: {info['iterations']} iterations (oracle {_C2_REF[precision]}), "
+        print(f"[gpu] C2 {precision} reorder={reorder}: {info['iterations']} iterations (oracle {_C2_REF[precision]}), "
               f"error {err:.2e}", flush=True)
         assert err <= 1e-6
         assert abs(info["iterations"] - _C2_REF[precision]) <= (1 if precision == "f64" else 2)
