@@ -133,15 +133,15 @@ std::vector<int> pack_tiles(const Csr& H, int max_rows, int64_t max_nnz) {
 // Row tiles of the CSR-stream kernel (nb + 1 row boundaries).  Matrices whose every row fits
 // the staging buffer use it (measured faster than the lane-group kernel on every level of the
 // slab hierarchies, short and long rows alike); longer rows fall back to the lane-group kernel
-// (empty result).  Tiles hold at most kStreamCap entries and kStreamRows rows (149 rows of a
-// 27-point operator, 256 of a prolongator), so that every tile streams a few thousand entries.
+// (empty result).  Tiles hold at most cap entries and max_rows rows (149 rows of a 27-point
+// operator, 512 of a prolongator), so that every tile streams a few thousand entries.
 // (Capping long-row tiles at 128 rows, for two lanes per row in phase 2, measured slower; so
 // did shrinking tiles until their count fills whole rounds of resident blocks.)
-std::vector<int> stream_blocks(const Csr& H, int cap) {
+std::vector<int> stream_blocks(const Csr& H, int cap, int max_rows) {
   if (H.nrows == 0) return {};
   for (int32_t i = 0; i < H.nrows; ++i)
     if (H.rp[i + 1] - H.rp[i] > cap) return {};
-  return pack_tiles(H, kStreamRows, cap);
+  return pack_tiles(H, max_rows, cap);
 }
 
 // Offset dictionary: if the matrix's column - row offsets take at most kDictMax distinct values
@@ -365,12 +365,12 @@ StreamPlan plan_stream(const Csr& H, bool diag_form) {
   StreamPlan P;
   if (diag_form && sym_diagonals(H, P)) return P;
   // index form: offset dictionary, else 16-bit per-tile offsets, else 32-bit indices
-  P.blk = stream_blocks(H, kStreamCapD);
+  P.blk = stream_blocks(H, kStreamCapD, kStreamRowsD);
   const bool dictf = !P.blk.empty() && dict_columns(H, P.cd, P.dict);
   if (!dictf) {
     P.cd.clear();
     P.dict.clear();
-    P.blk = stream_blocks(H, kStreamCap);
+    P.blk = stream_blocks(H, kStreamCap, kStreamRows);
     if (!P.blk.empty() && !compact_columns(H, P.blk, P.cs, P.cbase)) {
       P.cs.clear();
       P.cbase.clear();

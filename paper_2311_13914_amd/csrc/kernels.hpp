@@ -467,11 +467,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv(SpArgs<T> a) {
 // at most kStreamRows rows whose nonzeros fit in kStreamCap.  Phase 1 streams the tile's
 // contiguous value/column range with consecutive lanes on consecutive entries (every load
 // instruction covers one contiguous span) and stages the products a_k x_{c_k} in LDS;
-// phase 2 reduces each row from LDS with a power-of-two lane group and applies the epilogue.
+// phase 2 reduces each row from LDS with a power-of-two lane group (or, in a tile of more than
+// kBlock rows, one thread for two rows) and applies the epilogue.
 // 4028 entries: the staging buffer (kStageLen doubles) plus the reduction scratch stay within
 // 32 KiB of LDS, so five blocks fit a CU's 160 KiB (4 aligned 4-entry chunks per thread)
 constexpr int kStreamCap = 4028;
-constexpr int kStreamRows = kBlock;  // phase 2 gives each row at least one lane
+// Rows of a tile: up to two a thread in phase 2 (one thread a row, each taking a second row
+// kBlock further on) -- a prolongator's rows of ~7 entries fill 512-row tiles to 90 % of the
+// staging buffer, 256-row ones to 45 % (the 14.4 M-row fine prolongator of the
+// 384 x 384 x 96 slab: 266 -> 242 us a product).  Dictionary tiles keep a lane group a row.
+constexpr int kStreamRows = 2 * kBlock;
+constexpr int kStreamRowsD = kBlock;
 constexpr int kStreamPad = 4;   // value/column arrays carry this many padding entries
 // aligned 4-entry chunks spanned by kStreamCap entries at the worst alignment, per thread
 constexpr int kStreamChunks = ((kStreamCap + 2) / 4 + 1 + kBlock - 1) / kBlock;
@@ -669,6 +675,28 @@ __device__ __forceinline__ void tile_reduce(const SpArgs<T>& a, const Tile& t, c
     s3 += prod[k + 3 * t.g];
   }
   for (; k < hi; k += t.g) s0 += prod[k];
+  if (t.r1 - t.r0 > kBlock) {  // the same for the whole block: rows r0 + tid and r0 + tid + kBlock
+    double acc[3] = {0.0, 0.0, 0.0};
+    VcAcc<T> vc;
+    row_apply<T, OP>(a, t.r0 + (int)threadIdx.x, (s0 + s1) + (s2 + s3), in, acc, vc);
+    const int row2 = t.r0 + (int)threadIdx.x + kBlock;
+    if (row2 < t.r1) {
+      const RowIn<T> in2 = row_fetch<T, OP>(a, row2);
+      const int hi2 = a.rp[row2 + 1] - t.k0;
+      T u0 = T(0), u1 = T(0), u2 = T(0), u3 = T(0);
+      int q = a.rp[row2] - t.k0;
+      for (; q + 3 < hi2; q += 4) {
+        u0 += prod[q];
+        u1 += prod[q + 1];
+        u2 += prod[q + 2];
+        u3 += prod[q + 3];
+      }
+      for (; q < hi2; ++q) u0 += prod[q];
+      row_apply<T, OP>(a, row2, (u0 + u1) + (u2 + u3), in2, acc, vc);
+    }
+    block_tail<T, OP>(a, acc, vc, bi, nb, lds, lds32);
+    return;
+  }
   tile_finish<T, OP>(a, t, in, (s0 + s1) + (s2 + s3), bi, nb, lds, lds32);
 }
 
