@@ -525,6 +525,7 @@ struct DLevel {
   int n = 0;
   DCsr<T> A, P, R;
   const int* perm = nullptr;  // device numbering of the level's unknowns, new -> old (null: the host's)
+  int dir = 0;                // direction of the next pass over A (diagonal form), alternating
   T* dinv = nullptr;
   T* f = nullptr;  // right-hand side (level 0: set per call)
   T *x = nullptr, *r = nullptr, *da = nullptr, *db = nullptr;
@@ -695,14 +696,14 @@ void smooth_pre(bd_amg* h, DLevel<T>& L, const Solve& sv, bool d_ready, hipStrea
   if (deg < 2) return;
   SpArgs<T> a = args<T>(sv);
   a.x = L.da; a.xs = L.x; a.f = L.f; a.dinv = L.dinv; a.c1 = L.c1[0]; a.c2 = L.c2[0];
-  a.store_rd = deg > 2; a.r = L.r; a.y2 = L.db;
+  a.store_rd = deg > 2; a.r = L.r; a.y2 = L.db; a.rev = L.dir ^= 1;
   launch_spmv<T, OP_CHEB_FIRST>(L.A, a, st);
   T* dcur = L.db;
   T* doth = L.da;
   for (int j = 2; j < deg; ++j) {
     SpArgs<T> b = args<T>(sv);
     b.x = dcur; b.xs = L.x; b.r = L.r; b.dinv = L.dinv; b.c1 = L.c1[j - 1]; b.c2 = L.c2[j - 1];
-    b.add_d = 0; b.store_rd = j < deg - 1; b.y2 = doth;
+    b.add_d = 0; b.store_rd = j < deg - 1; b.y2 = doth; b.rev = L.dir ^= 1;
     launch_spmv<T, OP_CHEB_STEP>(L.A, b, st);
     std::swap(dcur, doth);
   }
@@ -736,7 +737,7 @@ bool smooth_post(bd_amg* h, DLevel<T>& L, const Solve& sv, const RedSpec& red, h
     return false;
   }
   SpArgs<T> a = args<T>(sv);
-  a.x = L.x; a.f = L.f; a.r = L.r; a.y2 = L.da; a.dinv = L.dinv; a.c0 = L.c0;
+  a.x = L.x; a.f = L.f; a.r = L.r; a.y2 = L.da; a.dinv = L.dinv; a.c0 = L.c0; a.rev = L.dir ^= 1;
   launch_spmv<T, OP_CHEB_POST0>(L.A, a, st);
   if (deg == 1) {
     k_add<T><<<vec_blocks(L.n), kBlock, 0, st>>>(sv, L.x, L.da, 0, L.n);
@@ -749,7 +750,7 @@ bool smooth_post(bd_amg* h, DLevel<T>& L, const Solve& sv, const RedSpec& red, h
   for (int j = 1; j < deg; ++j) {
     SpArgs<T> b = args<T>(sv);
     b.x = dcur; b.xs = L.x; b.r = L.r; b.dinv = L.dinv; b.c1 = L.c1[j - 1]; b.c2 = L.c2[j - 1];
-    b.add_d = j == 1; b.store_rd = j < deg - 1; b.y2 = doth;
+    b.add_d = j == 1; b.store_rd = j < deg - 1; b.y2 = doth; b.rev = L.dir ^= 1;
     if (j == deg - 1 && red.red != RED_NONE) {
       b.red = red.red; b.r64 = red.r64; b.r32 = red.r32; b.r32_old = red.r32_old;
       fused = true;
@@ -783,7 +784,7 @@ bool vcycle(bd_amg* h, int k, const Solve& sv, bool d_ready, const RedSpec& red,
   smooth_pre<T>(h, Lk, sv, d_ready, st);
   {  // residual
     SpArgs<T> a = args<T>(sv);
-    a.x = Lk.x; a.f = Lk.f; a.y = Lk.r;
+    a.x = Lk.x; a.f = Lk.f; a.y = Lk.r; a.rev = Lk.dir ^= 1;
     launch_spmv<T, OP_RESID>(Lk.A, a, st);
   }
   DLevel<T>& Ln = L[k + 1];
