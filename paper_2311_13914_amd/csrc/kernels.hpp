@@ -6,10 +6,14 @@
 // contraction (the coarsest-level matrix-vector product has at most a few thousand rows).
 //
 // Conventions:
-//  * a block has 256 threads (4 waves); products run as the CSR-stream kernel (a block owns a
-//    tile of consecutive rows whose entries it streams through LDS), or, for rows longer than
-//    the staging buffer, as the lane-group kernel (a row per group of G lanes, G a power of two
-//    chosen from the mean row length, rows_per_block = 256 / G * TPB);
+//  * a block has 256 threads (4 waves); products run as the symmetric diagonal kernel (the fine
+//    27-point operators stored as their 14 diagonals of offset >= 0), the CSR-stream kernel (a
+//    block owns a tile of consecutive rows whose entries it streams through LDS; column indices
+//    as 8-bit offset-dictionary entries, 16-bit per-tile offsets, 24-bit or 32-bit indices), or,
+//    for rows longer than the staging buffer, as the lane-group kernel (a row per group of G
+//    lanes, G a power of two chosen from the mean row length, rows_per_block = 256 / G * TPB);
+//  * consecutive passes over one matrix walk its tiles in alternating order, so each pass
+//    starts on what the previous one left in the memory-side Infinity Cache;
 //  * the block -> row-tile map is XCD-aware: the hardware deals blocks round-robin over the
 //    8 XCDs, so consecutive block ids are remapped to one contiguous row range per XCD, which
 //    keeps each XCD's L2 working on neighbouring rows (and their shared x entries);
